@@ -1,0 +1,187 @@
+"""FP64 CPU oracle of the batched randomized renderer (ctypes wrapper of oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the CPU
+baseline of the benchmark, never by the product path.  It shares no code with the
+HIP renderer and imports nothing from the product package: a batch is any object with
+the structure-of-arrays attributes documented in ``_pack`` (the seeded generators'
+``Batch`` has them).
+
+Entry points
+------------
+``render(batch)``      -> dict of FP64/int32 planar channels plus the two-nearest
+                          depths and per-pixel fragment counts (oracle.c, steps O1-O9).
+``shade_grad(batch, target, pixel_weight)`` -> (loss, grads): the analytic adjoint of
+                          the shading over the fixed visibility (step O10).
+``loss(batch, target, pixel_weight)``       -> the FP64 loss alone (for finite
+                          differences).
+``near_tie(out, rel)``  -> bool mask of pixels whose two nearest fragments are within
+                          ``rel`` relative depth (several visibility answers are right).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (contraction off, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = C.CDLL(_LIB_PATH)
+            P = C.c_void_p
+            inputs = [P] * 17 + [C.c_int32] + [P] * 8
+            lib.oracle_render.argtypes = inputs + [P] * 7 + [C.c_int32]
+            lib.oracle_render.restype = C.c_int
+            lib.oracle_shade_grad.argtypes = inputs + [C.c_int32, P, P, P, P, P, P, P, P, P, C.c_int32]
+            lib.oracle_shade_grad.restype = C.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class _Packed:
+    """Contiguous FP64 / int arrays of a batch, kept alive for the C call."""
+
+    def __init__(self, b):
+        meshes = b.meshes
+        nv = np.array([m.pos.shape[0] for m in meshes], np.int64)
+        nt = np.array([m.idx.shape[0] for m in meshes], np.int64)
+        self.mesh_vbegin = np.concatenate([[0], np.cumsum(nv)]).astype(np.int64)
+        self.mesh_tbegin = np.concatenate([[0], np.cumsum(nt)]).astype(np.int64)
+        self.mesh_pos = np.ascontiguousarray(np.concatenate([m.pos for m in meshes]), np.float64)
+        self.mesh_nrm = np.ascontiguousarray(np.concatenate([m.nrm for m in meshes]), np.float64)
+        self.mesh_idx = np.ascontiguousarray(np.concatenate([m.idx for m in meshes]), np.int32)
+        i32 = lambda x: np.ascontiguousarray(x, np.int32)
+        f64 = lambda x: np.ascontiguousarray(np.asarray(x, np.float32), np.float64)  # exact promotion
+        self.scene_object_begin = i32(b.scene_object_begin)
+        self.object_mesh = i32(b.object_mesh)
+        self.object_pose = f64(b.object_pose)
+        self.object_seg = i32(b.object_seg)
+        self.object_visible = np.ascontiguousarray(b.object_visible, np.uint8)
+        self.scene_light_begin = i32(b.scene_light_begin)
+        self.light_type = i32(b.light_type)
+        self.frame_scene = i32(b.frame_scene)
+        self.view = f64(b.view)
+        self.intr = f64(b.intr)
+        self.near = f64(b.near)
+        self.width = i32(b.width)
+        self.height = i32(b.height)
+        w = self.width.astype(np.int64) * self.height.astype(np.int64)
+        self.pixel_offset = np.concatenate([[0], np.cumsum(w)]).astype(np.int64)
+        # shading parameters may be given in FP64 (finite differences perturb them)
+        p64 = lambda x: np.ascontiguousarray(x, np.float64)
+        self.albedo = p64(b.albedo)
+        self.roughness = p64(b.roughness)
+        self.specular = p64(b.specular)
+        self.light_vec = p64(b.light_vec)
+        self.light_intensity = p64(b.light_intensity)
+        self.exposure = p64(b.exposure)
+        self.n_frames = int(self.frame_scene.shape[0])
+        self.n_scenes = int(self.scene_object_begin.shape[0] - 1)
+        self.total_pixels = int(self.pixel_offset[-1])
+        lights = np.diff(self.scene_light_begin)
+        if lights.size and lights.max() > 64:
+            raise ValueError("oracle supports at most 64 lights per scene")
+
+    def args(self):
+        return [_ptr(self.mesh_vbegin), _ptr(self.mesh_tbegin), _ptr(self.mesh_pos), _ptr(self.mesh_nrm),
+                _ptr(self.mesh_idx), _ptr(self.scene_object_begin), _ptr(self.object_mesh),
+                _ptr(self.object_pose), _ptr(self.object_seg), _ptr(self.object_visible),
+                _ptr(self.albedo), _ptr(self.roughness), _ptr(self.specular),
+                _ptr(self.scene_light_begin), _ptr(self.light_type), _ptr(self.light_vec),
+                _ptr(self.light_intensity), self.n_frames, _ptr(self.frame_scene), _ptr(self.view),
+                _ptr(self.intr), _ptr(self.near), _ptr(self.exposure), _ptr(self.width),
+                _ptr(self.height), _ptr(self.pixel_offset)]
+
+
+def _pack(batch):
+    return _Packed(batch)
+
+
+def render(batch, threads: int = 0) -> dict:
+    """FP64 render of every frame (planar layout, frames packed in order).
+
+    Keys: rgb f64[3*P], depth f64[P], normal f64[3*P], seg i32[P], tri_id i32[P],
+    depth2 f64[P] (second-nearest fragment depth, +inf if none), frag_count i32[P],
+    pixel_offset i64[F+1]; P = total pixels."""
+    pk = _pack(batch)
+    P = pk.total_pixels
+    out = dict(rgb=np.zeros(3 * P), depth=np.zeros(P), normal=np.zeros(3 * P),
+               seg=np.zeros(P, np.int32), tri_id=np.zeros(P, np.int32), depth2=np.zeros(P),
+               frag_count=np.zeros(P, np.int32))
+    rc = _load().oracle_render(*pk.args(), _ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["normal"]),
+                               _ptr(out["seg"]), _ptr(out["tri_id"]), _ptr(out["depth2"]),
+                               _ptr(out["frag_count"]), int(threads))
+    if rc != 0:
+        raise MemoryError("oracle_render failed")
+    out["pixel_offset"] = pk.pixel_offset
+    return out
+
+
+def shade_grad(batch, target_rgb, pixel_weight=None, threads: int = 0):
+    """FP64 loss sum w_px (rgb - target)^2 and its gradient over the fixed visibility.
+
+    Returns (loss, dict(albedo [O,3], roughness [O], specular [O], light_pos [L,3],
+    light_intensity [L], exposure [F]))."""
+    pk = _pack(batch)
+    P = pk.total_pixels
+    target = np.ascontiguousarray(target_rgb, np.float64).reshape(-1)
+    if target.shape[0] != 3 * P:
+        raise ValueError("target must hold 3 * total_pixels values")
+    wmask = None if pixel_weight is None else np.ascontiguousarray(pixel_weight, np.uint8).reshape(-1)
+    if wmask is not None and wmask.shape[0] != P:
+        raise ValueError("pixel_weight must hold total_pixels values")
+    O = int(pk.object_mesh.shape[0])
+    L = int(pk.light_type.shape[0])
+    g = dict(albedo=np.zeros((O, 3)), roughness=np.zeros(O), specular=np.zeros(O),
+             light_pos=np.zeros((L, 3)), light_intensity=np.zeros(L), exposure=np.zeros(pk.n_frames))
+    loss = np.zeros(1)
+    rc = _load().oracle_shade_grad(*pk.args(), pk.n_scenes, _ptr(target), _ptr(wmask), _ptr(loss),
+                                   _ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]),
+                                   _ptr(g["light_pos"]), _ptr(g["light_intensity"]), _ptr(g["exposure"]),
+                                   int(threads))
+    if rc != 0:
+        raise MemoryError("oracle_shade_grad failed")
+    return float(loss[0]), g
+
+
+def loss(batch, target_rgb, pixel_weight=None, threads: int = 0) -> float:
+    return shade_grad(batch, target_rgb, pixel_weight, threads)[0]
+
+
+def near_tie(out: dict, rel: float = 1e-5) -> np.ndarray:
+    """Pixels with a second fragment whose depth is within rel * d1 of the nearest."""
+    d1, d2 = out["depth"], out["depth2"]
+    return (out["tri_id"] >= 0) & np.isfinite(d2) & (d2 - d1 <= rel * d1)
+
+
+def frame_view(arr: np.ndarray, pixel_offset, f: int, width: int, height: int, planes: int = 1) -> np.ndarray:
+    """View of frame f's planes: [planes, H, W] (planes = 3 for rgb/normal)."""
+    po = int(pixel_offset[f])
+    n = width * height
+    return arr[planes * po: planes * po + planes * n].reshape(planes, height, width)

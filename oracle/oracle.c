@@ -1,0 +1,585 @@
+/*
+ * FP64 CPU oracle for the batched randomized renderer.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark load this library.  It shares no code, header, table or
+ * helper with the HIP path, and the HIP path never calls it.
+ *
+ * What it computes: for every frame of a batch of scenes, the four channels ORRB
+ * renders (Sec. 4.4: RGB, segmentation, depth, screen-space normal) of a scene whose
+ * material, camera, light and exposure parameters were drawn by the randomizers of
+ * Sec. 4.3.1.  The paper prints no projection, fill, depth, normal or shading rule;
+ * the readings taken here (FP64 vertex stage with a fixed fma order, 8-bit sub-pixel
+ * snapping, top-left fill rule, nearest-depth-then-lowest-triangle-ID visibility,
+ * eye depth, view-space normal, Lambert plus Blinn-Phong with point and directional
+ * lights, linear exposure) are the definitions this file writes out in the plainest
+ * form: loop over frames, objects, triangles, then the pixel centres in each
+ * triangle's bounding box, keep the two nearest fragments of every pixel, then shade
+ * the nearest.  Everything is FP64 except the integer snapping.
+ *
+ * The shading adjoint (oracle_shade_grad) is the analytic derivative of the per-pixel
+ * shading function over the fixed visibility, accumulated in FP64 in a fixed order.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC oracle.c -lm
+ * (contraction must stay off so every rounding is the one written here).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define GUARD_SUBPX 16777216LL /* 2^24 sub-pixel units = 65536 px */
+#define LIGHT_EPS 1e-4         /* clamp of the squared light distance, m^2 */
+#define HALF_EPS 1e-12         /* |l+v|^2 below this: no specular term */
+
+/* ------------------------------------------------------------------------------ */
+/* inputs, bundled once so the per-frame routines stay readable                     */
+/* ------------------------------------------------------------------------------ */
+typedef struct {
+    const int64_t *mesh_vbegin, *mesh_tbegin;
+    const double *mesh_pos, *mesh_nrm;
+    const int32_t *mesh_idx;
+    const int32_t *scene_object_begin, *object_mesh, *object_seg;
+    const double *object_pose;
+    const uint8_t *object_visible;
+    const double *albedo, *roughness, *specular;
+    const int32_t *scene_light_begin, *light_type;
+    const double *light_vec, *light_intensity;
+    const int32_t *frame_scene, *width, *height;
+    const double *view, *intr, *near_, *exposure;
+    const int64_t *pixel_offset;
+} Inputs;
+
+/* per-vertex results of the vertex stage for one (frame, object) */
+typedef struct {
+    int valid;       /* w >= near and inside the guard band */
+    int64_t X, Y;    /* snapped position, 1/256 px */
+    double w;        /* eye depth */
+    double n[3];     /* unit view-space normal */
+} Vert;
+
+/* per-pixel visibility record */
+typedef struct {
+    double d1, d2; /* nearest and second-nearest fragment depth (d2 = +inf if none) */
+    int32_t tri;   /* scene-local triangle ID of the nearest, -1 = none */
+    int32_t obj;   /* object of the nearest */
+    int32_t local; /* triangle index inside that object's mesh */
+    int32_t count; /* number of covering fragments */
+} Pix;
+
+/* ------------------------------------------------------------------------------ */
+/* vertex stage                                                                     */
+/* ------------------------------------------------------------------------------ */
+
+/* M = V o W for 3x4 affine matrices (rows), in the fixed fma order. */
+static void compose(const double *V, const double *W, double *M) {
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) {
+            double t = V[i * 4 + 2] * W[2 * 4 + j];
+            t = fma(V[i * 4 + 1], W[1 * 4 + j], t);
+            M[i * 4 + j] = fma(V[i * 4 + 0], W[0 * 4 + j], t);
+        }
+        M[i * 4 + 3] = fma(V[i * 4 + 0], W[0 * 4 + 3],
+                           fma(V[i * 4 + 1], W[1 * 4 + 3], fma(V[i * 4 + 2], W[2 * 4 + 3], V[i * 4 + 3])));
+    }
+}
+
+static void normalize3(double *v) {
+    double l = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= l;
+    v[1] /= l;
+    v[2] /= l;
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Transform, project and snap every vertex of one object for one frame. */
+static void vertex_stage(const Inputs *in, int f, int o, Vert *out) {
+    int m = in->object_mesh[o];
+    double M[12];
+    compose(in->view + 12 * (int64_t)f, in->object_pose + 12 * (int64_t)o, M);
+    const double *K = in->intr + 4 * (int64_t)f;
+    double fx = K[0], fy = K[1], cx = K[2], cy = K[3], nearp = in->near_[f];
+    int64_t v0 = in->mesh_vbegin[m], nv = in->mesh_vbegin[m + 1] - v0;
+    for (int64_t v = 0; v < nv; v++) {
+        const double *p = in->mesh_pos + 3 * (v0 + v);
+        const double *nn = in->mesh_nrm + 3 * (v0 + v);
+        double e[3];
+        for (int i = 0; i < 3; i++)
+            e[i] = fma(M[i * 4 + 0], p[0], fma(M[i * 4 + 1], p[1], fma(M[i * 4 + 2], p[2], M[i * 4 + 3])));
+        Vert *q = out + v;
+        q->w = -e[2];
+        q->valid = 0;
+        q->X = q->Y = 0;
+        if (q->w >= nearp) {
+            double qx = e[0] / q->w, qy = e[1] / q->w;
+            double sx = fma(fx, qx, cx), sy = fma(-fy, qy, cy);
+            double Xd = rint(256.0 * sx), Yd = rint(256.0 * sy);
+            if (fabs(Xd) <= (double)GUARD_SUBPX && fabs(Yd) <= (double)GUARD_SUBPX) {
+                q->valid = 1;
+                q->X = (int64_t)Xd;
+                q->Y = (int64_t)Yd;
+            }
+        }
+        for (int i = 0; i < 3; i++) q->n[i] = M[i * 4 + 0] * nn[0] + M[i * 4 + 1] * nn[1] + M[i * 4 + 2] * nn[2];
+        normalize3(q->n);
+    }
+}
+
+/* ------------------------------------------------------------------------------ */
+/* triangle set-up, fill rule, fragment depth                                       */
+/* ------------------------------------------------------------------------------ */
+
+static int64_t floor_div(int64_t a, int64_t b) { /* b > 0 */
+    return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+static int64_t edge_fn(int64_t Xa, int64_t Ya, int64_t Xb, int64_t Yb, int64_t PX, int64_t PY) {
+    return (Xb - Xa) * (PY - Ya) - (Yb - Ya) * (PX - Xa);
+}
+
+static int top_left(int64_t Xa, int64_t Ya, int64_t Xb, int64_t Yb) {
+    int64_t dX = Xb - Xa, dY = Yb - Ya;
+    return dY < 0 || (dY == 0 && dX > 0);
+}
+
+static int covered(int64_t E, int tl) { return E > 0 || (E == 0 && tl); }
+
+/* The three vertices of a front-facing triangle after the v1 <-> v2 swap that makes
+ * its area positive; returns 0 if the triangle is culled (invalid vertex, back-facing
+ * or degenerate). */
+static int setup(const Vert *vt, const int32_t *idx, const Vert **a, const Vert **b, const Vert **c, int64_t *area) {
+    const Vert *p0 = vt + idx[0], *p1 = vt + idx[1], *p2 = vt + idx[2];
+    if (!p0->valid || !p1->valid || !p2->valid) return 0;
+    int64_t A = (p1->X - p0->X) * (p2->Y - p0->Y) - (p1->Y - p0->Y) * (p2->X - p0->X);
+    if (A >= 0) return 0;
+    *a = p0;
+    *b = p2;
+    *c = p1;
+    *area = -A;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* visibility of one frame                                                          */
+/* ------------------------------------------------------------------------------ */
+
+/* Rasterize every visible object of frame f into pix[W*H].  vt_of[o - ob] points at
+ * that object's vertex-stage results. */
+static void visibility(const Inputs *in, int f, Vert **vt_of, Pix *pix) {
+    int s = in->frame_scene[f], W = in->width[f], H = in->height[f];
+    int ob = in->scene_object_begin[s], oe = in->scene_object_begin[s + 1];
+    for (int64_t p = 0; p < (int64_t)W * H; p++) {
+        pix[p].d1 = pix[p].d2 = INFINITY;
+        pix[p].tri = pix[p].obj = pix[p].local = -1;
+        pix[p].count = 0;
+    }
+    int32_t tri_base = 0;
+    for (int o = ob; o < oe; o++) {
+        int m = in->object_mesh[o];
+        int64_t t0 = in->mesh_tbegin[m], nt = in->mesh_tbegin[m + 1] - t0;
+        if (in->object_visible[o]) {
+            const Vert *vt = vt_of[o - ob];
+            for (int64_t t = 0; t < nt; t++) {
+                const Vert *a, *b, *c;
+                int64_t A;
+                if (!setup(vt, in->mesh_idx + 3 * (t0 + t), &a, &b, &c, &A)) continue;
+                int64_t xmin = a->X < b->X ? a->X : b->X, xmax = a->X > b->X ? a->X : b->X;
+                int64_t ymin = a->Y < b->Y ? a->Y : b->Y, ymax = a->Y > b->Y ? a->Y : b->Y;
+                if (c->X < xmin) xmin = c->X;
+                if (c->X > xmax) xmax = c->X;
+                if (c->Y < ymin) ymin = c->Y;
+                if (c->Y > ymax) ymax = c->Y;
+                /* pixel centres 256 i + 128 inside [xmin, xmax] */
+                int64_t i0 = -floor_div(-(xmin - 128), 256), i1 = floor_div(xmax - 128, 256);
+                int64_t j0 = -floor_div(-(ymin - 128), 256), j1 = floor_div(ymax - 128, 256);
+                if (i0 < 0) i0 = 0;
+                if (j0 < 0) j0 = 0;
+                if (i1 > W - 1) i1 = W - 1;
+                if (j1 > H - 1) j1 = H - 1;
+                int tl0 = top_left(b->X, b->Y, c->X, c->Y); /* edge opposite a */
+                int tl1 = top_left(c->X, c->Y, a->X, a->Y); /* edge opposite b */
+                int tl2 = top_left(a->X, a->Y, b->X, b->Y); /* edge opposite c */
+                for (int64_t j = j0; j <= j1; j++) {
+                    for (int64_t i = i0; i <= i1; i++) {
+                        int64_t PX = 256 * i + 128, PY = 256 * j + 128;
+                        int64_t E0 = edge_fn(b->X, b->Y, c->X, c->Y, PX, PY);
+                        int64_t E1 = edge_fn(c->X, c->Y, a->X, a->Y, PX, PY);
+                        int64_t E2 = edge_fn(a->X, a->Y, b->X, b->Y, PX, PY);
+                        if (!(covered(E0, tl0) && covered(E1, tl1) && covered(E2, tl2))) continue;
+                        double b0 = (double)E0 / (double)A, b1 = (double)E1 / (double)A, b2 = (double)E2 / (double)A;
+                        double z = 1.0 / (b0 / a->w + b1 / b->w + b2 / c->w);
+                        int32_t id = tri_base + (int32_t)t;
+                        Pix *q = pix + j * W + i;
+                        q->count++;
+                        if (z < q->d1 || (z == q->d1 && id < q->tri)) {
+                            q->d2 = q->d1;
+                            q->d1 = z;
+                            q->tri = id;
+                            q->obj = o;
+                            q->local = (int32_t)t;
+                        } else if (z < q->d2) {
+                            q->d2 = z;
+                        }
+                    }
+                }
+            }
+        }
+        tri_base += (int32_t)nt;
+    }
+}
+
+/* ------------------------------------------------------------------------------ */
+/* shading                                                                          */
+/* ------------------------------------------------------------------------------ */
+
+/* Everything the shading function and its adjoint need at one covered pixel. */
+typedef struct {
+    double z;       /* eye depth */
+    double n[3];    /* unit view-space normal */
+    double p[3];    /* view-space position */
+    double v[3];    /* unit direction to the eye */
+} Frag;
+
+static void fragment(const Inputs *in, int f, Vert **vt_of, const Pix *q, int i, int j, Frag *fr) {
+    int s = in->frame_scene[f];
+    int ob = in->scene_object_begin[s];
+    int m = in->object_mesh[q->obj];
+    const Vert *vt = vt_of[q->obj - ob];
+    const Vert *a, *b, *c;
+    int64_t A;
+    setup(vt, in->mesh_idx + 3 * (in->mesh_tbegin[m] + q->local), &a, &b, &c, &A);
+    int64_t PX = 256 * (int64_t)i + 128, PY = 256 * (int64_t)j + 128;
+    double b0 = (double)edge_fn(b->X, b->Y, c->X, c->Y, PX, PY) / (double)A;
+    double b1 = (double)edge_fn(c->X, c->Y, a->X, a->Y, PX, PY) / (double)A;
+    double b2 = (double)edge_fn(a->X, a->Y, b->X, b->Y, PX, PY) / (double)A;
+    double z = 1.0 / (b0 / a->w + b1 / b->w + b2 / c->w);
+    double be0 = z * b0 / a->w, be1 = z * b1 / b->w, be2 = z * b2 / c->w;
+    for (int k = 0; k < 3; k++) fr->n[k] = be0 * a->n[k] + be1 * b->n[k] + be2 * c->n[k];
+    normalize3(fr->n);
+    const double *K = in->intr + 4 * (int64_t)f;
+    fr->z = z;
+    fr->p[0] = z * ((i + 0.5 - K[2]) / K[0]);
+    fr->p[1] = z * (-(j + 0.5 - K[3]) / K[1]);
+    fr->p[2] = -z;
+    double pl = sqrt(dot3(fr->p, fr->p));
+    for (int k = 0; k < 3; k++) fr->v[k] = -fr->p[k] / pl;
+}
+
+/* A light expressed in the frame's view space. */
+typedef struct {
+    int type;      /* 0 point, 1 directional */
+    double q[3];   /* point: view-space position; directional: unit direction to the light */
+    double I;
+} VLight;
+
+static void view_lights(const Inputs *in, int f, VLight *L, int *nL) {
+    int s = in->frame_scene[f];
+    const double *V = in->view + 12 * (int64_t)f;
+    int lb = in->scene_light_begin[s], le = in->scene_light_begin[s + 1];
+    *nL = le - lb;
+    for (int l = lb; l < le; l++) {
+        VLight *x = L + (l - lb);
+        const double *u = in->light_vec + 3 * (int64_t)l;
+        x->type = in->light_type[l];
+        x->I = in->light_intensity[l];
+        if (x->type == 0) {
+            for (int r = 0; r < 3; r++) x->q[r] = V[r * 4 + 0] * u[0] + V[r * 4 + 1] * u[1] + V[r * 4 + 2] * u[2] + V[r * 4 + 3];
+        } else {
+            for (int r = 0; r < 3; r++) x->q[r] = -(V[r * 4 + 0] * u[0] + V[r * 4 + 1] * u[1] + V[r * 4 + 2] * u[2]);
+            normalize3(x->q);
+        }
+    }
+}
+
+/* Per-light terms of the shading function at one fragment. */
+typedef struct {
+    double l[3], dist, D, A, ndl, h[3], hl, ndh, s;
+    int has_h; /* |l+v|^2 >= HALF_EPS */
+} LTerm;
+
+static void light_term(const VLight *L, const Frag *fr, double m, LTerm *t) {
+    if (L->type == 0) {
+        double d[3] = {L->q[0] - fr->p[0], L->q[1] - fr->p[1], L->q[2] - fr->p[2]};
+        t->D = dot3(d, d);
+        t->dist = sqrt(t->D);
+        for (int k = 0; k < 3; k++) t->l[k] = d[k] / t->dist;
+        t->A = L->I / (t->D > LIGHT_EPS ? t->D : LIGHT_EPS);
+    } else {
+        for (int k = 0; k < 3; k++) t->l[k] = L->q[k];
+        t->D = t->dist = 1.0;
+        t->A = L->I;
+    }
+    double c = dot3(fr->n, t->l);
+    t->ndl = c > 0 ? c : 0;
+    double hh[3] = {t->l[0] + fr->v[0], t->l[1] + fr->v[1], t->l[2] + fr->v[2]};
+    double H2 = dot3(hh, hh);
+    t->has_h = H2 >= HALF_EPS;
+    t->s = 0;
+    t->ndh = 0;
+    t->hl = 0;
+    if (t->has_h) {
+        t->hl = sqrt(H2);
+        for (int k = 0; k < 3; k++) t->h[k] = hh[k] / t->hl;
+        double e = dot3(fr->n, t->h);
+        t->ndh = e > 0 ? e : 0;
+        t->s = t->ndh > 0 ? pow(t->ndh, m) : 0;
+    }
+}
+
+/* ------------------------------------------------------------------------------ */
+/* per-frame driver shared by render and gradient                                   */
+/* ------------------------------------------------------------------------------ */
+
+typedef struct {
+    Vert **vt_of;
+    Vert *vbuf;
+    Pix *pix;
+} FrameWork;
+
+static int frame_begin(const Inputs *in, int f, FrameWork *fw) {
+    int s = in->frame_scene[f];
+    int ob = in->scene_object_begin[s], oe = in->scene_object_begin[s + 1];
+    int64_t nv = 0;
+    for (int o = ob; o < oe; o++) {
+        int m = in->object_mesh[o];
+        nv += in->mesh_vbegin[m + 1] - in->mesh_vbegin[m];
+    }
+    fw->vt_of = (Vert **)malloc(sizeof(Vert *) * (size_t)(oe - ob + 1));
+    fw->vbuf = (Vert *)malloc(sizeof(Vert) * (size_t)(nv + 1));
+    fw->pix = (Pix *)malloc(sizeof(Pix) * (size_t)((int64_t)in->width[f] * in->height[f] + 1));
+    if (!fw->vt_of || !fw->vbuf || !fw->pix) return -1;
+    int64_t off = 0;
+    for (int o = ob; o < oe; o++) {
+        int m = in->object_mesh[o];
+        fw->vt_of[o - ob] = fw->vbuf + off;
+        vertex_stage(in, f, o, fw->vbuf + off);
+        off += in->mesh_vbegin[m + 1] - in->mesh_vbegin[m];
+    }
+    visibility(in, f, fw->vt_of, fw->pix);
+    return 0;
+}
+
+static void frame_end(FrameWork *fw) {
+    free(fw->vt_of);
+    free(fw->vbuf);
+    free(fw->pix);
+}
+
+static void render_frame(const Inputs *in, int f, double *rgb, double *depth, double *normal, int32_t *seg,
+                         int32_t *tri_id, double *depth2, int32_t *frag_count, int *err) {
+    FrameWork fw;
+    if (frame_begin(in, f, &fw)) {
+        *err = 1;
+        frame_end(&fw);
+        return;
+    }
+    int W = in->width[f], H = in->height[f];
+    int64_t HW = (int64_t)W * H, po = in->pixel_offset[f];
+    VLight L[64];
+    int nL;
+    view_lights(in, f, L, &nL);
+    for (int j = 0; j < H; j++) {
+        for (int i = 0; i < W; i++) {
+            int64_t p = (int64_t)j * W + i;
+            const Pix *q = fw.pix + p;
+            if (depth2) depth2[po + p] = q->tri >= 0 ? q->d2 : INFINITY;
+            if (frag_count) frag_count[po + p] = q->count;
+            if (q->tri < 0) {
+                for (int c = 0; c < 3; c++) {
+                    rgb[3 * po + c * HW + p] = 0;
+                    normal[3 * po + c * HW + p] = 0;
+                }
+                depth[po + p] = 0;
+                seg[po + p] = -1;
+                if (tri_id) tri_id[po + p] = -1;
+                continue;
+            }
+            Frag fr;
+            fragment(in, f, fw.vt_of, q, i, j, &fr);
+            int o = q->obj;
+            double r = in->roughness[o], ks = in->specular[o], mexp = 2.0 / (r * r) - 2.0;
+            const double *alb = in->albedo + 3 * (int64_t)o;
+            double U[3] = {0, 0, 0};
+            for (int l = 0; l < nL; l++) {
+                LTerm t;
+                light_term(L + l, &fr, mexp, &t);
+                for (int c = 0; c < 3; c++) U[c] += t.A * t.ndl * (alb[c] + ks * t.s);
+            }
+            double e = in->exposure[f];
+            for (int c = 0; c < 3; c++) {
+                rgb[3 * po + c * HW + p] = e * U[c];
+                normal[3 * po + c * HW + p] = fr.n[c];
+            }
+            depth[po + p] = q->d1;
+            seg[po + p] = in->object_seg[o];
+            if (tri_id) tri_id[po + p] = q->tri;
+        }
+    }
+    frame_end(&fw);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* exported entry points                                                            */
+/* ------------------------------------------------------------------------------ */
+
+#define INPUT_ARGS                                                                                            \
+    const int64_t *mesh_vbegin, const int64_t *mesh_tbegin, const double *mesh_pos, const double *mesh_nrm,   \
+        const int32_t *mesh_idx, const int32_t *scene_object_begin, const int32_t *object_mesh,               \
+        const double *object_pose, const int32_t *object_seg, const uint8_t *object_visible,                  \
+        const double *albedo, const double *roughness, const double *specular,                                \
+        const int32_t *scene_light_begin, const int32_t *light_type, const double *light_vec,                 \
+        const double *light_intensity, int32_t n_frames, const int32_t *frame_scene, const double *view,      \
+        const double *intr, const double *near_, const double *exposure, const int32_t *width,                \
+        const int32_t *height, const int64_t *pixel_offset
+
+#define FILL_INPUTS(in)                                                                                         \
+    Inputs in = {mesh_vbegin, mesh_tbegin, mesh_pos, mesh_nrm, mesh_idx, scene_object_begin, object_mesh,      \
+                 object_seg, object_pose, object_visible, albedo, roughness, specular, scene_light_begin,      \
+                 light_type, light_vec, light_intensity, frame_scene, width, height, view, intr, near_,        \
+                 exposure, pixel_offset}
+
+static void set_threads(int n_threads) {
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+}
+
+/* Render all frames.  Outputs use the planar layout: rgb and normal planes of frame f
+ * at 3*pixel_offset[f] + c*H*W, depth/seg/tri_id/depth2/frag_count at
+ * pixel_offset[f].  tri_id, depth2 and frag_count may be NULL.  Returns 0 on success. */
+int oracle_render(INPUT_ARGS, double *rgb, double *depth, double *normal, int32_t *seg, int32_t *tri_id,
+                  double *depth2, int32_t *frag_count, int32_t n_threads) {
+    FILL_INPUTS(in);
+    int err = 0;
+    set_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int f = 0; f < n_frames; f++) {
+        int e = 0;
+        render_frame(&in, f, rgb, depth, normal, seg, tri_id, depth2, frag_count, &e);
+        err |= e;
+    }
+    return err;
+}
+
+/* Loss L = sum over frames, pixels and channels of w_px (rgb - target)^2, and its
+ * analytic gradient over the fixed visibility with respect to per-object albedo (3),
+ * roughness and specular, per-light position (world, 3) and intensity, and per-frame
+ * exposure.  w_px is pixel_weight[px] (0/1, NULL = all 1).  Gradients are overwritten.
+ * Scenes are processed in parallel; within a scene, frames and pixels are summed in
+ * order, so the result is deterministic. */
+int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const uint8_t *pixel_weight,
+                      double *loss_out, double *g_albedo, double *g_rough, double *g_spec, double *g_lightpos,
+                      double *g_intensity, double *g_exposure, int32_t n_threads) {
+    FILL_INPUTS(in);
+    int err = 0;
+    double *scene_loss = (double *)calloc((size_t)n_scenes + 1, sizeof(double));
+    if (!scene_loss) return 1;
+    int64_t n_obj = scene_object_begin[n_scenes], n_light = scene_light_begin[n_scenes];
+    memset(g_albedo, 0, sizeof(double) * 3 * (size_t)n_obj);
+    memset(g_rough, 0, sizeof(double) * (size_t)n_obj);
+    memset(g_spec, 0, sizeof(double) * (size_t)n_obj);
+    memset(g_lightpos, 0, sizeof(double) * 3 * (size_t)n_light);
+    memset(g_intensity, 0, sizeof(double) * (size_t)n_light);
+    memset(g_exposure, 0, sizeof(double) * (size_t)n_frames);
+    set_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int s = 0; s < n_scenes; s++) {
+        int lb = scene_light_begin[s];
+        for (int f = 0; f < n_frames; f++) {
+            if (frame_scene[f] != s) continue;
+            FrameWork fw;
+            if (frame_begin(&in, f, &fw)) {
+                err |= 1;
+                frame_end(&fw);
+                continue;
+            }
+            int W = width[f], H = height[f];
+            int64_t HW = (int64_t)W * H, po = pixel_offset[f];
+            VLight L[64];
+            int nL;
+            view_lights(&in, f, L, &nL);
+            const double *V = view + 12 * (int64_t)f;
+            double e = exposure[f];
+            for (int j = 0; j < H; j++) {
+                for (int i = 0; i < W; i++) {
+                    int64_t p = (int64_t)j * W + i;
+                    const Pix *q = fw.pix + p;
+                    if (pixel_weight && !pixel_weight[po + p]) continue;
+                    if (q->tri < 0) { /* background renders 0: constant loss, no gradient */
+                        for (int c = 0; c < 3; c++) scene_loss[s] += target[3 * po + c * HW + p] * target[3 * po + c * HW + p];
+                        continue;
+                    }
+                    Frag fr;
+                    fragment(&in, f, fw.vt_of, q, i, j, &fr);
+                    int o = q->obj;
+                    double r = roughness[o], ks = specular[o], mexp = 2.0 / (r * r) - 2.0;
+                    const double *alb = albedo + 3 * (int64_t)o;
+                    LTerm t[64];
+                    double U[3] = {0, 0, 0};
+                    for (int l = 0; l < nL; l++) {
+                        light_term(L + l, &fr, mexp, t + l);
+                        for (int c = 0; c < 3; c++) U[c] += t[l].A * t[l].ndl * (alb[c] + ks * t[l].s);
+                    }
+                    double g[3], G = 0;
+                    for (int c = 0; c < 3; c++) {
+                        double rgbc = e * U[c];
+                        double d = rgbc - target[3 * po + c * HW + p];
+                        scene_loss[s] += d * d;
+                        g[c] = 2.0 * d;
+                        G += g[c];
+                    }
+                    /* exposure */
+                    g_exposure[f] += g[0] * U[0] + g[1] * U[1] + g[2] * U[2];
+                    double sum_And = 0, sum_Ands = 0, sum_Ands_ln = 0;
+                    for (int l = 0; l < nL; l++) {
+                        const LTerm *x = t + l;
+                        sum_And += x->A * x->ndl;
+                        sum_Ands += x->A * x->ndl * x->s;
+                        if (x->ndh > 0) sum_Ands_ln += x->A * x->ndl * x->s * log(x->ndh);
+                        /* intensity: A = I / max(D, eps) (point) or I (directional) */
+                        double Gh = 0;
+                        for (int c = 0; c < 3; c++) Gh += g[c] * (alb[c] + ks * x->s);
+                        double dA_dI = L[l].type == 0 ? 1.0 / (x->D > LIGHT_EPS ? x->D : LIGHT_EPS) : 1.0;
+                        g_intensity[lb + l] += e * Gh * x->ndl * dA_dI;
+                        if (L[l].type != 0) continue;
+                        /* point-light position, view space, then rotated to world */
+                        double gq[3] = {0, 0, 0};
+                        if (x->D > LIGHT_EPS) {
+                            double k = -2.0 * L[l].I / (x->D * x->D);
+                            double d[3] = {x->l[0] * x->dist, x->l[1] * x->dist, x->l[2] * x->dist};
+                            for (int c = 0; c < 3; c++) gq[c] += e * Gh * x->ndl * k * d[c];
+                        }
+                        if (x->ndl > 0) {
+                            for (int c = 0; c < 3; c++) gq[c] += e * Gh * x->A * (fr.n[c] - x->ndl * x->l[c]) / x->dist;
+                            if (x->has_h && x->ndh > 0 && mexp != 0) {
+                                /* d(n.h)/dd = (I - l l^T)(n - (n.h) h) / (|l+v| |d|) */
+                                double w[3], lw;
+                                for (int c = 0; c < 3; c++) w[c] = fr.n[c] - x->ndh * x->h[c];
+                                lw = dot3(x->l, w);
+                                double coef = e * G * x->A * x->ndl * ks * mexp * pow(x->ndh, mexp - 1.0) / (x->hl * x->dist);
+                                for (int c = 0; c < 3; c++) gq[c] += coef * (w[c] - lw * x->l[c]);
+                            }
+                        }
+                        for (int c = 0; c < 3; c++)
+                            g_lightpos[3 * (int64_t)(lb + l) + c] += V[0 * 4 + c] * gq[0] + V[1 * 4 + c] * gq[1] + V[2 * 4 + c] * gq[2];
+                    }
+                    for (int c = 0; c < 3; c++) g_albedo[3 * (int64_t)o + c] += e * g[c] * sum_And;
+                    g_spec[o] += e * G * sum_Ands;
+                    g_rough[o] += e * G * ks * sum_Ands_ln * (-4.0 / (r * r * r));
+                }
+            }
+            frame_end(&fw);
+        }
+    }
+    double loss = 0;
+    for (int s = 0; s < n_scenes; s++) loss += scene_loss[s];
+    *loss_out = loss;
+    free(scene_loss);
+    return err;
+}
