@@ -1,0 +1,204 @@
+/*
+ * orrb.h -- C ABI of the MI355X (gfx950) batched randomized renderer.
+ *
+ * The library renders many visually randomized robotics scenes at once into the four
+ * channel kinds ORRB produces (arXiv:1906.11633, Sec. 4.4: RGB, segmentation, depth and
+ * screen-space normal), for training-time batch rendering (Sec. 3).  Scenes follow the
+ * paper's Single Scene Multiple States model (Sec. 3): meshes and the batch structure
+ * ("layout") are uploaded once and stay resident; each call carries only the per-batch
+ * state that randomizers change (Sec. 4.3.1: materials, lights, cameras, exposure).
+ * Calls are asynchronous on a caller-supplied HIP stream, write into caller-allocated
+ * destinations and never synchronize with the host (Sec. 4.4).
+ *
+ * Conventions (the paper prints no rendering rule; these are the library's definitions):
+ *   - poses are 3x4 row-major [s*R | t], object -> world, rigid plus uniform scale;
+ *   - views are 3x4 row-major world -> camera; the camera looks down -z, +y up;
+ *   - intrinsics (fx, fy, cx, cy) in pixels, origin at the image's top-left corner,
+ *     x right, y down, pixel (i, j) centred at (i + 1/2, j + 1/2);
+ *   - meshes are counter-clockwise seen from outside; back faces are culled;
+ *   - the vertex stage runs in FP64 with a fixed fma order, projected positions snap
+ *     to 1/256 px (round half to even), triangles with a vertex nearer than the near
+ *     plane or beyond +-65536 px are discarded, coverage uses exact integer edge
+ *     functions with the top-left fill rule;
+ *   - visibility: nearest fp32 eye depth wins, exact ties go to the lower scene-local
+ *     triangle ID (objects in scene order, then triangles in mesh order);
+ *   - depth = eye depth along -z in metres; normal = unit view-space normal
+ *     interpolated perspective-correctly from vertex normals; seg = the object's id;
+ *     rgb = exposure * sum over lights of A * max(0, n.l) * (albedo + k_s * s),
+ *     s = max(0, n.h)^(2/r^2 - 2) (Blinn-Phong), A = I / max(|d|^2, 1e-4) for point
+ *     lights and A = I for directional lights; background: rgb = depth = normal = 0,
+ *     seg = -1, tri_id = -1.
+ *
+ * Output layout: frames are packed densely in layout order.  With P_f = W_f * H_f and
+ * off_f = sum of P over earlier frames, frame f's depth / seg / tri_id / vis plane is
+ * at [off_f, off_f + P_f) and its rgb / normal channel c plane at
+ * [3 off_f + c P_f, 3 off_f + (c+1) P_f), row-major.  A uniform batch is [F,3,H,W].
+ *
+ * Errors: every entry point returns an orrb_status; nothing aborts and no C++
+ * exception crosses the ABI.  Host-visible argument errors are reported before any
+ * work is enqueued.  orrb_last_error() returns a thread-local message describing the
+ * calling thread's most recent failure.
+ *
+ * Ownership: the caller owns every device buffer it passes (inputs, outputs,
+ * workspace) and keeps it alive and unmodified until the stream work completes.  The
+ * library owns the resident mesh pool (per context) and layout tables (per layout).
+ *
+ * Thread safety: a context may be used from several threads if calls on the same
+ * layout are serialized by the caller; calls on different layouts and streams may
+ * run concurrently.
+ */
+#ifndef ORRB_H
+#define ORRB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ORRB_OK = 0,
+    ORRB_ERR_INVALID_ARGUMENT = 1,  /* a size, index, pointer or range is wrong */
+    ORRB_ERR_OUT_OF_MEMORY = 2,     /* a library-owned device allocation failed */
+    ORRB_ERR_WORKSPACE_TOO_SMALL = 3,
+    ORRB_ERR_DEVICE = 4,            /* a HIP runtime call failed */
+    ORRB_ERR_UNSUPPORTED = 5        /* the request exceeds a documented limit */
+} orrb_status;
+
+typedef struct orrb_context orrb_context;
+typedef struct orrb_layout orrb_layout;
+
+/* Documented limits. */
+#define ORRB_MAX_LIGHTS_PER_SCENE 8
+#define ORRB_MAX_DIM 8192           /* frame width and height */
+#define ORRB_MAX_SCENE_TRIANGLES 0x7fffff00  /* scene-local triangle IDs fit 31 bits */
+
+/* --------------------------------------------------------------------------------- */
+/* context and resident meshes (Sec. 3, Single Scene Multiple States)                 */
+/* --------------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle. */
+orrb_status orrb_create(int hip_device, orrb_context **out);
+
+/* Destroy a context and free its mesh pool.  Layouts of the context must be destroyed
+ * first.  NULL is ignored. */
+void orrb_destroy(orrb_context *ctx);
+
+/* Message of the calling thread's last failure ("" if none); valid until that
+ * thread's next orrb_* call. */
+const char *orrb_last_error(void);
+
+/* Add a mesh to the context's resident pool (host arrays, copied synchronously).
+ *   pos   float [V,3] object-space positions (finite)
+ *   nrm   float [V,3] object-space vertex normals (non-zero; normalized on use)
+ *   idx   int32 [T,3] vertex indices in [0, V), counter-clockwise seen from outside
+ * *mesh_id receives the new mesh's id (0, 1, 2, ... in call order).  Errors:
+ * ORRB_ERR_INVALID_ARGUMENT for V or T < 1, V > 2^30, T > 2^26, an index out of range
+ * or a non-finite value; ORRB_ERR_OUT_OF_MEMORY / ORRB_ERR_DEVICE from the upload. */
+orrb_status orrb_add_mesh(orrb_context *ctx, const float *pos, const float *nrm, int32_t n_verts,
+                          const int32_t *idx, int32_t n_tris, int32_t *mesh_id);
+
+/* --------------------------------------------------------------------------------- */
+/* layout: the structure of a batch (host arrays, validated and copied)               */
+/* --------------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t n_scenes;
+    const int32_t *scene_object_begin; /* [n_scenes+1], non-decreasing, starts at 0 */
+    const int32_t *object_mesh;        /* [n_objects] mesh ids of this context */
+    const int32_t *scene_light_begin;  /* [n_scenes+1], <= ORRB_MAX_LIGHTS_PER_SCENE each */
+    const int32_t *light_type;         /* [n_lights] 0 = point, 1 = directional */
+    int32_t n_frames;
+    const int32_t *frame_scene;        /* [n_frames] scene of each frame (camera image) */
+    const int32_t *width;              /* [n_frames] in [1, ORRB_MAX_DIM] */
+    const int32_t *height;             /* [n_frames] in [1, ORRB_MAX_DIM] */
+} orrb_layout_desc;
+
+/* Tile size and LDS bin capacity of the raster kernel.  They change speed only: the
+ * output bits are the same for every valid tuning. */
+typedef struct {
+    int32_t tile_w, tile_h;  /* each in {8, 16, 32, 64}; tile_w * tile_h <= 4096 */
+    int32_t bin_cap;         /* triangles staged in LDS per flush, in {256, 512, 1024} */
+    int32_t persistent;      /* 1: persistent grid pulling tiles from a device queue */
+} orrb_tuning;
+
+typedef struct {
+    int64_t n_scenes, n_objects, n_lights, n_frames;
+    int64_t total_pixels;       /* P: depth/seg hold P values, rgb/normal 3P */
+    int64_t vertex_instances;   /* sum over frames of the frame's scene vertex count */
+    int64_t triangle_instances; /* sum over frames of the frame's scene triangle count */
+    int64_t tile_items;         /* raster work items with the current tuning */
+    size_t workspace_bytes;      /* workspace orrb_render_batch needs (current tuning) */
+    size_t workspace_bytes_any;  /* workspace enough for every valid tuning */
+    size_t grad_workspace_bytes; /* workspace orrb_shade_backward needs */
+    orrb_tuning tuning;
+} orrb_layout_info;
+
+/* Validate `desc` against the context's meshes and build a layout (device tables are
+ * uploaded synchronously).  Errors: ORRB_ERR_INVALID_ARGUMENT for any malformed array
+ * (negative counts, non-monotone offsets, unknown mesh id, bad light type, frame scene
+ * out of range, size out of range), ORRB_ERR_UNSUPPORTED beyond a documented limit. */
+orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *desc, orrb_layout **out);
+
+/* Destroy a layout (waits for nothing: the caller must have synchronized the streams
+ * that used it).  NULL is ignored. */
+void orrb_layout_destroy(orrb_layout *layout);
+
+orrb_status orrb_layout_info_get(const orrb_layout *layout, orrb_layout_info *info);
+
+/* Set the layout's tuning (validated; ORRB_ERR_INVALID_ARGUMENT if out of range). */
+orrb_status orrb_layout_set_tuning(orrb_layout *layout, const orrb_tuning *tuning);
+
+/* --------------------------------------------------------------------------------- */
+/* per-batch state (device pointers), the randomizers' outputs (Sec. 4.3.1)           */
+/* --------------------------------------------------------------------------------- */
+
+typedef struct {                  /* scenes: geometry state */
+    const float *object_pose;     /* [O,3,4] object -> world, rigid + uniform scale */
+    const int32_t *object_seg;    /* [O] segmentation id written for the object */
+    const uint8_t *object_visible;/* [O] 0 hides the object (Hide component, Sec. 4.3.2) */
+} orrb_scenes;
+
+typedef struct {                  /* cameras, one per frame */
+    const float *view;            /* [F,3,4] world -> camera */
+    const float *intr;            /* [F,4] fx, fy, cx, cy (pixels) */
+    const float *near_plane;      /* [F] > 0, metres */
+} orrb_cameras;
+
+typedef struct {                  /* sampled randomization parameters */
+    const float *albedo;          /* [O,3] material tint */
+    const float *roughness;       /* [O] in (0, 1] (1 - glossiness) */
+    const float *specular;        /* [O] highlight weight (metallic level) */
+    const float *light_vec;       /* [L,3] world position (point) or direction (directional) */
+    const float *light_intensity; /* [L] */
+    const float *exposure;        /* [F] linear post-processing gain */
+} orrb_params;
+
+typedef struct {                  /* destinations; rgb, depth, normal, seg may each be NULL */
+    float *rgb;                   /* [3P] */
+    float *depth;                 /* [P] */
+    float *normal;                /* [3P] */
+    int32_t *seg;                 /* [P] */
+    int32_t *tri_id;              /* [P] or NULL: scene-local winning triangle, -1 background */
+    uint64_t *vis;                /* [P] or NULL: visibility key (fp32 depth bits << 32 | tri_id),
+                                     ~0 for background; input of orrb_shade_backward */
+} orrb_outputs;
+
+/* Render every frame of the layout.  `scenes`, `cameras`, `params`, `out` are host
+ * structs holding device pointers; `workspace` is a device buffer of at least
+ * orrb_layout_info.workspace_bytes, `stream` a hipStream_t (NULL: the null stream).
+ * Asynchronous: returns once the kernels are enqueued.  Preconditions the host cannot
+ * check without a copy (values inside device arrays: rigid poses, near > 0, roughness
+ * in (0, 1]) are the caller's; violating them gives unspecified pixels, never an
+ * out-of-bounds access.  Errors: ORRB_ERR_INVALID_ARGUMENT (NULL handle or required
+ * pointer), ORRB_ERR_WORKSPACE_TOO_SMALL, ORRB_ERR_DEVICE (launch failure). */
+orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
+                              const orrb_cameras *cameras, const orrb_params *params, const orrb_outputs *out,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ORRB_H */

@@ -1,0 +1,104 @@
+"""ctypes declarations of the C ABI in include/orrb.h (argument marshalling only).
+
+Loads the in-tree ``liborrb.so``.  There is no fallback: if the library is missing or
+fails to load, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborrb.so")
+
+P = C.c_void_p
+
+ORRB_OK = 0
+STATUS_NAMES = {0: "ORRB_OK", 1: "ORRB_ERR_INVALID_ARGUMENT", 2: "ORRB_ERR_OUT_OF_MEMORY",
+                3: "ORRB_ERR_WORKSPACE_TOO_SMALL", 4: "ORRB_ERR_DEVICE", 5: "ORRB_ERR_UNSUPPORTED"}
+MAX_LIGHTS_PER_SCENE = 8
+
+
+class OrrbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class LayoutDesc(C.Structure):
+    _fields_ = [("n_scenes", C.c_int32), ("scene_object_begin", P), ("object_mesh", P),
+                ("scene_light_begin", P), ("light_type", P), ("n_frames", C.c_int32),
+                ("frame_scene", P), ("width", P), ("height", P)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("bin_cap", C.c_int32), ("persistent", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.tile_w, self.tile_h, self.bin_cap, self.persistent)
+
+
+class LayoutInfo(C.Structure):
+    _fields_ = [("n_scenes", C.c_int64), ("n_objects", C.c_int64), ("n_lights", C.c_int64),
+                ("n_frames", C.c_int64), ("total_pixels", C.c_int64), ("vertex_instances", C.c_int64),
+                ("triangle_instances", C.c_int64), ("tile_items", C.c_int64), ("workspace_bytes", C.c_size_t),
+                ("workspace_bytes_any", C.c_size_t), ("grad_workspace_bytes", C.c_size_t), ("tuning", Tuning)]
+
+
+class Scenes(C.Structure):
+    _fields_ = [("object_pose", P), ("object_seg", P), ("object_visible", P)]
+
+
+class Cameras(C.Structure):
+    _fields_ = [("view", P), ("intr", P), ("near_plane", P)]
+
+
+class Params(C.Structure):
+    _fields_ = [("albedo", P), ("roughness", P), ("specular", P), ("light_vec", P),
+                ("light_intensity", P), ("exposure", P)]
+
+
+class Outputs(C.Structure):
+    _fields_ = [("rgb", P), ("depth", P), ("normal", P), ("seg", P), ("tri_id", P), ("vis", P)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "orrb_create": (C.c_int, [C.c_int, C.POINTER(P)]),
+    "orrb_destroy": (None, [P]),
+    "orrb_last_error": (C.c_char_p, []),
+    "orrb_add_mesh": (C.c_int, [P, P, P, C.c_int32, P, C.c_int32, C.POINTER(C.c_int32)]),
+    "orrb_layout_create": (C.c_int, [P, C.POINTER(LayoutDesc), C.POINTER(P)]),
+    "orrb_layout_destroy": (None, [P]),
+    "orrb_layout_info_get": (C.c_int, [P, C.POINTER(LayoutInfo)]),
+    "orrb_layout_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
+    "orrb_render_batch": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params),
+                                    C.POINTER(Outputs), P, C.c_size_t, P]),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load():
+    """Load liborrb.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                                   "(python -c 'import __graft_entry__ as g; g.build()')")
+            lib = C.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def check(status: int):
+    if status != ORRB_OK:
+        msg = load().orrb_last_error()
+        raise OrrbError(status, msg.decode() if msg else "")

@@ -1,0 +1,75 @@
+// Device-side data structures shared by the HIP kernels and the host runtime of the
+// batched renderer.  Nothing here is used by the CPU oracle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace orrb {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // threads per raster / vertex workgroup
+constexpr int kMaxLights = 8;
+constexpr int kGuard = 1 << 24;      // snapped coordinates beyond this are discarded
+constexpr int kSmallExtent = 1 << 14;// triangles up to 64 px wide use exact int32 edges
+constexpr unsigned long long kEmptyKey = ~0ull;
+
+// Per frame, built on the host from the layout.
+struct FrameInfo {
+    int64_t pixel_offset;  // first pixel of the frame's planes
+    int64_t vbase;         // first transformed-vertex instance of the frame
+    int32_t scene, width, height, tiles_x;
+    int32_t obj_begin, n_obj;   // the scene's objects (global indices)
+    int32_t oi_base;            // first (frame, object) instance
+    int32_t light_begin, n_lights;
+    int32_t pad0;
+};
+
+// Per object, built on the host from the layout and the mesh pool.
+struct ObjInfo {
+    int32_t mesh_vbegin, n_verts;  // vertex range in the mesh pool
+    int32_t mesh_tbegin, n_tris;   // triangle range in the mesh pool
+    int32_t scene_vbase;           // vertex offset inside its scene's block
+    int32_t scene_tbase;           // scene-local triangle ID of its first triangle
+};
+
+struct RenderArgs {
+    // layout tables
+    const FrameInfo *frames;
+    const ObjInfo *objs;
+    const int2 *vitems;     // (frame, object-in-scene) work items of k_vertex
+    const int2 *titems;     // (frame, tile) work items of k_raster_shade
+    const int32_t *light_type;
+    int32_t n_vitems, n_titems;
+    int32_t tile_w, tile_h, bin_cap;
+    int32_t persistent;
+    // resident meshes
+    const float4 *mesh_pos;  // xyz, 0
+    const float4 *mesh_nrm;  // xyz, 0
+    const int4 *mesh_tri;    // local vertex indices, 0
+    // scenes
+    const float *pose;
+    const int32_t *seg;
+    const uint8_t *visible;
+    // cameras
+    const float *view;
+    const float *intr;
+    const float *near_plane;
+    // params
+    const float *albedo, *roughness, *specular, *light_vec, *light_intensity, *exposure;
+    // outputs
+    float *out_rgb, *out_depth, *out_normal;
+    int32_t *out_seg, *out_tri;
+    unsigned long long *out_vis;
+    // workspace
+    int4 *vtx_pos;     // X, Y (1/256 px), bits of fp32 1/w, valid flag
+    float4 *vtx_nrm;   // unit view-space normal, fp32 w
+    int4 *obj_bbox;    // per (frame, object): covered pixel-centre range i0, j0, i1, j1
+    unsigned int *queue;  // persistent work counter
+};
+
+// launchers (defined in orrb_kernels.hip)
+hipError_t launch_render(const RenderArgs &a, hipStream_t stream, int n_cu);
+size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap);
+
+}  // namespace orrb

@@ -1,0 +1,458 @@
+// Host runtime of the batched renderer: the C ABI declared in include/orrb.h.
+//
+// A context owns the resident mesh pool (Single Scene Multiple States: geometry is
+// uploaded once and shared by every scene instance).  A layout owns the device tables
+// describing one batch structure (which meshes each scene uses, frame sizes, tile and
+// vertex work items); building it validates every host-visible argument, so a render
+// call only checks pointers and the workspace size before enqueueing two kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/orrb.h"
+#include "orrb_device.h"
+
+using namespace orrb;
+
+// --------------------------------------------------------------------------------------
+// errors
+// --------------------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+static orrb_status fail(orrb_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t _e = (expr);                                                                    \
+        if (_e != hipSuccess)                                                                      \
+            return fail(_e == hipErrorOutOfMemory ? ORRB_ERR_OUT_OF_MEMORY : ORRB_ERR_DEVICE,       \
+                        "%s failed: %s", #expr, hipGetErrorString(_e));                            \
+    } while (0)
+
+// --------------------------------------------------------------------------------------
+// device buffers
+// --------------------------------------------------------------------------------------
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t upload(const void *src, size_t n) {
+        if (n > bytes) {
+            if (p) (void)hipFree(p);
+            p = nullptr;
+            bytes = 0;
+            hipError_t e = hipMalloc(&p, n);
+            if (e != hipSuccess) return e;
+            bytes = n;
+        }
+        if (n == 0) return hipSuccess;
+        return hipMemcpy(p, src, n, hipMemcpyHostToDevice);
+    }
+};
+
+struct ScopedDevice {
+    int prev = -1;
+    explicit ScopedDevice(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~ScopedDevice() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+struct orrb_context {
+    int device = 0;
+    int n_cu = 256;
+    // host copies of the pool
+    std::vector<float4> pos, nrm;
+    std::vector<int4> tri;
+    std::vector<int32_t> mesh_vbegin{0}, mesh_tbegin{0};
+    DevBuf d_pos, d_nrm, d_tri;
+    int n_layouts = 0;
+};
+
+struct orrb_layout {
+    orrb_context *ctx = nullptr;
+    int64_t n_scenes = 0, n_objects = 0, n_lights = 0, n_frames = 0;
+    int64_t total_pixels = 0, vertex_instances = 0, triangle_instances = 0, object_instances = 0;
+    std::vector<FrameInfo> frames;
+    std::vector<ObjInfo> objs;
+    std::vector<int2> vitems;
+    std::vector<int32_t> light_type;
+    std::vector<int32_t> widths, heights;
+    DevBuf d_frames, d_objs, d_vitems, d_titems, d_light_type;
+    std::vector<int2> titems;
+    orrb_tuning tuning{32, 32, 512, 0};
+};
+
+// --------------------------------------------------------------------------------------
+// workspace
+// --------------------------------------------------------------------------------------
+
+static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct WsLayout {
+    size_t vtx_pos, vtx_nrm, obj_bbox, queue, total;
+};
+
+static WsLayout ws_layout(const orrb_layout *L) {
+    WsLayout w;
+    size_t off = 0;
+    w.vtx_pos = off;
+    off = al256(off + sizeof(int4) * (size_t)L->vertex_instances);
+    w.vtx_nrm = off;
+    off = al256(off + sizeof(float4) * (size_t)L->vertex_instances);
+    w.obj_bbox = off;
+    off = al256(off + sizeof(int4) * (size_t)L->object_instances);
+    w.queue = off;
+    off = al256(off + 64);
+    w.total = off;
+    return w;
+}
+
+static bool valid_tuning(const orrb_tuning &t) {
+    auto ok_dim = [](int d) { return d == 8 || d == 16 || d == 32 || d == 64; };
+    if (!ok_dim(t.tile_w) || !ok_dim(t.tile_h)) return false;
+    if (t.tile_w * t.tile_h > 4096) return false;
+    if (t.bin_cap != 256 && t.bin_cap != 512 && t.bin_cap != 1024) return false;
+    if (t.persistent != 0 && t.persistent != 1) return false;
+    return raster_lds_bytes(t.tile_w, t.tile_h, t.bin_cap) <= 160 * 1024;
+}
+
+static void build_titems(orrb_layout *L) {
+    L->titems.clear();
+    const int TW = L->tuning.tile_w, TH = L->tuning.tile_h;
+    for (int64_t f = 0; f < L->n_frames; ++f) {
+        FrameInfo &fi = L->frames[f];
+        fi.tiles_x = (fi.width + TW - 1) / TW;
+        const int ty = (fi.height + TH - 1) / TH;
+        for (int t = 0; t < fi.tiles_x * ty; ++t) L->titems.push_back(make_int2((int)f, t));
+    }
+}
+
+static orrb_status upload_layout(orrb_layout *L) {
+    ScopedDevice sd(L->ctx->device);
+    HIP_TRY(L->d_frames.upload(L->frames.data(), sizeof(FrameInfo) * L->frames.size()));
+    HIP_TRY(L->d_objs.upload(L->objs.data(), sizeof(ObjInfo) * L->objs.size()));
+    HIP_TRY(L->d_vitems.upload(L->vitems.data(), sizeof(int2) * L->vitems.size()));
+    HIP_TRY(L->d_titems.upload(L->titems.data(), sizeof(int2) * L->titems.size()));
+    HIP_TRY(L->d_light_type.upload(L->light_type.data(), sizeof(int32_t) * L->light_type.size()));
+    return ORRB_OK;
+}
+
+// --------------------------------------------------------------------------------------
+// C ABI
+// --------------------------------------------------------------------------------------
+
+extern "C" {
+
+const char *orrb_last_error(void) { return g_last_error.c_str(); }
+
+orrb_status orrb_create(int hip_device, orrb_context **out) {
+    g_last_error.clear();
+    if (!out) return fail(ORRB_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (hip_device < 0 || hip_device >= n)
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "device %d out of range [0, %d)", hip_device, n);
+    ScopedDevice sd(hip_device);
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+    auto *c = new (std::nothrow) orrb_context();
+    if (!c) return fail(ORRB_ERR_OUT_OF_MEMORY, "host allocation failed");
+    c->device = hip_device;
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    *out = c;
+    return ORRB_OK;
+}
+
+void orrb_destroy(orrb_context *ctx) {
+    if (!ctx) return;
+    ScopedDevice sd(ctx->device);
+    delete ctx;
+}
+
+orrb_status orrb_add_mesh(orrb_context *ctx, const float *pos, const float *nrm, int32_t n_verts, const int32_t *idx,
+                          int32_t n_tris, int32_t *mesh_id) {
+    g_last_error.clear();
+    if (!ctx || !pos || !nrm || !idx || !mesh_id) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (n_verts < 1 || n_verts > (1 << 30)) return fail(ORRB_ERR_INVALID_ARGUMENT, "n_verts %d out of range", n_verts);
+    if (n_tris < 1 || n_tris > (1 << 26)) return fail(ORRB_ERR_INVALID_ARGUMENT, "n_tris %d out of range", n_tris);
+    if ((int64_t)ctx->pos.size() + n_verts > 0x7fffffff || (int64_t)ctx->tri.size() + n_tris > 0x7fffffff)
+        return fail(ORRB_ERR_UNSUPPORTED, "mesh pool would exceed 2^31 entries");
+    for (int64_t k = 0; k < 3 * (int64_t)n_verts; ++k) {
+        if (!std::isfinite(pos[k]) || !std::isfinite(nrm[k]))
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "non-finite position or normal at vertex %lld", (long long)(k / 3));
+    }
+    for (int64_t v = 0; v < n_verts; ++v) {
+        const float *n = nrm + 3 * v;
+        if (n[0] == 0.f && n[1] == 0.f && n[2] == 0.f)
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "zero normal at vertex %lld", (long long)v);
+    }
+    for (int64_t k = 0; k < 3 * (int64_t)n_tris; ++k) {
+        if (idx[k] < 0 || idx[k] >= n_verts)
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "index %d of triangle %lld out of range", idx[k], (long long)(k / 3));
+    }
+    const size_t v0 = ctx->pos.size(), t0 = ctx->tri.size();
+    for (int64_t v = 0; v < n_verts; ++v) {
+        ctx->pos.push_back(make_float4(pos[3 * v], pos[3 * v + 1], pos[3 * v + 2], 0.f));
+        ctx->nrm.push_back(make_float4(nrm[3 * v], nrm[3 * v + 1], nrm[3 * v + 2], 0.f));
+    }
+    for (int64_t t = 0; t < n_tris; ++t) ctx->tri.push_back(make_int4(idx[3 * t], idx[3 * t + 1], idx[3 * t + 2], 0));
+    ScopedDevice sd(ctx->device);
+    hipError_t e = ctx->d_pos.upload(ctx->pos.data(), sizeof(float4) * ctx->pos.size());
+    if (e == hipSuccess) e = ctx->d_nrm.upload(ctx->nrm.data(), sizeof(float4) * ctx->nrm.size());
+    if (e == hipSuccess) e = ctx->d_tri.upload(ctx->tri.data(), sizeof(int4) * ctx->tri.size());
+    if (e != hipSuccess) {
+        ctx->pos.resize(v0);
+        ctx->nrm.resize(v0);
+        ctx->tri.resize(t0);
+        return fail(e == hipErrorOutOfMemory ? ORRB_ERR_OUT_OF_MEMORY : ORRB_ERR_DEVICE, "mesh upload failed: %s",
+                    hipGetErrorString(e));
+    }
+    ctx->mesh_vbegin.push_back((int32_t)ctx->pos.size());
+    ctx->mesh_tbegin.push_back((int32_t)ctx->tri.size());
+    *mesh_id = (int32_t)ctx->mesh_vbegin.size() - 2;
+    return ORRB_OK;
+}
+
+orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orrb_layout **out) {
+    g_last_error.clear();
+    if (!ctx || !d || !out) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL argument");
+    *out = nullptr;
+    if (d->n_scenes < 0 || d->n_frames < 0) return fail(ORRB_ERR_INVALID_ARGUMENT, "negative scene or frame count");
+    if (d->n_scenes > 0 && (!d->scene_object_begin || !d->scene_light_begin))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL scene arrays");
+    if (d->n_frames > 0 && (!d->frame_scene || !d->width || !d->height))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL frame arrays");
+    const int S = d->n_scenes;
+    if (S > 0 && (d->scene_object_begin[0] != 0 || d->scene_light_begin[0] != 0))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "scene offsets must start at 0");
+    for (int s = 0; s < S; ++s) {
+        if (d->scene_object_begin[s + 1] < d->scene_object_begin[s])
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "scene_object_begin decreases at scene %d", s);
+        const int nl = d->scene_light_begin[s + 1] - d->scene_light_begin[s];
+        if (nl < 0) return fail(ORRB_ERR_INVALID_ARGUMENT, "scene_light_begin decreases at scene %d", s);
+        if (nl > ORRB_MAX_LIGHTS_PER_SCENE)
+            return fail(ORRB_ERR_UNSUPPORTED, "scene %d has %d lights (max %d)", s, nl, ORRB_MAX_LIGHTS_PER_SCENE);
+    }
+    const int64_t O = S > 0 ? d->scene_object_begin[S] : 0, NL = S > 0 ? d->scene_light_begin[S] : 0;
+    if (O > 0 && !d->object_mesh) return fail(ORRB_ERR_INVALID_ARGUMENT, "object_mesh is NULL");
+    if (NL > 0 && !d->light_type) return fail(ORRB_ERR_INVALID_ARGUMENT, "light_type is NULL");
+    const int n_meshes = (int)ctx->mesh_vbegin.size() - 1;
+    for (int64_t o = 0; o < O; ++o)
+        if (d->object_mesh[o] < 0 || d->object_mesh[o] >= n_meshes)
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "object %lld uses unknown mesh %d", (long long)o, d->object_mesh[o]);
+    for (int64_t l = 0; l < NL; ++l)
+        if (d->light_type[l] != 0 && d->light_type[l] != 1)
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "light %lld has type %d (0 point, 1 directional)", (long long)l, d->light_type[l]);
+    for (int f = 0; f < d->n_frames; ++f) {
+        if (d->frame_scene[f] < 0 || d->frame_scene[f] >= S)
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "frame %d refers to scene %d of %d", f, d->frame_scene[f], S);
+        if (d->width[f] < 1 || d->width[f] > ORRB_MAX_DIM || d->height[f] < 1 || d->height[f] > ORRB_MAX_DIM)
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "frame %d size %dx%d out of range", f, d->width[f], d->height[f]);
+    }
+    auto *L = new (std::nothrow) orrb_layout();
+    if (!L) return fail(ORRB_ERR_OUT_OF_MEMORY, "host allocation failed");
+    L->ctx = ctx;
+    L->n_scenes = S;
+    L->n_objects = O;
+    L->n_lights = NL;
+    L->n_frames = d->n_frames;
+    // objects: mesh ranges and scene-local vertex / triangle bases
+    std::vector<int64_t> scene_verts(S, 0), scene_tris(S, 0);
+    L->objs.resize(O);
+    for (int s = 0; s < S; ++s) {
+        int64_t vb = 0, tb = 0;
+        for (int o = d->scene_object_begin[s]; o < d->scene_object_begin[s + 1]; ++o) {
+            const int m = d->object_mesh[o];
+            ObjInfo &ob = L->objs[o];
+            ob.mesh_vbegin = ctx->mesh_vbegin[m];
+            ob.n_verts = ctx->mesh_vbegin[m + 1] - ctx->mesh_vbegin[m];
+            ob.mesh_tbegin = ctx->mesh_tbegin[m];
+            ob.n_tris = ctx->mesh_tbegin[m + 1] - ctx->mesh_tbegin[m];
+            ob.scene_vbase = (int32_t)vb;
+            ob.scene_tbase = (int32_t)tb;
+            vb += ob.n_verts;
+            tb += ob.n_tris;
+            if (vb > 0x7fffffff || tb > ORRB_MAX_SCENE_TRIANGLES) {
+                delete L;
+                return fail(ORRB_ERR_UNSUPPORTED, "scene %d exceeds the vertex or triangle limit", s);
+            }
+        }
+        scene_verts[s] = vb;
+        scene_tris[s] = tb;
+    }
+    L->light_type.assign(d->light_type, d->light_type + NL);
+    L->frames.resize(d->n_frames);
+    int64_t pix = 0, vi = 0, oi = 0, ti = 0;
+    for (int f = 0; f < d->n_frames; ++f) {
+        const int s = d->frame_scene[f];
+        FrameInfo &fi = L->frames[f];
+        fi.pixel_offset = pix;
+        fi.vbase = vi;
+        fi.scene = s;
+        fi.width = d->width[f];
+        fi.height = d->height[f];
+        fi.tiles_x = 0;
+        fi.obj_begin = d->scene_object_begin[s];
+        fi.n_obj = d->scene_object_begin[s + 1] - d->scene_object_begin[s];
+        fi.oi_base = (int32_t)oi;
+        fi.light_begin = d->scene_light_begin[s];
+        fi.n_lights = d->scene_light_begin[s + 1] - d->scene_light_begin[s];
+        fi.pad0 = 0;
+        for (int k = 0; k < fi.n_obj; ++k) L->vitems.push_back(make_int2(f, k));
+        pix += (int64_t)fi.width * fi.height;
+        vi += scene_verts[s];
+        ti += scene_tris[s];
+        oi += fi.n_obj;
+        if (oi > 0x7fffffff || (int64_t)L->vitems.size() > 0x7fffffff) {
+            delete L;
+            return fail(ORRB_ERR_UNSUPPORTED, "too many (frame, object) instances");
+        }
+    }
+    L->total_pixels = pix;
+    L->vertex_instances = vi;
+    L->triangle_instances = ti;
+    L->object_instances = oi;
+    build_titems(L);
+    if ((int64_t)L->titems.size() > 0x7fffffff) {
+        delete L;
+        return fail(ORRB_ERR_UNSUPPORTED, "too many tiles");
+    }
+    orrb_status st = upload_layout(L);
+    if (st != ORRB_OK) {
+        delete L;
+        return st;
+    }
+    ctx->n_layouts++;
+    *out = L;
+    return ORRB_OK;
+}
+
+void orrb_layout_destroy(orrb_layout *L) {
+    if (!L) return;
+    ScopedDevice sd(L->ctx->device);
+    L->ctx->n_layouts--;
+    delete L;
+}
+
+orrb_status orrb_layout_info_get(const orrb_layout *L, orrb_layout_info *info) {
+    g_last_error.clear();
+    if (!L || !info) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL argument");
+    info->n_scenes = L->n_scenes;
+    info->n_objects = L->n_objects;
+    info->n_lights = L->n_lights;
+    info->n_frames = L->n_frames;
+    info->total_pixels = L->total_pixels;
+    info->vertex_instances = L->vertex_instances;
+    info->triangle_instances = L->triangle_instances;
+    info->tile_items = (int64_t)L->titems.size();
+    info->workspace_bytes = ws_layout(L).total;
+    info->workspace_bytes_any = ws_layout(L).total;  // the tuning does not change the workspace
+    info->grad_workspace_bytes = 0;
+    info->tuning = L->tuning;
+    return ORRB_OK;
+}
+
+orrb_status orrb_layout_set_tuning(orrb_layout *L, const orrb_tuning *t) {
+    g_last_error.clear();
+    if (!L || !t) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (!valid_tuning(*t))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "invalid tuning tile %dx%d cap %d persistent %d", t->tile_w, t->tile_h,
+                    t->bin_cap, t->persistent);
+    const bool retile = t->tile_w != L->tuning.tile_w || t->tile_h != L->tuning.tile_h;
+    L->tuning = *t;
+    if (retile) {
+        build_titems(L);
+        return upload_layout(L);
+    }
+    return ORRB_OK;
+}
+
+orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+                              const orrb_params *par, const orrb_outputs *out, void *workspace, size_t workspace_bytes,
+                              void *stream) {
+    g_last_error.clear();
+    if (!ctx || !L || !sc || !cam || !par || !out) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL handle or struct");
+    if (L->ctx != ctx) return fail(ORRB_ERR_INVALID_ARGUMENT, "layout belongs to another context");
+    if (L->n_frames == 0) return ORRB_OK;
+    if (L->n_objects > 0 && (!sc->object_pose || !sc->object_seg || !sc->object_visible || !par->albedo ||
+                             !par->roughness || !par->specular))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL object array");
+    if (L->n_lights > 0 && (!par->light_vec || !par->light_intensity))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL light array");
+    if (!cam->view || !cam->intr || !cam->near_plane || !par->exposure)
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL camera array");
+    const WsLayout w = ws_layout(L);
+    if (!workspace) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace is NULL");
+    if (workspace_bytes < w.total)
+        return fail(ORRB_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", workspace_bytes, w.total);
+    if ((uintptr_t)workspace % 16 != 0) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace must be 16-byte aligned");
+    RenderArgs a;
+    memset(&a, 0, sizeof(a));
+    a.frames = (const FrameInfo *)L->d_frames.p;
+    a.objs = (const ObjInfo *)L->d_objs.p;
+    a.vitems = (const int2 *)L->d_vitems.p;
+    a.titems = (const int2 *)L->d_titems.p;
+    a.light_type = (const int32_t *)L->d_light_type.p;
+    a.n_vitems = (int32_t)L->vitems.size();
+    a.n_titems = (int32_t)L->titems.size();
+    a.tile_w = L->tuning.tile_w;
+    a.tile_h = L->tuning.tile_h;
+    a.bin_cap = L->tuning.bin_cap;
+    a.persistent = L->tuning.persistent;
+    a.mesh_pos = (const float4 *)ctx->d_pos.p;
+    a.mesh_nrm = (const float4 *)ctx->d_nrm.p;
+    a.mesh_tri = (const int4 *)ctx->d_tri.p;
+    a.pose = sc->object_pose;
+    a.seg = sc->object_seg;
+    a.visible = sc->object_visible;
+    a.view = cam->view;
+    a.intr = cam->intr;
+    a.near_plane = cam->near_plane;
+    a.albedo = par->albedo;
+    a.roughness = par->roughness;
+    a.specular = par->specular;
+    a.light_vec = par->light_vec;
+    a.light_intensity = par->light_intensity;
+    a.exposure = par->exposure;
+    a.out_rgb = out->rgb;
+    a.out_depth = out->depth;
+    a.out_normal = out->normal;
+    a.out_seg = out->seg;
+    a.out_tri = out->tri_id;
+    a.out_vis = (unsigned long long *)out->vis;
+    char *ws = (char *)workspace;
+    a.vtx_pos = (int4 *)(ws + w.vtx_pos);
+    a.vtx_nrm = (float4 *)(ws + w.vtx_nrm);
+    a.obj_bbox = (int4 *)(ws + w.obj_bbox);
+    a.queue = (unsigned int *)(ws + w.queue);
+    ScopedDevice sd(ctx->device);
+    hipError_t e = launch_render(a, (hipStream_t)stream, ctx->n_cu);
+    if (e != hipSuccess) return fail(ORRB_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ORRB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+"""Python binding of the batched renderer: argument marshalling over the C ABI.
+
+Every step of rendering runs in the HIP kernels of liborrb.so; this module only
+uploads host arrays into torch device tensors, passes their pointers and the current
+HIP stream, and allocates destinations.
+
+Typical use::
+
+    r = Renderer(device=0)
+    job = r.prepare(batch)              # upload meshes + layout + per-batch state
+    out = r.render(job)                 # dict of device tensors (planar channels)
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+STATE_FIELDS = dict(
+    object_pose=torch.float32, object_seg=torch.int32, object_visible=torch.uint8, albedo=torch.float32,
+    roughness=torch.float32, specular=torch.float32, light_vec=torch.float32, light_intensity=torch.float32,
+    view=torch.float32, intr=torch.float32, near=torch.float32, exposure=torch.float32)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, np.int32)
+
+
+class Context:
+    """A device context with its resident mesh pool."""
+
+    def __init__(self, device: int = 0):
+        self.lib = L.load()
+        self.device = int(device)
+        h = C.c_void_p()
+        L.check(self.lib.orrb_create(self.device, C.byref(h)))
+        self.handle = h
+        self._mesh_ids: Dict[int, int] = {}
+        self._keep = []  # meshes whose ids are cached (keeps id() stable)
+
+    def add_mesh(self, mesh) -> int:
+        key = id(mesh)
+        if key in self._mesh_ids:
+            return self._mesh_ids[key]
+        pos = np.ascontiguousarray(mesh.pos, np.float32)
+        nrm = np.ascontiguousarray(mesh.nrm, np.float32)
+        idx = np.ascontiguousarray(mesh.idx, np.int32)
+        mid = C.c_int32()
+        L.check(self.lib.orrb_add_mesh(self.handle, pos.ctypes.data_as(C.c_void_p), nrm.ctypes.data_as(C.c_void_p),
+                                       int(pos.shape[0]), idx.ctypes.data_as(C.c_void_p), int(idx.shape[0]),
+                                       C.byref(mid)))
+        self._mesh_ids[key] = mid.value
+        self._keep.append(mesh)
+        return mid.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.orrb_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Layout:
+    """Validated batch structure (host arrays copied into library-owned device tables)."""
+
+    def __init__(self, ctx: Context, batch, mesh_ids=None):
+        self.ctx = ctx
+        if mesh_ids is None:
+            mesh_ids = [ctx.add_mesh(m) for m in batch.meshes]
+        mesh_ids = np.asarray(mesh_ids, np.int32)
+        om = np.asarray(batch.object_mesh, np.int64)
+        if om.size and (om.min() < 0 or om.max() >= mesh_ids.size):
+            raise L.OrrbError(1, "object_mesh refers to a mesh outside batch.meshes")
+        self._arrays = dict(
+            sob=_i32(batch.scene_object_begin), om=_i32(mesh_ids[om] if om.size else om),
+            slb=_i32(batch.scene_light_begin), lt=_i32(batch.light_type), fs=_i32(batch.frame_scene),
+            w=_i32(batch.width), h=_i32(batch.height))
+        a = self._arrays
+        p = lambda x: x.ctypes.data_as(C.c_void_p)
+        desc = L.LayoutDesc(int(a["sob"].shape[0] - 1), p(a["sob"]), p(a["om"]), p(a["slb"]), p(a["lt"]),
+                            int(a["fs"].shape[0]), p(a["fs"]), p(a["w"]), p(a["h"]))
+        h = C.c_void_p()
+        L.check(ctx.lib.orrb_layout_create(ctx.handle, C.byref(desc), C.byref(h)))
+        self.handle = h
+        self.pixel_offset = np.concatenate([[0], np.cumsum(a["w"].astype(np.int64) * a["h"].astype(np.int64))])
+
+    @property
+    def info(self) -> L.LayoutInfo:
+        inf = L.LayoutInfo()
+        L.check(self.ctx.lib.orrb_layout_info_get(self.handle, C.byref(inf)))
+        return inf
+
+    def set_tuning(self, tile_w=32, tile_h=32, bin_cap=512, persistent=0):
+        t = L.Tuning(tile_w, tile_h, bin_cap, persistent)
+        L.check(self.ctx.lib.orrb_layout_set_tuning(self.handle, C.byref(t)))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.ctx.lib.orrb_layout_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_state(batch, device="cuda") -> Dict[str, torch.Tensor]:
+    """Per-batch state of a generator Batch as contiguous device tensors."""
+    src = dict(object_pose=batch.object_pose, object_seg=batch.object_seg, object_visible=batch.object_visible,
+               albedo=batch.albedo, roughness=batch.roughness, specular=batch.specular, light_vec=batch.light_vec,
+               light_intensity=batch.light_intensity, view=batch.view, intr=batch.intr, near=batch.near,
+               exposure=batch.exposure)
+    out = {}
+    for k, dt in STATE_FIELDS.items():
+        arr = np.ascontiguousarray(src[k])
+        t = torch.from_numpy(arr.astype({torch.float32: np.float32, torch.int32: np.int32,
+                                         torch.uint8: np.uint8}[dt], copy=False))
+        out[k] = t.to(device, non_blocking=False).contiguous()
+    return out
+
+
+@dataclass
+class Job:
+    layout: Layout
+    state: Dict[str, torch.Tensor]
+    total_pixels: int
+    workspace: Optional[torch.Tensor] = None
+    extra: dict = field(default_factory=dict)
+
+
+class Renderer:
+    """Context + helpers to render generator batches."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP renderer needs a GPU (torch.cuda.is_available() is False)")
+        self.device = device
+        self.ctx = Context(device)
+
+    def prepare(self, batch, state: Optional[Dict[str, torch.Tensor]] = None) -> Job:
+        lay = Layout(self.ctx, batch)
+        st = state if state is not None else device_state(batch, f"cuda:{self.device}")
+        inf = lay.info
+        ws = torch.empty(max(int(inf.workspace_bytes_any), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return Job(lay, st, int(inf.total_pixels), ws)
+
+    def alloc_outputs(self, job: Job, tri_id=False, vis=False) -> Dict[str, torch.Tensor]:
+        P = job.total_pixels
+        dev = f"cuda:{self.device}"
+        out = dict(rgb=torch.empty(3 * P, dtype=torch.float32, device=dev),
+                   depth=torch.empty(P, dtype=torch.float32, device=dev),
+                   normal=torch.empty(3 * P, dtype=torch.float32, device=dev),
+                   seg=torch.empty(P, dtype=torch.int32, device=dev))
+        if tri_id:
+            out["tri_id"] = torch.empty(P, dtype=torch.int32, device=dev)
+        if vis:
+            out["vis"] = torch.empty(P, dtype=torch.int64, device=dev)
+        return out
+
+    def render(self, job: Job, out: Optional[Dict[str, torch.Tensor]] = None, tri_id=False, vis=False,
+               stream=None) -> Dict[str, torch.Tensor]:
+        if out is None:
+            out = self.alloc_outputs(job, tri_id, vis)
+        render_batch(self.ctx, job.layout, job.state, out, job.workspace, stream)
+        return out
+
+
+def render_batch(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], out: Dict[str, torch.Tensor],
+                 workspace: torch.Tensor, stream=None):
+    """orrb_render_batch on `stream` (default: torch's current stream)."""
+    s = state
+    sc = L.Scenes(_ptr(s["object_pose"]), _ptr(s["object_seg"]), _ptr(s["object_visible"]))
+    cam = L.Cameras(_ptr(s["view"]), _ptr(s["intr"]), _ptr(s["near"]))
+    par = L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
+                   _ptr(s["light_intensity"]), _ptr(s["exposure"]))
+    o = L.Outputs(_ptr(out.get("rgb")), _ptr(out.get("depth")), _ptr(out.get("normal")), _ptr(out.get("seg")),
+                  _ptr(out.get("tri_id")), _ptr(out.get("vis")))
+    st = stream if stream is not None else torch.cuda.current_stream(ctx.device)
+    L.check(ctx.lib.orrb_render_batch(ctx.handle, layout.handle, C.byref(sc), C.byref(cam), C.byref(par), C.byref(o),
+                                      _ptr(workspace), int(workspace.numel()), C.c_void_p(st.cuda_stream)))
+
+
+def frame_planes(arr: torch.Tensor, pixel_offset, f: int, width: int, height: int, planes: int = 1) -> torch.Tensor:
+    po = int(pixel_offset[f])
+    n = width * height
+    return arr[planes * po: planes * po + planes * n].view(planes, height, width)

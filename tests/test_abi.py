@@ -1,0 +1,87 @@
+"""The C-ABI library: it loads, exports every entry point include/orrb.h declares, and
+the binding's struct layouts match the header (CPU only: no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "orrb.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(orrb_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1906_11633_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("liborrb.so not built")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_1906_11633_amd import _lib
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_struct_sizes_match_header():
+    """Compile a tiny C program against the header and compare struct sizes/offsets
+    with the ctypes declarations."""
+    import subprocess
+    import tempfile
+    from paper_1906_11633_amd import _lib as L
+    structs = {"orrb_layout_desc": L.LayoutDesc, "orrb_tuning": L.Tuning, "orrb_layout_info": L.LayoutInfo,
+               "orrb_scenes": L.Scenes, "orrb_cameras": L.Cameras, "orrb_params": L.Params, "orrb_outputs": L.Outputs}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "s.c"), os.path.join(d, "s")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-o", exe, src], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(l.split() for l in out if l.strip())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
+
+
+def test_create_without_gpu_reports_error(lib):
+    """With no GPU visible, orrb_create fails with a status and a message instead of
+    aborting."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    st = lib.orrb_create(0, C.byref(h))
+    assert st != 0
+    assert lib.orrb_last_error()
+    assert not h.value
+
+
+def test_null_arguments_rejected(lib):
+    """Host validation returns ORRB_ERR_INVALID_ARGUMENT for NULL handles before any
+    device work."""
+    assert lib.orrb_create(0, None) == 1
+    mid = C.c_int32()
+    assert lib.orrb_add_mesh(None, None, None, 3, None, 1, C.byref(mid)) == 1
+    assert lib.orrb_render_batch(None, None, None, None, None, None, None, 0, None) == 1
+    assert lib.orrb_layout_info_get(None, None) == 1
+    lib.orrb_destroy(None)
+    lib.orrb_layout_destroy(None)

@@ -1,0 +1,99 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Sizes are chosen so the oracle finishes in seconds while the GPU path still spans
+many tiles, ragged edge tiles, several objects per tile and several bin flushes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1906_11633_amd import scenes as S
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def renderer():
+    import torch
+    from paper_1906_11633_amd.renderer import Renderer
+    assert torch.cuda.is_available()
+    return Renderer(0)
+
+
+def _render(renderer, batch, tuning=None):
+    import torch
+    job = renderer.prepare(batch)
+    if tuning is not None:
+        job.layout.set_tuning(*tuning)
+    out = renderer.render(job, tri_id=True, vis=True)
+    torch.cuda.synchronize()
+    return parity.to_numpy(out), job
+
+
+def _check(renderer, batch, tuning=None):
+    gpu, _ = _render(renderer, batch, tuning)
+    ref = oracle.render(batch)
+    stats = parity.compare(batch, gpu, ref)
+    print(batch.name, tuning, stats, flush=True)
+    return stats
+
+
+def test_config1(renderer):
+    _check(renderer, S.config1())
+
+
+def test_config1_materials(renderer):
+    _check(renderer, S.config1(materials=True))
+
+
+@pytest.mark.parametrize("res", [200, 77])
+def test_config2_subset(renderer, res):
+    st = _check(renderer, S.config2(2, 3, res))
+    assert st["covered"] > 1000
+
+
+@pytest.mark.parametrize("tuning", [(8, 8, 256, 0), (16, 16, 256, 0), (64, 64, 1024, 0), (64, 16, 512, 1), (32, 32, 512, 1)])
+def test_tunings_bit_identical(renderer, tuning):
+    """Every tuning gives bit-identical outputs (and each meets the oracle bar)."""
+    b = S.config2(2, 2, 96)
+    ref_gpu, _ = _render(renderer, b)
+    gpu, _ = _render(renderer, b, tuning)
+    for k in ("rgb", "depth", "normal", "seg", "tri_id", "vis"):
+        assert np.array_equal(gpu[k], ref_gpu[k]), k
+
+
+def test_fixtures_exact_edges(renderer):
+    """Edge and snapping cases of the oracle's pins, through the HIP path."""
+    from tests.test_oracle_geometry import _view_space_quad
+    for delta in (0.375, 0.5, 0.625, 1.5, -0.375, -0.625):
+        _check(renderer, _view_space_quad(5.5 + delta / 256, 12.75, 3.25, 11.75))
+    _check(renderer, _view_space_quad(3.5, 11.5, 2.5, 9.5))
+
+
+def test_exact_ties_lower_id(renderer):
+    mesh = S.box_mesh(2)
+    pose = S.make_pose(S.uniform_rotation(np.random.default_rng(3)), (0.0, 0.0, -2.0), 0.8)
+    b = S.single_object_batch(mesh, pose, res=(48, 48), extra_objects=[(mesh, pose)])
+    gpu, _ = _render(renderer, b)
+    cov = gpu["tri_id"] >= 0
+    assert cov.sum() > 200
+    assert np.all(gpu["tri_id"][cov] < mesh.n_tris)
+
+
+def test_large_triangles_fp64_edge_path(renderer):
+    """Triangles wider than 64 px take the FP64 edge path; a big tilted plane and a
+    near plane-filling triangle still match the oracle."""
+    R = S.rot_axis("x", 0.7) @ S.rot_axis("y", -0.4)
+    b = S.single_object_batch(S.plane_mesh(2, 2, 3.0, 3.0), S.make_pose(R, (0.05, -0.02, -2.0)), res=(256, 192),
+                              lights=((0, (0.5, 0.5, 0.5), 2.0), (1, (0.2, -0.3, -1.0), 0.7)), spec=0.5, rough=0.3)
+    st = _check(renderer, b)
+    assert st["covered"] > 20000
+
+
+def test_hidden_objects_and_empty_scenes(renderer):
+    b = S.config1(n_scenes=3)
+    vis = b.object_visible.copy()
+    vis[1] = 0
+    vis[3:6] = 0  # every object of scene 1
+    _check(renderer, b.replace(object_visible=vis))
