@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""Benchmark of the batched randomized renderer on one MI355X.
+
+Workload: 256 articulated hand-like scenes (25 capsule links of 512 triangles on a
+24-hinge tree plus a 768-triangle cube, 13,568 triangles per scene) x 3 jittered
+cameras = 768 frames at 200x200, each frame written as fp32 RGB, fp32 depth, fp32
+view-space normal and int32 segmentation (32 B per pixel).  Synthetic, seeded inputs
+stand in for the paper's Shadow-hand benchmark scene (which is not available).
+
+A step is one orrb_render_batch over the whole batch (vertex stage, binning, raster,
+shading, channel writes) with every input already resident in device memory.  The
+line printed reports whole-job frames per second, the raster kernel's achieved write
+bandwidth against the 8 TB/s HBM peak, the plain one-scene-per-launch form, and the
+FP64 CPU oracle timed on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PIXEL = 32  # rgb 12 + depth 4 + normal 12 + seg 4
+METRIC = "randomized 4-channel 200x200 frames/sec on 1 MI355X"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_raster_shade_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1906_11633_amd", "csrc", "orrb_kernels.hip")
+
+
+def kernel_source_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per raster launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source (else None)."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha") != kernel_source_sha():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(batch_fn, n_scenes_total: int, target_s: float, threads: int):
+    """Time the FP64 oracle on the workload (its first scenes if the whole batch would
+    take longer than target_s), repeating it until about target_s of work, and scale
+    to frames per second."""
+    import oracle
+    oracle.build()
+    probe = batch_fn(2)
+    t0 = time.perf_counter()
+    oracle.render(probe, threads=threads)
+    per_scene = (time.perf_counter() - t0) / 2
+    n = max(2, min(n_scenes_total, int(target_s / max(per_scene, 1e-6))))
+    b = batch_fn(n)
+    reps, frames = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.render(b, threads=threads)
+        reps += 1
+        frames += b.n_frames
+        dt = time.perf_counter() - t0
+        if dt >= target_s or reps >= 1000:
+            break
+    what = "the whole workload" if n == n_scenes_total else f"the first {n} of {n_scenes_total} scenes"
+    return dict(value=frames / dt, unit="frames/s", cores=threads, kind="oracle",
+                sample=f"{what} x 3 cameras ({b.n_frames} frames) rendered {reps}x by the FP64 oracle "
+                       f"(OpenMP over frames) in {dt:.1f} s")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--scenes", type=int, default=256)
+    ap.add_argument("--res", type=int, default=200)
+    ap.add_argument("--tile", type=str, default="", help="tile_w,tile_h,bin_cap,persistent")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
+              "(frames shard by scene across GPUs with no exchange; see the design notes).", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1906_11633_amd import scenes as S
+    from paper_1906_11633_amd import _lib
+    from paper_1906_11633_amd.renderer import Renderer, Layout, render_batch
+    import ctypes as C
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    t_gen = time.perf_counter()
+    batch = S.config2(2, args.scenes, args.res)
+    print(f"[bench] generated {batch.n_frames} frames in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    r = Renderer(0)
+    job = r.prepare(batch)
+    if args.tile:
+        tw, th, cap, pers = (int(x) for x in args.tile.split(","))
+        job.layout.set_tuning(tw, th, cap, pers)
+    out = r.alloc_outputs(job)
+    lib, ctx = r.ctx.lib, r.ctx.handle
+    F = batch.n_frames
+    pixels = batch.total_pixels
+
+    for _ in range(args.warmup):
+        r.render(job, out)
+    torch.cuda.synchronize()
+    _lib.check(lib.orrb_profile_enable(ctx, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r.render(job, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = _lib.KernelTimes()
+    _lib.check(lib.orrb_profile_read(ctx, C.byref(kt)))
+    _lib.check(lib.orrb_profile_enable(ctx, 0))
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = F * args.steps / elapsed
+    raster_ms = kt.raster_ms / max(kt.raster_launches, 1)
+    vertex_ms = kt.vertex_ms / max(kt.vertex_launches, 1)
+    bytes_per_launch = BYTES_PER_PIXEL * pixels
+    achieved = bytes_per_launch / (raster_ms * 1e-3) / 1e9
+    print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, raster {raster_ms:.3f} ms, vertex {vertex_ms:.3f} ms",
+          file=sys.stderr, flush=True)
+
+    extra = dict(kernel_ms=dict(k_vertex=round(vertex_ms, 4), k_raster_shade=round(raster_ms, 4)),
+                 tuning=list(job.layout.info.tuning.as_tuple()),
+                 whole_step_hbm_frac=round(bytes_per_launch / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+
+    if not args.no_plain:
+        # the plain form: the same kernels, one scene (3 frames) per launch, no graph
+        ws = job.workspace
+        lays = []
+        st = job.state
+        for s in range(batch.n_scenes):
+            sub = batch.select_scenes([s])
+            lay = Layout(r.ctx, sub)
+            ob, oe = int(batch.scene_object_begin[s]), int(batch.scene_object_begin[s + 1])
+            lb, le = int(batch.scene_light_begin[s]), int(batch.scene_light_begin[s + 1])
+            fr = [int(f) for f in range(F) if batch.frame_scene[f] == s]
+            f0, f1 = fr[0], fr[-1] + 1
+            po = batch.pixel_offset
+            sst = dict(object_pose=st["object_pose"][ob:oe], object_seg=st["object_seg"][ob:oe],
+                       object_visible=st["object_visible"][ob:oe], albedo=st["albedo"][ob:oe],
+                       roughness=st["roughness"][ob:oe], specular=st["specular"][ob:oe],
+                       light_vec=st["light_vec"][lb:le], light_intensity=st["light_intensity"][lb:le],
+                       view=st["view"][f0:f1], intr=st["intr"][f0:f1], near=st["near"][f0:f1],
+                       exposure=st["exposure"][f0:f1])
+            p0, p1 = int(po[f0]), int(po[f1])
+            sout = dict(rgb=out["rgb"][3 * p0:3 * p1], depth=out["depth"][p0:p1], normal=out["normal"][3 * p0:3 * p1],
+                        seg=out["seg"][p0:p1])
+            lays.append((lay, sst, sout))
+        plain_steps = max(3, args.steps // 20)
+        for _ in range(2):
+            for lay, sst, sout in lays:
+                render_batch(r.ctx, lay, sst, sout, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(plain_steps):
+            for lay, sst, sout in lays:
+                render_batch(r.ctx, lay, sst, sout, ws)
+        torch.cuda.synchronize()
+        plain_fps = F * plain_steps / (time.perf_counter() - t0)
+        extra["plain_form_frames_per_s"] = round(plain_fps, 1)
+        extra["batched_over_plain"] = round(value / plain_fps, 2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = cpu_baseline(lambda n: S.config2(2, n, args.res), args.scenes, args.cpu_seconds, threads)
+        cpu["value"] = round(cpu["value"], 3)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.scenes} hand-like scenes x 3 cameras at {args.res}x{args.res} "
+                               f"({F} frames, 13568 triangles/scene, 1-4 point lights), 4 channels fp32 RGB/depth/"
+                               "normal + int32 seg",
+                   "frames_per_step": F, "pixels_per_step": pixels, "bytes_per_pixel": BYTES_PER_PIXEL},
+        "roofline": {"bound": "hbm", "kernel": "k_raster_shade", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic()},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -197,6 +197,24 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *layout, cons
                               const orrb_cameras *cameras, const orrb_params *params, const orrb_outputs *out,
                               void *workspace, size_t workspace_bytes, void *stream);
 
+/* --------------------------------------------------------------------------------- */
+/* kernel timing (observability)                                                      */
+/* --------------------------------------------------------------------------------- */
+
+typedef struct {
+    double vertex_ms;          /* summed device time of k_vertex launches */
+    double raster_ms;          /* summed device time of k_raster_shade launches */
+    int64_t vertex_launches, raster_launches;
+} orrb_kernel_times;
+
+/* Enable (1) or disable (0) per-kernel timing and reset the totals.  While enabled,
+ * every render call brackets each kernel with HIP events recorded on the call's own
+ * stream (a few microseconds of overhead per call). */
+orrb_status orrb_profile_enable(orrb_context *ctx, int enable);
+
+/* Wait for the recorded events and return the totals since the last enable. */
+orrb_status orrb_profile_read(orrb_context *ctx, orrb_kernel_times *out);
+
 #ifdef __cplusplus
 }
 #endif

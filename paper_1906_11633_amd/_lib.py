@@ -63,6 +63,11 @@ class Outputs(C.Structure):
     _fields_ = [("rgb", P), ("depth", P), ("normal", P), ("seg", P), ("tri_id", P), ("vis", P)]
 
 
+class KernelTimes(C.Structure):
+    _fields_ = [("vertex_ms", C.c_double), ("raster_ms", C.c_double), ("vertex_launches", C.c_int64),
+                ("raster_launches", C.c_int64)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "orrb_create": (C.c_int, [C.c_int, C.POINTER(P)]),
@@ -75,6 +80,8 @@ SIGNATURES = {
     "orrb_layout_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
     "orrb_render_batch": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params),
                                     C.POINTER(Outputs), P, C.c_size_t, P]),
+    "orrb_profile_enable": (C.c_int, [P, C.c_int]),
+    "orrb_profile_read": (C.c_int, [P, C.POINTER(KernelTimes)]),
 }
 
 _lock = threading.Lock()

@@ -69,7 +69,8 @@ struct RenderArgs {
 };
 
 // launchers (defined in orrb_kernels.hip)
-hipError_t launch_render(const RenderArgs &a, hipStream_t stream, int n_cu);
+hipError_t launch_vertex(const RenderArgs &a, hipStream_t stream);
+hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu);
 size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap);
 
 }  // namespace orrb

@@ -80,9 +80,50 @@ struct ScopedDevice {
     }
 };
 
+// Per-kernel timing with HIP events on the caller's stream (observability).
+struct KernelTimer {
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];  // 0 vertex, 1 raster
+    double total_ms[2] = {0, 0};
+    int64_t count[2] = {0, 0};
+    hipEvent_t get() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
+    hipError_t drain() {
+        for (int k = 0; k < 2; ++k) {
+            for (auto &pr : pending[k]) {
+                hipError_t e = hipEventSynchronize(pr.second);
+                if (e != hipSuccess) return e;
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, pr.first, pr.second);
+                if (e != hipSuccess) return e;
+                total_ms[k] += ms;
+                count[k] += 1;
+                pool.push_back(pr.first);
+                pool.push_back(pr.second);
+            }
+            pending[k].clear();
+        }
+        return hipSuccess;
+    }
+    ~KernelTimer() {
+        (void)drain();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct orrb_context {
     int device = 0;
     int n_cu = 256;
+    KernelTimer timer;
     // host copies of the pool
     std::vector<float4> pos, nrm;
     std::vector<int4> tri;
@@ -450,8 +491,48 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
     a.obj_bbox = (int4 *)(ws + w.obj_bbox);
     a.queue = (unsigned int *)(ws + w.queue);
     ScopedDevice sd(ctx->device);
-    hipError_t e = launch_render(a, (hipStream_t)stream, ctx->n_cu);
+    hipStream_t st = (hipStream_t)stream;
+    KernelTimer &T = ctx->timer;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (T.enabled) {
+            e0 = T.get();
+            e1 = T.get();
+            if (e0) e = hipEventRecord(e0, st);
+        }
+        if (e == hipSuccess) e = k == 0 ? launch_vertex(a, st) : launch_raster(a, st, ctx->n_cu);
+        if (T.enabled && e0 && e1 && e == hipSuccess) {
+            e = hipEventRecord(e1, st);
+            T.pending[k].push_back({e0, e1});
+        }
+    }
     if (e != hipSuccess) return fail(ORRB_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ORRB_OK;
+}
+
+orrb_status orrb_profile_enable(orrb_context *ctx, int enable) {
+    g_last_error.clear();
+    if (!ctx) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL context");
+    ScopedDevice sd(ctx->device);
+    HIP_TRY(ctx->timer.drain());
+    ctx->timer.enabled = enable != 0;
+    for (int k = 0; k < 2; ++k) {
+        ctx->timer.total_ms[k] = 0;
+        ctx->timer.count[k] = 0;
+    }
+    return ORRB_OK;
+}
+
+orrb_status orrb_profile_read(orrb_context *ctx, orrb_kernel_times *out) {
+    g_last_error.clear();
+    if (!ctx || !out) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL argument");
+    ScopedDevice sd(ctx->device);
+    HIP_TRY(ctx->timer.drain());
+    out->vertex_ms = ctx->timer.total_ms[0];
+    out->raster_ms = ctx->timer.total_ms[1];
+    out->vertex_launches = ctx->timer.count[0];
+    out->raster_launches = ctx->timer.count[1];
     return ORRB_OK;
 }
 

@@ -581,10 +581,13 @@ __global__ __launch_bounds__(kBlock) void k_raster_shade(RenderArgs a) {
     }
 }
 
-hipError_t launch_render(const RenderArgs &a, hipStream_t stream, int n_cu) {
+hipError_t launch_vertex(const RenderArgs &a, hipStream_t stream) {
     hipLaunchKernelGGL(k_vertex, dim3(a.n_vitems > 0 ? a.n_vitems : 1), dim3(kBlock), 0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu) {
+    hipError_t e = hipSuccess;
     if (a.n_titems <= 0) return hipSuccess;
     const size_t lds = raster_lds_bytes(a.tile_w, a.tile_h, a.bin_cap);
     if (lds > 64 * 1024) {
