@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PIXEL = 32  # rgb 12 + depth 4 + normal 12 + seg 4
 METRIC = "randomized 4-channel 200x200 frames/sec on 1 MI355X"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_raster_shade_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_frame_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1906_11633_amd", "csrc", "orrb_kernels.hip")
 
 
@@ -82,7 +82,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--scenes", type=int, default=256)
     ap.add_argument("--res", type=int, default=200)
-    ap.add_argument("--tile", type=str, default="", help="tile_w,tile_h,bin_cap,persistent")
+    ap.add_argument("--tile", type=str, default="", help="tile_w,tile_h,bin_cap,persistent,path")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -107,8 +107,7 @@ def main(argv=None):
     r = Renderer(0)
     job = r.prepare(batch)
     if args.tile:
-        tw, th, cap, pers = (int(x) for x in args.tile.split(","))
-        job.layout.set_tuning(tw, th, cap, pers)
+        job.layout.set_tuning(*(int(x) for x in args.tile.split(",")))
     out = r.alloc_outputs(job)
     lib, ctx = r.ctx.lib, r.ctx.handle
     F = batch.n_frames
@@ -130,14 +129,24 @@ def main(argv=None):
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = F * args.steps / elapsed
-    raster_ms = kt.raster_ms / max(kt.raster_launches, 1)
-    vertex_ms = kt.vertex_ms / max(kt.vertex_launches, 1)
-    bytes_per_launch = BYTES_PER_PIXEL * pixels
-    achieved = bytes_per_launch / (raster_ms * 1e-3) / 1e9
-    print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, raster {raster_ms:.3f} ms, vertex {vertex_ms:.3f} ms",
-          file=sys.stderr, flush=True)
+    avg = lambda ms, n: ms / n if n else 0.0
+    kernel_ms = dict(k_vertex=avg(kt.vertex_ms, kt.vertex_launches), k_raster_shade=avg(kt.raster_ms, kt.raster_launches),
+                     k_frame=avg(kt.frame_ms, kt.frame_launches))
+    # the dominant kernel writes every pixel of the frames it renders
+    info = job.layout.info
+    frame_pixels = sum(int(batch.width[f]) * int(batch.height[f]) for f in range(F)) if info.frame_path_frames == F else None
+    if kernel_ms["k_frame"] >= kernel_ms["k_raster_shade"] and info.frame_path_frames == F:
+        dom, dom_ms, dom_pixels = "k_frame", kernel_ms["k_frame"], frame_pixels
+    else:
+        dom, dom_ms, dom_pixels = "k_raster_shade", kernel_ms["k_raster_shade"], pixels if info.frame_path_frames == 0 else None
+    if dom_pixels is None:
+        raise SystemExit("bench.py expects every frame of the workload on one path")
+    bytes_per_launch = BYTES_PER_PIXEL * dom_pixels
+    achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
+    print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, " +
+          ", ".join(f"{k} {v:.3f} ms" for k, v in kernel_ms.items() if v), file=sys.stderr, flush=True)
 
-    extra = dict(kernel_ms=dict(k_vertex=round(vertex_ms, 4), k_raster_shade=round(raster_ms, 4)),
+    extra = dict(kernel_ms={k: round(v, 4) for k, v in kernel_ms.items() if v},
                  tuning=list(job.layout.info.tuning.as_tuple()),
                  whole_step_hbm_frac=round(bytes_per_launch / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
 
@@ -201,7 +210,7 @@ def main(argv=None):
                                f"({F} frames, 13568 triangles/scene, 1-4 point lights), 4 channels fp32 RGB/depth/"
                                "normal + int32 seg",
                    "frames_per_step": F, "pixels_per_step": pixels, "bytes_per_pixel": BYTES_PER_PIXEL},
-        "roofline": {"bound": "hbm", "kernel": "k_raster_shade", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic()},
         "cpu_baseline": cpu,

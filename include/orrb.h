@@ -115,12 +115,16 @@ typedef struct {
     const int32_t *height;             /* [n_frames] in [1, ORRB_MAX_DIM] */
 } orrb_layout_desc;
 
-/* Tile size and LDS bin capacity of the raster kernel.  They change speed only: the
- * output bits are the same for every valid tuning. */
+/* Launch choices.  They change speed only: the output bits are the same for every
+ * valid tuning.  Frames whose scene fits in LDS (<= 7040 vertices, <= 64 objects,
+ * < 65536 triangles, <= 256x256 pixels) can be rendered whole by one workgroup
+ * ("frame path"); the others go through the tiled path (a vertex kernel, then one
+ * workgroup per screen tile). */
 typedef struct {
-    int32_t tile_w, tile_h;  /* each in {8, 16, 32, 64}; tile_w * tile_h <= 4096 */
-    int32_t bin_cap;         /* triangles staged in LDS per flush, in {256, 512, 1024} */
-    int32_t persistent;      /* 1: persistent grid pulling tiles from a device queue */
+    int32_t tile_w, tile_h;  /* tiled path: tile size, each in {16, 32, 64} */
+    int32_t bin_cap;         /* tiled path: triangles staged in LDS per flush, in {256, 512, 1024} */
+    int32_t persistent;      /* tiled path: 1 = persistent grid pulling tiles from a device queue */
+    int32_t path;            /* 0 = frame path where the scene fits, 1 = tiled path for every frame */
 } orrb_tuning;
 
 typedef struct {
@@ -128,7 +132,8 @@ typedef struct {
     int64_t total_pixels;       /* P: depth/seg hold P values, rgb/normal 3P */
     int64_t vertex_instances;   /* sum over frames of the frame's scene vertex count */
     int64_t triangle_instances; /* sum over frames of the frame's scene triangle count */
-    int64_t tile_items;         /* raster work items with the current tuning */
+    int64_t tile_items;         /* tiled-path work items with the current tuning */
+    int64_t frame_path_frames;  /* frames rendered by the frame path with the current tuning */
     size_t workspace_bytes;      /* workspace orrb_render_batch needs (current tuning) */
     size_t workspace_bytes_any;  /* workspace enough for every valid tuning */
     size_t grad_workspace_bytes; /* workspace orrb_shade_backward needs */
@@ -198,13 +203,41 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *layout, cons
                               void *workspace, size_t workspace_bytes, void *stream);
 
 /* --------------------------------------------------------------------------------- */
+/* shading adjoint (gradients with respect to the randomization parameters)           */
+/* --------------------------------------------------------------------------------- */
+
+typedef struct {                  /* device destinations, overwritten (not accumulated) */
+    float *albedo;                /* [O,3] */
+    float *roughness;             /* [O] */
+    float *specular;              /* [O] */
+    float *light_pos;             /* [L,3] world-space position (0 for directional lights) */
+    float *light_intensity;       /* [L] */
+    float *exposure;              /* [F] */
+} orrb_grads;
+
+/* Gradient of a scalar loss L through the shading, given dL/d(rgb) (`grad_rgb`, device
+ * [3P], planar like the rgb output) and the visibility keys `vis` (device [P]) written
+ * by an orrb_render_batch call with the same layout, scenes and cameras.  The
+ * visibility is held fixed (no parameter here moves geometry).  The adjoint is the
+ * analytic derivative of the shading function in include/orrb.h's conventions,
+ * evaluated per pixel in FP64 and reduced in a fixed order, so repeated calls are
+ * bit-identical.  Sub-gradient 0 is taken where a max(0, .) is inactive.  Scenes with
+ * more than 1024 objects return ORRB_ERR_UNSUPPORTED.  `workspace` needs
+ * orrb_layout_info.grad_workspace_bytes.  Asynchronous on `stream`. */
+orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
+                                const orrb_cameras *cameras, const orrb_params *params, const uint64_t *vis,
+                                const float *grad_rgb, const orrb_grads *grads, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
+/* --------------------------------------------------------------------------------- */
 /* kernel timing (observability)                                                      */
 /* --------------------------------------------------------------------------------- */
 
 typedef struct {
-    double vertex_ms;          /* summed device time of k_vertex launches */
-    double raster_ms;          /* summed device time of k_raster_shade launches */
-    int64_t vertex_launches, raster_launches;
+    double vertex_ms;          /* summed device time of k_vertex launches (tiled path) */
+    double raster_ms;          /* summed device time of k_raster_shade launches (tiled path) */
+    double frame_ms;           /* summed device time of k_frame launches (frame path) */
+    int64_t vertex_launches, raster_launches, frame_launches;
 } orrb_kernel_times;
 
 /* Enable (1) or disable (0) per-kernel timing and reset the totals.  While enabled,

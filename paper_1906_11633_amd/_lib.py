@@ -33,16 +33,18 @@ class LayoutDesc(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("bin_cap", C.c_int32), ("persistent", C.c_int32)]
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("bin_cap", C.c_int32), ("persistent", C.c_int32),
+                ("path", C.c_int32)]
 
     def as_tuple(self):
-        return (self.tile_w, self.tile_h, self.bin_cap, self.persistent)
+        return (self.tile_w, self.tile_h, self.bin_cap, self.persistent, self.path)
 
 
 class LayoutInfo(C.Structure):
     _fields_ = [("n_scenes", C.c_int64), ("n_objects", C.c_int64), ("n_lights", C.c_int64),
                 ("n_frames", C.c_int64), ("total_pixels", C.c_int64), ("vertex_instances", C.c_int64),
-                ("triangle_instances", C.c_int64), ("tile_items", C.c_int64), ("workspace_bytes", C.c_size_t),
+                ("triangle_instances", C.c_int64), ("tile_items", C.c_int64), ("frame_path_frames", C.c_int64),
+                ("workspace_bytes", C.c_size_t),
                 ("workspace_bytes_any", C.c_size_t), ("grad_workspace_bytes", C.c_size_t), ("tuning", Tuning)]
 
 
@@ -63,9 +65,14 @@ class Outputs(C.Structure):
     _fields_ = [("rgb", P), ("depth", P), ("normal", P), ("seg", P), ("tri_id", P), ("vis", P)]
 
 
+class Grads(C.Structure):
+    _fields_ = [("albedo", P), ("roughness", P), ("specular", P), ("light_pos", P), ("light_intensity", P),
+                ("exposure", P)]
+
+
 class KernelTimes(C.Structure):
-    _fields_ = [("vertex_ms", C.c_double), ("raster_ms", C.c_double), ("vertex_launches", C.c_int64),
-                ("raster_launches", C.c_int64)]
+    _fields_ = [("vertex_ms", C.c_double), ("raster_ms", C.c_double), ("frame_ms", C.c_double),
+                ("vertex_launches", C.c_int64), ("raster_launches", C.c_int64), ("frame_launches", C.c_int64)]
 
 
 # name -> (restype, argtypes)
@@ -80,6 +87,8 @@ SIGNATURES = {
     "orrb_layout_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
     "orrb_render_batch": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params),
                                     C.POINTER(Outputs), P, C.c_size_t, P]),
+    "orrb_shade_backward": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params), P, P,
+                                      C.POINTER(Grads), P, C.c_size_t, P]),
     "orrb_profile_enable": (C.c_int, [P, C.c_int]),
     "orrb_profile_read": (C.c_int, [P, C.POINTER(KernelTimes)]),
 }

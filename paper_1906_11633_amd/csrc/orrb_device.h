@@ -39,8 +39,9 @@ struct RenderArgs {
     const ObjInfo *objs;
     const int2 *vitems;     // (frame, object-in-scene) work items of k_vertex
     const int2 *titems;     // (frame, tile) work items of k_raster_shade
+    const int32_t *fitems;  // frames rendered by k_frame
     const int32_t *light_type;
-    int32_t n_vitems, n_titems;
+    int32_t n_vitems, n_titems, n_fitems;
     int32_t tile_w, tile_h, bin_cap;
     int32_t persistent;
     // resident meshes
@@ -62,15 +63,36 @@ struct RenderArgs {
     int32_t *out_seg, *out_tri;
     unsigned long long *out_vis;
     // workspace
-    int4 *vtx_pos;     // X, Y (1/256 px), bits of fp32 1/w, valid flag
-    float4 *vtx_nrm;   // unit view-space normal, fp32 w
+    int4 *vtx_pos;     // per vertex instance: X, Y (1/256 px), bits of fp32 1/w, valid flag
+    float4 *obj_rot;   // per (frame, object): rows of the fp32 view rotation (x, y, z, 0)
     int4 *obj_bbox;    // per (frame, object): covered pixel-centre range i0, j0, i1, j1
     unsigned int *queue;  // persistent work counter
 };
 
-// launchers (defined in orrb_kernels.hip)
+// Shading adjoint over a fixed visibility buffer (orrb_adjoint.hip).
+struct GradArgs {
+    RenderArgs r;                    // every frame on the tiled-path tables (vertex stage)
+    const unsigned long long *vis;   // forward visibility keys
+    const float *grad_rgb;           // dL/d rgb, planar like the forward rgb
+    const int2 *gitems;              // (frame, 32x32 tile) work items
+    const int64_t *gitem_pbase;      // first partial (double) of each item
+    int32_t n_gitems;
+    double *partial;                 // per item: 5 per object, 4 per light, 1 exposure
+    const int32_t *scene_frames, *scene_frame_begin;  // frames of each scene (CSR)
+    const int32_t *frame_item_begin;                  // [F+1] item range of each frame
+    const int32_t *obj_scene, *obj_local, *light_scene, *light_local;
+    float *g_albedo, *g_rough, *g_spec, *g_lpos, *g_lint, *g_expo;
+    int32_t n_objects, n_lights, n_frames;
+};
+
+// launchers (defined in orrb_kernels.hip and orrb_adjoint.hip)
+hipError_t launch_grad(const GradArgs &g, hipStream_t stream);
+int grad_tile_size();
+int grad_max_objects();
 hipError_t launch_vertex(const RenderArgs &a, hipStream_t stream);
 hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu);
+hipError_t launch_frame(const RenderArgs &a, hipStream_t stream);
+bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height);
 size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap);
 
 }  // namespace orrb

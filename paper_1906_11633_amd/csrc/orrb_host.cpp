@@ -84,9 +84,9 @@ struct ScopedDevice {
 struct KernelTimer {
     bool enabled = false;
     std::vector<hipEvent_t> pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];  // 0 vertex, 1 raster
-    double total_ms[2] = {0, 0};
-    int64_t count[2] = {0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];  // 0 vertex, 1 raster, 2 frame
+    double total_ms[3] = {0, 0, 0};
+    int64_t count[3] = {0, 0, 0};
     hipEvent_t get() {
         hipEvent_t e = nullptr;
         if (!pool.empty()) {
@@ -98,7 +98,7 @@ struct KernelTimer {
         return e;
     }
     hipError_t drain() {
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 3; ++k) {
             for (auto &pr : pending[k]) {
                 hipError_t e = hipEventSynchronize(pr.second);
                 if (e != hipSuccess) return e;
@@ -135,15 +135,29 @@ struct orrb_context {
 struct orrb_layout {
     orrb_context *ctx = nullptr;
     int64_t n_scenes = 0, n_objects = 0, n_lights = 0, n_frames = 0;
-    int64_t total_pixels = 0, vertex_instances = 0, triangle_instances = 0, object_instances = 0;
+    int64_t total_pixels = 0, vertex_instances = 0, triangle_instances = 0;
+    // tiled-path sizes with the current tuning, and with every frame on the tiled path
+    int64_t tiled_vertex_instances = 0, tiled_object_instances = 0;
+    int64_t all_vertex_instances = 0, all_object_instances = 0;
     std::vector<FrameInfo> frames;
     std::vector<ObjInfo> objs;
-    std::vector<int2> vitems;
+    std::vector<int64_t> scene_verts, scene_tris;
+    std::vector<uint8_t> fits;  // per frame: the scene fits the frame path
+    std::vector<int2> vitems, titems;
+    std::vector<int32_t> fitems;
     std::vector<int32_t> light_type;
-    std::vector<int32_t> widths, heights;
-    DevBuf d_frames, d_objs, d_vitems, d_titems, d_light_type;
-    std::vector<int2> titems;
-    orrb_tuning tuning{32, 32, 512, 0};
+    DevBuf d_frames, d_objs, d_vitems, d_titems, d_fitems, d_light_type;
+    orrb_tuning tuning{32, 32, 256, 0, 0};
+    // shading adjoint: every frame on the tiled-path vertex tables, gradient tiles
+    std::vector<FrameInfo> frames_all;
+    std::vector<int2> vitems_all, gitems;
+    std::vector<int64_t> gitem_pbase;
+    std::vector<int32_t> frame_item_begin, scene_frame_begin, scene_frames, obj_scene, obj_local, light_scene,
+        light_local;
+    int64_t grad_partials = 0;
+    int max_scene_objects = 0;
+    DevBuf d_frames_all, d_vitems_all, d_gitems, d_gitem_pbase, d_frame_item_begin, d_scene_frame_begin,
+        d_scene_frames, d_obj_scene, d_obj_local, d_light_scene, d_light_local;
 };
 
 // --------------------------------------------------------------------------------------
@@ -153,42 +167,134 @@ struct orrb_layout {
 static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct WsLayout {
-    size_t vtx_pos, vtx_nrm, obj_bbox, queue, total;
+    size_t vtx_pos, obj_rot, obj_bbox, queue, total;
 };
 
-static WsLayout ws_layout(const orrb_layout *L) {
+static WsLayout ws_layout(int64_t vertex_instances, int64_t object_instances) {
     WsLayout w;
     size_t off = 0;
     w.vtx_pos = off;
-    off = al256(off + sizeof(int4) * (size_t)L->vertex_instances);
-    w.vtx_nrm = off;
-    off = al256(off + sizeof(float4) * (size_t)L->vertex_instances);
+    off = al256(off + sizeof(int4) * (size_t)vertex_instances);
+    w.obj_rot = off;
+    off = al256(off + 3 * sizeof(float4) * (size_t)object_instances);
     w.obj_bbox = off;
-    off = al256(off + sizeof(int4) * (size_t)L->object_instances);
+    off = al256(off + sizeof(int4) * (size_t)object_instances);
     w.queue = off;
     off = al256(off + 64);
     w.total = off;
     return w;
 }
 
+static WsLayout ws_layout(const orrb_layout *L) { return ws_layout(L->tiled_vertex_instances, L->tiled_object_instances); }
+
 static bool valid_tuning(const orrb_tuning &t) {
-    auto ok_dim = [](int d) { return d == 8 || d == 16 || d == 32 || d == 64; };
+    auto ok_dim = [](int d) { return d == 16 || d == 32 || d == 64; };
     if (!ok_dim(t.tile_w) || !ok_dim(t.tile_h)) return false;
     if (t.tile_w * t.tile_h > 4096) return false;
     if (t.bin_cap != 256 && t.bin_cap != 512 && t.bin_cap != 1024) return false;
     if (t.persistent != 0 && t.persistent != 1) return false;
+    if (t.path != 0 && t.path != 1) return false;
     return raster_lds_bytes(t.tile_w, t.tile_h, t.bin_cap) <= 160 * 1024;
 }
 
-static void build_titems(orrb_layout *L) {
+// Split frames between the frame path and the tiled path and build the work items.
+static void build_items(orrb_layout *L) {
     L->titems.clear();
+    L->vitems.clear();
+    L->fitems.clear();
     const int TW = L->tuning.tile_w, TH = L->tuning.tile_h;
+    int64_t vi = 0, oi = 0;
     for (int64_t f = 0; f < L->n_frames; ++f) {
         FrameInfo &fi = L->frames[f];
         fi.tiles_x = (fi.width + TW - 1) / TW;
+        if (L->tuning.path == 0 && L->fits[f]) {
+            L->fitems.push_back((int32_t)f);
+            fi.vbase = 0;
+            fi.oi_base = 0;
+            continue;
+        }
+        fi.vbase = vi;
+        fi.oi_base = (int32_t)oi;
+        for (int k = 0; k < fi.n_obj; ++k) L->vitems.push_back(make_int2((int)f, k));
+        vi += L->scene_verts[fi.scene];
+        oi += fi.n_obj;
         const int ty = (fi.height + TH - 1) / TH;
         for (int t = 0; t < fi.tiles_x * ty; ++t) L->titems.push_back(make_int2((int)f, t));
     }
+    L->tiled_vertex_instances = vi;
+    L->tiled_object_instances = oi;
+}
+
+// Tables of the shading adjoint (independent of the tuning).
+static void build_grad_tables(orrb_layout *L, const orrb_layout_desc *d) {
+    const int S = (int)L->n_scenes, F = (int)L->n_frames;
+    L->frames_all = L->frames;
+    int64_t vi = 0, oi = 0;
+    for (int f = 0; f < F; ++f) {
+        FrameInfo &fi = L->frames_all[f];
+        fi.vbase = vi;
+        fi.oi_base = (int32_t)oi;
+        for (int k = 0; k < fi.n_obj; ++k) L->vitems_all.push_back(make_int2(f, k));
+        vi += L->scene_verts[fi.scene];
+        oi += fi.n_obj;
+    }
+    const int G = grad_tile_size();
+    int64_t pb = 0;
+    L->frame_item_begin.assign(F + 1, 0);
+    for (int f = 0; f < F; ++f) {
+        const FrameInfo &fi = L->frames_all[f];
+        const int nt = ((fi.width + G - 1) / G) * ((fi.height + G - 1) / G);
+        L->frame_item_begin[f] = (int32_t)L->gitems.size();
+        for (int t = 0; t < nt; ++t) {
+            L->gitems.push_back(make_int2(f, t));
+            L->gitem_pbase.push_back(pb);
+            pb += 5 * (int64_t)fi.n_obj + 4 * (int64_t)fi.n_lights + 1;
+        }
+    }
+    L->frame_item_begin[F] = (int32_t)L->gitems.size();
+    L->grad_partials = pb;
+    L->scene_frame_begin.assign(S + 1, 0);
+    for (int f = 0; f < F; ++f) L->scene_frame_begin[d->frame_scene[f] + 1]++;
+    for (int s = 0; s < S; ++s) L->scene_frame_begin[s + 1] += L->scene_frame_begin[s];
+    L->scene_frames.assign(F, 0);
+    std::vector<int32_t> cur(L->scene_frame_begin.begin(), L->scene_frame_begin.end() - 1);
+    for (int f = 0; f < F; ++f) L->scene_frames[cur[d->frame_scene[f]]++] = f;
+    L->obj_scene.resize(L->n_objects);
+    L->obj_local.resize(L->n_objects);
+    L->light_scene.resize(L->n_lights);
+    L->light_local.resize(L->n_lights);
+    for (int s = 0; s < S; ++s) {
+        for (int o = d->scene_object_begin[s]; o < d->scene_object_begin[s + 1]; ++o) {
+            L->obj_scene[o] = s;
+            L->obj_local[o] = o - d->scene_object_begin[s];
+        }
+        for (int l = d->scene_light_begin[s]; l < d->scene_light_begin[s + 1]; ++l) {
+            L->light_scene[l] = s;
+            L->light_local[l] = l - d->scene_light_begin[s];
+        }
+        L->max_scene_objects = std::max(L->max_scene_objects, d->scene_object_begin[s + 1] - d->scene_object_begin[s]);
+    }
+}
+
+static orrb_status upload_grad_tables(orrb_layout *L) {
+    ScopedDevice sd(L->ctx->device);
+    HIP_TRY(L->d_frames_all.upload(L->frames_all.data(), sizeof(FrameInfo) * L->frames_all.size()));
+    HIP_TRY(L->d_vitems_all.upload(L->vitems_all.data(), sizeof(int2) * L->vitems_all.size()));
+    HIP_TRY(L->d_gitems.upload(L->gitems.data(), sizeof(int2) * L->gitems.size()));
+    HIP_TRY(L->d_gitem_pbase.upload(L->gitem_pbase.data(), sizeof(int64_t) * L->gitem_pbase.size()));
+    HIP_TRY(L->d_frame_item_begin.upload(L->frame_item_begin.data(), sizeof(int32_t) * L->frame_item_begin.size()));
+    HIP_TRY(L->d_scene_frame_begin.upload(L->scene_frame_begin.data(), sizeof(int32_t) * L->scene_frame_begin.size()));
+    HIP_TRY(L->d_scene_frames.upload(L->scene_frames.data(), sizeof(int32_t) * L->scene_frames.size()));
+    HIP_TRY(L->d_obj_scene.upload(L->obj_scene.data(), sizeof(int32_t) * L->obj_scene.size()));
+    HIP_TRY(L->d_obj_local.upload(L->obj_local.data(), sizeof(int32_t) * L->obj_local.size()));
+    HIP_TRY(L->d_light_scene.upload(L->light_scene.data(), sizeof(int32_t) * L->light_scene.size()));
+    HIP_TRY(L->d_light_local.upload(L->light_local.data(), sizeof(int32_t) * L->light_local.size()));
+    return ORRB_OK;
+}
+
+static size_t grad_workspace(const orrb_layout *L) {
+    return al256(ws_layout(L->all_vertex_instances, L->all_object_instances).total) +
+           al256(sizeof(double) * (size_t)L->grad_partials);
 }
 
 static orrb_status upload_layout(orrb_layout *L) {
@@ -197,6 +303,7 @@ static orrb_status upload_layout(orrb_layout *L) {
     HIP_TRY(L->d_objs.upload(L->objs.data(), sizeof(ObjInfo) * L->objs.size()));
     HIP_TRY(L->d_vitems.upload(L->vitems.data(), sizeof(int2) * L->vitems.size()));
     HIP_TRY(L->d_titems.upload(L->titems.data(), sizeof(int2) * L->titems.size()));
+    HIP_TRY(L->d_fitems.upload(L->fitems.data(), sizeof(int32_t) * L->fitems.size()));
     HIP_TRY(L->d_light_type.upload(L->light_type.data(), sizeof(int32_t) * L->light_type.size()));
     return ORRB_OK;
 }
@@ -204,6 +311,40 @@ static orrb_status upload_layout(orrb_layout *L) {
 // --------------------------------------------------------------------------------------
 // C ABI
 // --------------------------------------------------------------------------------------
+
+static void fill_args(const orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+                      const orrb_params *par, RenderArgs *a) {
+    memset(a, 0, sizeof(*a));
+    a->objs = (const ObjInfo *)L->d_objs.p;
+    a->light_type = (const int32_t *)L->d_light_type.p;
+    a->mesh_pos = (const float4 *)ctx->d_pos.p;
+    a->mesh_nrm = (const float4 *)ctx->d_nrm.p;
+    a->mesh_tri = (const int4 *)ctx->d_tri.p;
+    a->pose = sc->object_pose;
+    a->seg = sc->object_seg;
+    a->visible = sc->object_visible;
+    a->view = cam->view;
+    a->intr = cam->intr;
+    a->near_plane = cam->near_plane;
+    a->albedo = par->albedo;
+    a->roughness = par->roughness;
+    a->specular = par->specular;
+    a->light_vec = par->light_vec;
+    a->light_intensity = par->light_intensity;
+    a->exposure = par->exposure;
+}
+
+static orrb_status check_inputs(const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+                                const orrb_params *par) {
+    if (L->n_objects > 0 && (!sc->object_pose || !sc->object_seg || !sc->object_visible || !par->albedo ||
+                             !par->roughness || !par->specular))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL object array");
+    if (L->n_lights > 0 && (!par->light_vec || !par->light_intensity))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL light array");
+    if (!cam->view || !cam->intr || !cam->near_plane || !par->exposure)
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL camera array");
+    return ORRB_OK;
+}
 
 extern "C" {
 
@@ -322,7 +463,8 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
     L->n_lights = NL;
     L->n_frames = d->n_frames;
     // objects: mesh ranges and scene-local vertex / triangle bases
-    std::vector<int64_t> scene_verts(S, 0), scene_tris(S, 0);
+    L->scene_verts.assign(S, 0);
+    L->scene_tris.assign(S, 0);
     L->objs.resize(O);
     for (int s = 0; s < S; ++s) {
         int64_t vb = 0, tb = 0;
@@ -342,33 +484,35 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
                 return fail(ORRB_ERR_UNSUPPORTED, "scene %d exceeds the vertex or triangle limit", s);
             }
         }
-        scene_verts[s] = vb;
-        scene_tris[s] = tb;
+        L->scene_verts[s] = vb;
+        L->scene_tris[s] = tb;
     }
     L->light_type.assign(d->light_type, d->light_type + NL);
     L->frames.resize(d->n_frames);
+    L->fits.resize(d->n_frames);
     int64_t pix = 0, vi = 0, oi = 0, ti = 0;
     for (int f = 0; f < d->n_frames; ++f) {
         const int s = d->frame_scene[f];
         FrameInfo &fi = L->frames[f];
         fi.pixel_offset = pix;
-        fi.vbase = vi;
+        fi.vbase = 0;
         fi.scene = s;
         fi.width = d->width[f];
         fi.height = d->height[f];
         fi.tiles_x = 0;
         fi.obj_begin = d->scene_object_begin[s];
         fi.n_obj = d->scene_object_begin[s + 1] - d->scene_object_begin[s];
-        fi.oi_base = (int32_t)oi;
+        fi.oi_base = 0;
         fi.light_begin = d->scene_light_begin[s];
         fi.n_lights = d->scene_light_begin[s + 1] - d->scene_light_begin[s];
         fi.pad0 = 0;
-        for (int k = 0; k < fi.n_obj; ++k) L->vitems.push_back(make_int2(f, k));
+        L->fits[f] = frame_fits((int)std::min<int64_t>(L->scene_verts[s], 0x7fffffff), fi.n_obj,
+                                (int)std::min<int64_t>(L->scene_tris[s], 0x7fffffff), fi.width, fi.height);
         pix += (int64_t)fi.width * fi.height;
-        vi += scene_verts[s];
-        ti += scene_tris[s];
+        vi += L->scene_verts[s];
+        ti += L->scene_tris[s];
         oi += fi.n_obj;
-        if (oi > 0x7fffffff || (int64_t)L->vitems.size() > 0x7fffffff) {
+        if (oi > 0x7fffffff) {
             delete L;
             return fail(ORRB_ERR_UNSUPPORTED, "too many (frame, object) instances");
         }
@@ -376,13 +520,16 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
     L->total_pixels = pix;
     L->vertex_instances = vi;
     L->triangle_instances = ti;
-    L->object_instances = oi;
-    build_titems(L);
-    if ((int64_t)L->titems.size() > 0x7fffffff) {
+    L->all_vertex_instances = vi;
+    L->all_object_instances = oi;
+    build_items(L);
+    if ((int64_t)L->titems.size() > 0x7fffffff || (int64_t)L->vitems.size() > 0x7fffffff) {
         delete L;
         return fail(ORRB_ERR_UNSUPPORTED, "too many tiles");
     }
+    build_grad_tables(L, d);
     orrb_status st = upload_layout(L);
+    if (st == ORRB_OK) st = upload_grad_tables(L);
     if (st != ORRB_OK) {
         delete L;
         return st;
@@ -410,9 +557,10 @@ orrb_status orrb_layout_info_get(const orrb_layout *L, orrb_layout_info *info) {
     info->vertex_instances = L->vertex_instances;
     info->triangle_instances = L->triangle_instances;
     info->tile_items = (int64_t)L->titems.size();
+    info->frame_path_frames = (int64_t)L->fitems.size();
     info->workspace_bytes = ws_layout(L).total;
-    info->workspace_bytes_any = ws_layout(L).total;  // the tuning does not change the workspace
-    info->grad_workspace_bytes = 0;
+    info->workspace_bytes_any = ws_layout(L->all_vertex_instances, L->all_object_instances).total;
+    info->grad_workspace_bytes = grad_workspace(L);
     info->tuning = L->tuning;
     return ORRB_OK;
 }
@@ -423,10 +571,10 @@ orrb_status orrb_layout_set_tuning(orrb_layout *L, const orrb_tuning *t) {
     if (!valid_tuning(*t))
         return fail(ORRB_ERR_INVALID_ARGUMENT, "invalid tuning tile %dx%d cap %d persistent %d", t->tile_w, t->tile_h,
                     t->bin_cap, t->persistent);
-    const bool retile = t->tile_w != L->tuning.tile_w || t->tile_h != L->tuning.tile_h;
+    const bool rebuild = t->tile_w != L->tuning.tile_w || t->tile_h != L->tuning.tile_h || t->path != L->tuning.path;
     L->tuning = *t;
-    if (retile) {
-        build_titems(L);
+    if (rebuild) {
+        build_items(L);
         return upload_layout(L);
     }
     return ORRB_OK;
@@ -439,24 +587,23 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
     if (!ctx || !L || !sc || !cam || !par || !out) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL handle or struct");
     if (L->ctx != ctx) return fail(ORRB_ERR_INVALID_ARGUMENT, "layout belongs to another context");
     if (L->n_frames == 0) return ORRB_OK;
-    if (L->n_objects > 0 && (!sc->object_pose || !sc->object_seg || !sc->object_visible || !par->albedo ||
-                             !par->roughness || !par->specular))
-        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL object array");
-    if (L->n_lights > 0 && (!par->light_vec || !par->light_intensity))
-        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL light array");
-    if (!cam->view || !cam->intr || !cam->near_plane || !par->exposure)
-        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL camera array");
+    {
+        const orrb_status st = check_inputs(L, sc, cam, par);
+        if (st != ORRB_OK) return st;
+    }
     const WsLayout w = ws_layout(L);
     if (!workspace) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace is NULL");
     if (workspace_bytes < w.total)
         return fail(ORRB_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", workspace_bytes, w.total);
     if ((uintptr_t)workspace % 16 != 0) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace must be 16-byte aligned");
     RenderArgs a;
-    memset(&a, 0, sizeof(a));
+    fill_args(ctx, L, sc, cam, par, &a);
     a.frames = (const FrameInfo *)L->d_frames.p;
     a.objs = (const ObjInfo *)L->d_objs.p;
     a.vitems = (const int2 *)L->d_vitems.p;
     a.titems = (const int2 *)L->d_titems.p;
+    a.fitems = (const int32_t *)L->d_fitems.p;
+    a.n_fitems = (int32_t)L->fitems.size();
     a.light_type = (const int32_t *)L->d_light_type.p;
     a.n_vitems = (int32_t)L->vitems.size();
     a.n_titems = (int32_t)L->titems.size();
@@ -464,21 +611,6 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
     a.tile_h = L->tuning.tile_h;
     a.bin_cap = L->tuning.bin_cap;
     a.persistent = L->tuning.persistent;
-    a.mesh_pos = (const float4 *)ctx->d_pos.p;
-    a.mesh_nrm = (const float4 *)ctx->d_nrm.p;
-    a.mesh_tri = (const int4 *)ctx->d_tri.p;
-    a.pose = sc->object_pose;
-    a.seg = sc->object_seg;
-    a.visible = sc->object_visible;
-    a.view = cam->view;
-    a.intr = cam->intr;
-    a.near_plane = cam->near_plane;
-    a.albedo = par->albedo;
-    a.roughness = par->roughness;
-    a.specular = par->specular;
-    a.light_vec = par->light_vec;
-    a.light_intensity = par->light_intensity;
-    a.exposure = par->exposure;
     a.out_rgb = out->rgb;
     a.out_depth = out->depth;
     a.out_normal = out->normal;
@@ -487,26 +619,91 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
     a.out_vis = (unsigned long long *)out->vis;
     char *ws = (char *)workspace;
     a.vtx_pos = (int4 *)(ws + w.vtx_pos);
-    a.vtx_nrm = (float4 *)(ws + w.vtx_nrm);
+    a.obj_rot = (float4 *)(ws + w.obj_rot);
     a.obj_bbox = (int4 *)(ws + w.obj_bbox);
     a.queue = (unsigned int *)(ws + w.queue);
     ScopedDevice sd(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     KernelTimer &T = ctx->timer;
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        if (k < 2 && a.n_titems == 0) continue;  // no frame on the tiled path
+        if (k == 2 && a.n_fitems == 0) continue;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (T.enabled) {
             e0 = T.get();
             e1 = T.get();
             if (e0) e = hipEventRecord(e0, st);
         }
-        if (e == hipSuccess) e = k == 0 ? launch_vertex(a, st) : launch_raster(a, st, ctx->n_cu);
+        if (e == hipSuccess) e = k == 0 ? launch_vertex(a, st) : k == 1 ? launch_raster(a, st, ctx->n_cu) : launch_frame(a, st);
         if (T.enabled && e0 && e1 && e == hipSuccess) {
             e = hipEventRecord(e1, st);
             T.pending[k].push_back({e0, e1});
         }
     }
+    if (e != hipSuccess) return fail(ORRB_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ORRB_OK;
+}
+
+orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+                                const orrb_params *par, const uint64_t *vis, const float *grad_rgb, const orrb_grads *gr,
+                                void *workspace, size_t workspace_bytes, void *stream) {
+    g_last_error.clear();
+    if (!ctx || !L || !sc || !cam || !par || !gr) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL handle or struct");
+    if (L->ctx != ctx) return fail(ORRB_ERR_INVALID_ARGUMENT, "layout belongs to another context");
+    if (L->n_frames == 0 && L->n_objects == 0 && L->n_lights == 0) return ORRB_OK;
+    {
+        const orrb_status st = check_inputs(L, sc, cam, par);
+        if (st != ORRB_OK) return st;
+    }
+    if (L->n_frames > 0 && (!vis || !grad_rgb)) return fail(ORRB_ERR_INVALID_ARGUMENT, "vis or grad_rgb is NULL");
+    if ((L->n_objects > 0 && (!gr->albedo || !gr->roughness || !gr->specular)) ||
+        (L->n_lights > 0 && (!gr->light_pos || !gr->light_intensity)) || (L->n_frames > 0 && !gr->exposure))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL gradient destination");
+    if (L->max_scene_objects > grad_max_objects())
+        return fail(ORRB_ERR_UNSUPPORTED, "a scene has %d objects; the adjoint supports %d", L->max_scene_objects,
+                    grad_max_objects());
+    const size_t need = grad_workspace(L);
+    if (!workspace) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace is NULL");
+    if (workspace_bytes < need)
+        return fail(ORRB_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", workspace_bytes, need);
+    if ((uintptr_t)workspace % 16 != 0) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace must be 16-byte aligned");
+    GradArgs g;
+    memset(&g, 0, sizeof(g));
+    fill_args(ctx, L, sc, cam, par, &g.r);
+    const WsLayout w = ws_layout(L->all_vertex_instances, L->all_object_instances);
+    char *ws = (char *)workspace;
+    g.r.frames = (const FrameInfo *)L->d_frames_all.p;
+    g.r.vitems = (const int2 *)L->d_vitems_all.p;
+    g.r.n_vitems = (int32_t)L->vitems_all.size();
+    g.r.vtx_pos = (int4 *)(ws + w.vtx_pos);
+    g.r.obj_rot = (float4 *)(ws + w.obj_rot);
+    g.r.obj_bbox = (int4 *)(ws + w.obj_bbox);
+    g.r.queue = (unsigned int *)(ws + w.queue);
+    g.vis = (const unsigned long long *)vis;
+    g.grad_rgb = grad_rgb;
+    g.gitems = (const int2 *)L->d_gitems.p;
+    g.gitem_pbase = (const int64_t *)L->d_gitem_pbase.p;
+    g.n_gitems = (int32_t)L->gitems.size();
+    g.partial = (double *)(ws + al256(w.total));
+    g.scene_frames = (const int32_t *)L->d_scene_frames.p;
+    g.scene_frame_begin = (const int32_t *)L->d_scene_frame_begin.p;
+    g.frame_item_begin = (const int32_t *)L->d_frame_item_begin.p;
+    g.obj_scene = (const int32_t *)L->d_obj_scene.p;
+    g.obj_local = (const int32_t *)L->d_obj_local.p;
+    g.light_scene = (const int32_t *)L->d_light_scene.p;
+    g.light_local = (const int32_t *)L->d_light_local.p;
+    g.g_albedo = gr->albedo;
+    g.g_rough = gr->roughness;
+    g.g_spec = gr->specular;
+    g.g_lpos = gr->light_pos;
+    g.g_lint = gr->light_intensity;
+    g.g_expo = gr->exposure;
+    g.n_objects = (int32_t)L->n_objects;
+    g.n_lights = (int32_t)L->n_lights;
+    g.n_frames = (int32_t)L->n_frames;
+    ScopedDevice sd(ctx->device);
+    const hipError_t e = launch_grad(g, (hipStream_t)stream);
     if (e != hipSuccess) return fail(ORRB_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ORRB_OK;
 }
@@ -517,7 +714,7 @@ orrb_status orrb_profile_enable(orrb_context *ctx, int enable) {
     ScopedDevice sd(ctx->device);
     HIP_TRY(ctx->timer.drain());
     ctx->timer.enabled = enable != 0;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         ctx->timer.total_ms[k] = 0;
         ctx->timer.count[k] = 0;
     }
@@ -531,8 +728,10 @@ orrb_status orrb_profile_read(orrb_context *ctx, orrb_kernel_times *out) {
     HIP_TRY(ctx->timer.drain());
     out->vertex_ms = ctx->timer.total_ms[0];
     out->raster_ms = ctx->timer.total_ms[1];
+    out->frame_ms = ctx->timer.total_ms[2];
     out->vertex_launches = ctx->timer.count[0];
     out->raster_launches = ctx->timer.count[1];
+    out->frame_launches = ctx->timer.count[2];
     return ORRB_OK;
 }
 

@@ -1,114 +1,38 @@
 // HIP kernels of the batched randomized renderer, written for CDNA4 (gfx950, wave64).
 //
-// Pipeline per batch (all frames of all scenes in two launches):
-//   k_vertex        one workgroup per (frame, object): FP64 transform, projection and
-//                   1/256-px snapping of the object's vertices in a fixed fma order,
-//                   view-space normals, and the object's covered pixel-centre range.
-//   k_raster_shade  one workgroup per (frame, screen tile): cull objects by their
-//                   range, set up their triangles (exact integer area, back-face and
-//                   range cull) and stage the survivors in an LDS bin; rasterize the
-//                   bin with exact edge functions and the top-left rule, one lane per
-//                   (triangle, pixel) pair, into an LDS visibility tile of 64-bit keys
-//                   (fp32 eye depth << 32 | scene-local triangle ID) resolved with
-//                   ds_min_u64; then shade every pixel of the tile from its key
-//                   (deferred shading) and write the planar channels.
+// Two paths render a batch; both produce bit-identical outputs because they share
+// every arithmetic primitive below (vertex snapping, edge functions, fragment depth,
+// shading), compiled with floating-point contraction off.
 //
-// The visibility result is a 64-bit minimum, so it does not depend on the order in
-// which lanes, bins, tiles or workgroups run: outputs are bit-identical for every
-// tile size, bin capacity, launch shape and batch composition.
-#include "orrb_device.h"
+// Frame path (k_frame), for frames whose scene fits in LDS: one 1024-thread workgroup
+// renders a whole frame with no intermediate data in global memory:
+//   1. transform and snap every vertex of the scene (FP64) into LDS;
+//   2. set up every triangle once (exact area, back-face and range cull) and count, per
+//      16x16 screen tile, the triangles whose pixel-centre range touches it;
+//   3. scan the counts and scatter 16-bit triangle IDs into per-tile LDS bins;
+//   4. each wave takes tiles from an LDS counter, rasterizes the tile's bin into its own
+//      256-key LDS visibility tile (ds_min_u64), then shades and writes the tile.
+//
+// Tiled path (k_vertex + k_raster_shade), for any scene size:
+//   k_vertex        one workgroup per (frame, object): FP64 transform and snap into a
+//                   global workspace, the object's covered pixel-centre range and its
+//                   view rotation;
+//   k_raster_shade  one workgroup per (frame, screen tile): cull objects by their
+//                   range, set up their triangles and stage survivors in an LDS bin,
+//                   rasterize (triangle, pixel) pairs into an LDS tile of 64-bit keys,
+//                   then shade and write the tile.
+//
+// A visibility key is (fp32 eye depth bits << 32 | scene-local triangle ID); the
+// nearest fragment wins and exact depth ties go to the lower ID.  Being a 64-bit
+// minimum, the result does not depend on the order in which lanes, bins, tiles or
+// workgroups run: outputs are bit-identical for every tuning and batch composition.
+#include "orrb_primitives.h"
 
 namespace orrb {
 
 // ------------------------------------------------------------------------------------
-// small wave / block helpers
+// tiled path: k_vertex
 // ------------------------------------------------------------------------------------
-
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ int lanes_below(unsigned long long m) {
-    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
-
-// floor(a / 256) and ceil(a / 256) for int32 (arithmetic shift floors)
-__device__ __forceinline__ int floor256(int a) { return a >> 8; }
-__device__ __forceinline__ int ceil256(int a) { return -((-a) >> 8); }
-
-// Exclusive block scan of cnt(k) for k < n (n <= 4 * kBlock); writes pre[0..n].
-template <class F>
-__device__ void block_scan(F cnt, int n, int *pre, int *wave_tot) {
-    const int per = (n + kBlock - 1) / kBlock;
-    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
-    const int start = t * per;
-    int local = 0;
-    for (int k = 0; k < per; ++k)
-        if (start + k < n) local += cnt(start + k);
-    int incl = local;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        int y = __shfl_up(incl, off);
-        if (lane >= off) incl += y;
-    }
-    if (lane == kWave - 1) wave_tot[wave] = incl;
-    __syncthreads();
-    int wbase = 0;
-    for (int w = 0; w < wave; ++w) wbase += wave_tot[w];
-    int run = wbase + incl - local;
-    for (int k = 0; k < per; ++k) {
-        if (start + k < n) {
-            pre[start + k] = run;
-            run += cnt(start + k);
-        }
-    }
-    if (t == kBlock - 1) pre[n] = wbase + incl;
-    __syncthreads();
-}
-
-// ------------------------------------------------------------------------------------
-// k_vertex
-// ------------------------------------------------------------------------------------
-
-// One entry of M = V o W (3x4 affine, row-major) in the fixed fma order the oracle
-// uses; contraction is off so no other fusing can change a rounding.
-__device__ double compose_entry(const float *V, const float *Wp, int e) {
-#pragma clang fp contract(off)
-    const int i = e >> 2, j = e & 3;
-    const double v0 = V[i * 4 + 0], v1 = V[i * 4 + 1], v2 = V[i * 4 + 2], v3 = V[i * 4 + 3];
-    if (j < 3) {
-        double t = v2 * (double)Wp[2 * 4 + j];
-        t = fma(v1, (double)Wp[1 * 4 + j], t);
-        return fma(v0, (double)Wp[0 * 4 + j], t);
-    }
-    return fma(v0, (double)Wp[3], fma(v1, (double)Wp[7], fma(v2, (double)Wp[11], v3)));
-}
-
-struct Snapped {
-    int X, Y, valid;
-    double w;
-};
-
-__device__ Snapped snap_vertex(const double *M, float4 p, double fx, double fy, double cx, double cy, double nearp) {
-#pragma clang fp contract(off)
-    const double x = p.x, y = p.y, z = p.z;
-    const double e0 = fma(M[0], x, fma(M[1], y, fma(M[2], z, M[3])));
-    const double e1 = fma(M[4], x, fma(M[5], y, fma(M[6], z, M[7])));
-    const double e2 = fma(M[8], x, fma(M[9], y, fma(M[10], z, M[11])));
-    Snapped s;
-    s.w = -e2;
-    s.valid = 0;
-    s.X = s.Y = 0;
-    if (s.w >= nearp) {
-        const double qx = e0 / s.w, qy = e1 / s.w;       // IEEE division, round to nearest
-        const double sx = fma(fx, qx, cx), sy = fma(-fy, qy, cy);
-        const double Xd = rint(256.0 * sx), Yd = rint(256.0 * sy);  // half to even
-        if (fabs(Xd) <= (double)kGuard && fabs(Yd) <= (double)kGuard) {
-            s.valid = 1;
-            s.X = (int)Xd;
-            s.Y = (int)Yd;
-        }
-    }
-    return s;
-}
 
 __global__ __launch_bounds__(kBlock) void k_vertex(RenderArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.queue = 0u;  // persistent raster counter
@@ -127,6 +51,10 @@ __global__ __launch_bounds__(kBlock) void k_vertex(RenderArgs a) {
     const ObjInfo ob = a.objs[o];
     if (threadIdx.x < 12) M[threadIdx.x] = compose_entry(a.view + 12 * (int64_t)f, a.pose + 12 * (int64_t)o, threadIdx.x);
     __syncthreads();
+    if (threadIdx.x < 3) {
+        const int r = threadIdx.x;
+        a.obj_rot[3 * (int64_t)oi + r] = make_float4((float)M[4 * r + 0], (float)M[4 * r + 1], (float)M[4 * r + 2], 0.f);
+    }
     const float *K = a.intr + 4 * (int64_t)f;
     const double fx = K[0], fy = K[1], cx = K[2], cy = K[3], nearp = a.near_plane[f];
     double Mr[12];
@@ -135,17 +63,8 @@ __global__ __launch_bounds__(kBlock) void k_vertex(RenderArgs a) {
     int xmin = 0x7fffffff, ymin = 0x7fffffff, xmax = -0x7fffffff, ymax = -0x7fffffff;
     const int64_t vb = fi.vbase + ob.scene_vbase;
     for (int v = threadIdx.x; v < ob.n_verts; v += kBlock) {
-        const float4 p = a.mesh_pos[ob.mesh_vbegin + v];
-        const float4 nn = a.mesh_nrm[ob.mesh_vbegin + v];
-        const Snapped s = snap_vertex(Mr, p, fx, fy, cx, cy, nearp);
-        double nx = Mr[0] * nn.x + Mr[1] * nn.y + Mr[2] * nn.z;
-        double ny = Mr[4] * nn.x + Mr[5] * nn.y + Mr[6] * nn.z;
-        double nz = Mr[8] * nn.x + Mr[9] * nn.y + Mr[10] * nn.z;
-        const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
-        const float wf = (float)s.w;
-        const float iw = 1.0f / wf;
-        a.vtx_pos[vb + v] = make_int4(s.X, s.Y, __float_as_int(iw), s.valid);
-        a.vtx_nrm[vb + v] = make_float4((float)(nx * inv), (float)(ny * inv), (float)(nz * inv), wf);
+        const Snapped s = snap_vertex(Mr, a.mesh_pos[ob.mesh_vbegin + v], fx, fy, cx, cy, nearp);
+        a.vtx_pos[vb + v] = make_int4(s.X, s.Y, __float_as_int(s.iw), s.valid);
         if (s.valid) {
             xmin = min(xmin, s.X);
             xmax = max(xmax, s.X);
@@ -187,139 +106,82 @@ __global__ __launch_bounds__(kBlock) void k_vertex(RenderArgs a) {
 }
 
 // ------------------------------------------------------------------------------------
-// k_raster_shade
+// tiled path: k_raster_shade
 // ------------------------------------------------------------------------------------
 
-// LDS carve-up of one raster workgroup.
-struct Lds {
-    unsigned long long *vis;  // tile_w * tile_h keys
-    int *b_tri, *b_x0, *b_y0, *b_x1, *b_y1, *b_x2, *b_y2, *b_rng, *b_flags, *b_pre;
-    float *b_iw0, *b_iw1, *b_iw2, *b_area;
-    int *ol_obj, *ol_cnt, *ol_pre;
-    float4 *light;
-    int *light_type;
-    int *misc;  // [0] bin count, [1] next item, [4..8) scan scratch
+// LDS of one raster workgroup: a compile-time layout per (tile pixels, bin capacity)
+// instantiation, so every access is a constant LDS address.
+template <int VIS, int CAP>
+struct TileLds {
+    unsigned long long vis[VIS];  // visibility keys of the tile
+    int b_tri[CAP], b_x0[CAP], b_y0[CAP], b_x1[CAP], b_y1[CAP], b_x2[CAP], b_y2[CAP], b_rng[CAP], b_flags[CAP];
+    int b_pre[CAP + 1];
+    float b_iw0[CAP], b_iw1[CAP], b_iw2[CAP], b_area[CAP];
+    // overlapping objects of the current chunk, in scene order
+    int ol_obj[kBlock], ol_tbase[kBlock], ol_mtb[kBlock], ol_mvb[kBlock], ol_vb[kBlock], ol_cnt[kBlock];
+    int ol_pre[kBlock + 1];
+    float ol_R[kBlock][9];
+    float4 light[kMaxLights];
+    int light_type[kMaxLights];
+    int misc[16];  // [0] bin count, [1] next item, [4..8) scan, [8..12) wave counts
 };
 
-__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
-
-__host__ __device__ inline size_t lds_layout(int tw, int th, int cap, char *base, Lds *L) {
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        char *p = base ? base + off : nullptr;
-        off = align16(off + bytes);
-        return p;
-    };
-    char *vis = take(sizeof(unsigned long long) * tw * th);
-    char *bi[10];
-    for (int k = 0; k < 9; ++k) bi[k] = take(sizeof(int) * cap);
-    bi[9] = take(sizeof(int) * (cap + 1));
-    char *bf[4];
-    for (int k = 0; k < 4; ++k) bf[k] = take(sizeof(float) * cap);
-    char *ol0 = take(sizeof(int) * kBlock), *ol1 = take(sizeof(int) * kBlock), *ol2 = take(sizeof(int) * (kBlock + 1));
-    char *lt = take(sizeof(float4) * kMaxLights), *ltt = take(sizeof(int) * kMaxLights);
-    char *misc = take(sizeof(int) * 16);
-    if (L) {
-        L->vis = (unsigned long long *)vis;
-        L->b_tri = (int *)bi[0];
-        L->b_x0 = (int *)bi[1];
-        L->b_y0 = (int *)bi[2];
-        L->b_x1 = (int *)bi[3];
-        L->b_y1 = (int *)bi[4];
-        L->b_x2 = (int *)bi[5];
-        L->b_y2 = (int *)bi[6];
-        L->b_rng = (int *)bi[7];
-        L->b_flags = (int *)bi[8];
-        L->b_pre = (int *)bi[9];
-        L->b_iw0 = (float *)bf[0];
-        L->b_iw1 = (float *)bf[1];
-        L->b_iw2 = (float *)bf[2];
-        L->b_area = (float *)bf[3];
-        L->ol_obj = (int *)ol0;
-        L->ol_cnt = (int *)ol1;
-        L->ol_pre = (int *)ol2;
-        L->light = (float4 *)lt;
-        L->light_type = (int *)ltt;
-        L->misc = (int *)misc;
+// Exclusive scan over n <= 4 * kBlock counts; writes pre[0..n].
+template <class F>
+ORRB_INLINE void block_scan(F cnt, int n, int *pre, int *wave_tot) {
+    const int per = (n + kBlock - 1) / kBlock;
+    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+    const int start = t * per;
+    int local = 0;
+    for (int k = 0; k < per; ++k)
+        if (start + k < n) local += cnt(start + k);
+    int incl = local;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
     }
-    return off;
-}
-
-size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap) { return lds_layout(tile_w, tile_h, bin_cap, nullptr, nullptr); }
-
-// Exact edge functions of the (already swapped, positive-area) triangle a, b, c at
-// pixel centre (PX, PY).  Small triangles (extent <= 2^14) use 24-bit integer
-// products, larger ones FP64 products (exact below 2^53).  Returns E as floats.
-struct Edges {
-    float e0, e1, e2;
-    bool covered;
-};
-
-__device__ __forceinline__ Edges edge_eval(int xa, int ya, int xb, int yb, int xc, int yc, int PX, int PY, int flags) {
-    Edges r;
-    const int b0 = (flags & 1) ? 0 : 1, b1 = (flags & 2) ? 0 : 1, b2 = (flags & 4) ? 0 : 1;
-    if (!(flags & 8)) {
-        const int E0 = __mul24(xc - xb, PY - yb) - __mul24(yc - yb, PX - xb);
-        const int E1 = __mul24(xa - xc, PY - yc) - __mul24(ya - yc, PX - xc);
-        const int E2 = __mul24(xb - xa, PY - ya) - __mul24(yb - ya, PX - xa);
-        r.covered = ((E0 - b0) | (E1 - b1) | (E2 - b2)) >= 0;
-        r.e0 = (float)E0;
-        r.e1 = (float)E1;
-        r.e2 = (float)E2;
-    } else {
-        const double E0 = fma((double)(xc - xb), (double)(PY - yb), -((double)(yc - yb) * (double)(PX - xb)));
-        const double E1 = fma((double)(xa - xc), (double)(PY - yc), -((double)(ya - yc) * (double)(PX - xc)));
-        const double E2 = fma((double)(xb - xa), (double)(PY - ya), -((double)(yb - ya) * (double)(PX - xa)));
-        r.covered = (E0 - b0) >= 0 && (E1 - b1) >= 0 && (E2 - b2) >= 0;
-        r.e0 = (float)E0;
-        r.e1 = (float)E1;
-        r.e2 = (float)E2;
+    if (lane == kWave - 1) wave_tot[wave] = incl;
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += wave_tot[w];
+    int run = wbase + incl - local;
+    for (int k = 0; k < per; ++k) {
+        if (start + k < n) {
+            pre[start + k] = run;
+            run += cnt(start + k);
+        }
     }
-    return r;
+    if (t == kBlock - 1) pre[n] = wbase + incl;
+    __syncthreads();
 }
 
-__device__ __forceinline__ int top_left(int dX, int dY) { return dY < 0 || (dY == 0 && dX > 0); }
-
-// Edge flags of triangle a, b, c: bit k = edge opposite vertex k is top-left, bit 3 =
-// large triangle (FP64 edge path).
-__device__ __forceinline__ int tri_flags(int xa, int ya, int xb, int yb, int xc, int yc, int extent) {
-    return top_left(xc - xb, yc - yb) | (top_left(xa - xc, ya - yc) << 1) | (top_left(xb - xa, yb - ya) << 2) |
-           ((extent > kSmallExtent) ? 8 : 0);
-}
-
-__device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
-__device__ __forceinline__ float dot3(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
-
-// Raster every staged triangle of the bin into the LDS visibility tile.
-__device__ void flush_bin(const Lds &L, int n, int tx0, int ty0, int tile_w) {
+// Raster every staged triangle of the bin: one lane per (triangle, bounding-box pixel)
+// pair, so lanes stay busy whatever the triangle sizes.
+template <class LD>
+ORRB_INLINE void flush_bin(LD &L, int n, int tx0, int ty0, int tile_w) {
     block_scan([&](int k) { const unsigned r = (unsigned)L.b_rng[k]; return (int)(((r >> 16) & 0xff) * (r >> 24)); },
                n, L.b_pre, L.misc + 4);
     const int total = L.b_pre[n];
     for (int w = threadIdx.x; w < total; w += kBlock) {
-        int lo = 0, hi = n;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (L.b_pre[mid] <= w) lo = mid; else hi = mid;
-        }
-        const int k = lo;
+        const int k = find_slot(L.b_pre, n, w);
         const unsigned rng = (unsigned)L.b_rng[k];
         const int nx = (rng >> 16) & 0xff;
         const int r = w - L.b_pre[k];
-        const int dj = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)nx));
+        const int dj = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)nx));  // exact: r < 4096, nx <= 64
         const int di = r - dj * nx;
         const int li = (int)(rng & 0xff) + di, lj = (int)((rng >> 8) & 0xff) + dj;
-        const int PX = ((tx0 + li) << 8) + 128, PY = ((ty0 + lj) << 8) + 128;
-        const Edges e = edge_eval(L.b_x0[k], L.b_y0[k], L.b_x1[k], L.b_y1[k], L.b_x2[k], L.b_y2[k], PX, PY, L.b_flags[k]);
+        const Edges e = edge_eval(L.b_x0[k], L.b_y0[k], L.b_x1[k], L.b_y1[k], L.b_x2[k], L.b_y2[k],
+                                  ((tx0 + li) << 8) + 128, ((ty0 + lj) << 8) + 128, L.b_flags[k]);
         if (!e.covered) continue;
-        const float T = fmaf(e.e0, L.b_iw0[k], fmaf(e.e1, L.b_iw1[k], e.e2 * L.b_iw2[k]));
-        const float z = L.b_area[k] / T;
-        const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | (unsigned)L.b_tri[k];
-        atomicMin(&L.vis[lj * tile_w + li], key);
+        const float z = fragment_depth(e, L.b_iw0[k], L.b_iw1[k], L.b_iw2[k], L.b_area[k]);
+        atomicMin(&L.vis[lj * tile_w + li], vis_key(z, L.b_tri[k]));
     }
     __syncthreads();
 }
 
-__device__ void raster_shade_tile(const RenderArgs &a, int item, const Lds &L) {
+template <class LD>
+ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
     const int2 it = a.titems[item];
     const int f = it.x;
     const FrameInfo fi = a.frames[f];
@@ -327,55 +189,53 @@ __device__ void raster_shade_tile(const RenderArgs &a, int item, const Lds &L) {
     const int tx0 = (it.y % fi.tiles_x) * TW, ty0 = (it.y / fi.tiles_x) * TH;
     const int tw = min(TW, fi.width - tx0), th = min(TH, fi.height - ty0);
     const int tx1 = tx0 + tw - 1, ty1 = ty0 + th - 1;
-    const int tid = threadIdx.x, lane = lane_id();
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
 
     for (int p = tid; p < TW * TH; p += kBlock) L.vis[p] = kEmptyKey;
     if (tid == 0) L.misc[0] = 0;
     if (tid < fi.n_lights) {
         const int l = fi.light_begin + tid;
-        const float *V = a.view + 12 * (int64_t)f;
-        const float *u = a.light_vec + 3 * (int64_t)l;
-        const int type = a.light_type[l];
-        double q[3];
-        for (int r = 0; r < 3; ++r) {
-            const double d = (double)V[r * 4 + 0] * u[0] + (double)V[r * 4 + 1] * u[1] + (double)V[r * 4 + 2] * u[2];
-            q[r] = type == 0 ? d + (double)V[r * 4 + 3] : -d;
-        }
-        if (type != 0) {
-            const double inv = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-            q[0] *= inv;
-            q[1] *= inv;
-            q[2] *= inv;
-        }
-        L.light[tid] = make_float4((float)q[0], (float)q[1], (float)q[2], a.light_intensity[l]);
-        L.light_type[tid] = type;
+        L.light[tid] = view_light(a.view + 12 * (int64_t)f, a.light_vec + 3 * (int64_t)l, a.light_type[l], a.light_intensity[l]);
+        L.light_type[tid] = a.light_type[l];
     }
     __syncthreads();
 
     // ---- visibility: object cull, triangle set-up into the LDS bin, raster ----
     const int64_t vbase = fi.vbase;
+    int n_ol = 0;
     for (int c0 = 0; c0 < fi.n_obj; c0 += kBlock) {
         const int s = c0 + tid;
         bool ov = false;
-        int ntri = 0;
         if (s < fi.n_obj) {
             const int4 bb = a.obj_bbox[fi.oi_base + s];
             ov = bb.x <= bb.z && bb.y <= bb.w && bb.x <= tx1 && bb.z >= tx0 && bb.y <= ty1 && bb.w >= ty0;
-            if (ov) ntri = a.objs[fi.obj_begin + s].n_tris;
         }
-        {   // order-free compaction of overlapping objects
+        {   // order-preserving compaction: the list stays sorted by scene triangle base
             const unsigned long long m = __ballot(ov);
+            if (lane == 0) L.misc[8 + wave] = __popcll(m);
+            __syncthreads();
             int base = 0;
-            if (lane == 0 && m) base = atomicAdd(&L.misc[2], __popcll(m));
-            base = __shfl(base, 0);
+            for (int w = 0; w < wave; ++w) base += L.misc[8 + w];
+            n_ol = L.misc[8] + L.misc[9] + L.misc[10] + L.misc[11];
             if (ov) {
+                const ObjInfo ob = a.objs[fi.obj_begin + s];
                 const int slot = base + lanes_below(m);
                 L.ol_obj[slot] = fi.obj_begin + s;
-                L.ol_cnt[slot] = ntri;
+                L.ol_tbase[slot] = ob.scene_tbase;
+                L.ol_mtb[slot] = ob.mesh_tbegin;
+                L.ol_mvb[slot] = ob.mesh_vbegin;
+                L.ol_vb[slot] = ob.scene_vbase;
+                L.ol_cnt[slot] = ob.n_tris;
+                const float4 *rot = a.obj_rot + 3 * (int64_t)(fi.oi_base + s);
+                for (int r = 0; r < 3; ++r) {
+                    const float4 q = rot[r];
+                    L.ol_R[slot][3 * r + 0] = q.x;
+                    L.ol_R[slot][3 * r + 1] = q.y;
+                    L.ol_R[slot][3 * r + 2] = q.z;
+                }
             }
         }
         __syncthreads();
-        const int n_ol = L.misc[2];
         block_scan([&](int k) { return L.ol_cnt[k]; }, n_ol, L.ol_pre, L.misc + 4);
         const int n_cand = L.ol_pre[n_ol];
         for (int base = 0; base < n_cand; base += kBlock) {
@@ -384,36 +244,28 @@ __device__ void raster_shade_tile(const RenderArgs &a, int item, const Lds &L) {
             int xa = 0, ya = 0, xb = 0, yb = 0, xc = 0, yc = 0, rng = 0, flags = 0, tri_id = 0;
             float iwa = 0.f, iwb = 0.f, iwc = 0.f, area = 0.f;
             if (k < n_cand) {
-                int lo = 0, hi = n_ol;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (L.ol_pre[mid] <= k) lo = mid; else hi = mid;
-                }
-                const int o = L.ol_obj[lo];
-                const int t = k - L.ol_pre[lo];
-                const ObjInfo ob = a.objs[o];
-                const int4 tri = a.mesh_tri[ob.mesh_tbegin + t];
-                const int64_t vb = vbase + ob.scene_vbase;
+                const int sl = find_slot(L.ol_pre, n_ol, k);
+                const int t = k - L.ol_pre[sl];
+                const int4 tri = a.mesh_tri[L.ol_mtb[sl] + t];
+                const int64_t vb = vbase + L.ol_vb[sl];
                 const int4 p0 = a.vtx_pos[vb + tri.x], p1 = a.vtx_pos[vb + tri.y], p2 = a.vtx_pos[vb + tri.z];
-                if (p0.w & p1.w & p2.w) {
+                const int xmin = min(p0.x, min(p1.x, p2.x)), xmax = max(p0.x, max(p1.x, p2.x));
+                const int ymin = min(p0.y, min(p1.y, p2.y)), ymax = max(p0.y, max(p1.y, p2.y));
+                const int i0 = max(ceil256(xmin - 128), tx0), i1 = min(floor256(xmax - 128), tx1);
+                const int j0 = max(ceil256(ymin - 128), ty0), j1 = min(floor256(ymax - 128), ty1);
+                if ((p0.w & p1.w & p2.w) && i0 <= i1 && j0 <= j1) {
                     const long long A = (long long)(p1.x - p0.x) * (p2.y - p0.y) - (long long)(p1.y - p0.y) * (p2.x - p0.x);
                     if (A < 0) {
                         // front face: a = v0, b = v2, c = v1 gives a positive area
+                        keep = true;
                         xa = p0.x; ya = p0.y; xb = p2.x; yb = p2.y; xc = p1.x; yc = p1.y;
-                        const int xmin = min(xa, min(xb, xc)), xmax = max(xa, max(xb, xc));
-                        const int ymin = min(ya, min(yb, yc)), ymax = max(ya, max(yb, yc));
-                        const int i0 = max(ceil256(xmin - 128), tx0), i1 = min(floor256(xmax - 128), tx1);
-                        const int j0 = max(ceil256(ymin - 128), ty0), j1 = min(floor256(ymax - 128), ty1);
-                        if (i0 <= i1 && j0 <= j1) {
-                            keep = true;
-                            rng = (i0 - tx0) | ((j0 - ty0) << 8) | ((i1 - i0 + 1) << 16) | ((j1 - j0 + 1) << 24);
-                            flags = tri_flags(xa, ya, xb, yb, xc, yc, max(xmax - xmin, ymax - ymin));
-                            iwa = __int_as_float(p0.z);
-                            iwb = __int_as_float(p2.z);
-                            iwc = __int_as_float(p1.z);
-                            area = (float)(-A);
-                            tri_id = ob.scene_tbase + t;
-                        }
+                        rng = (i0 - tx0) | ((j0 - ty0) << 8) | ((i1 - i0 + 1) << 16) | ((j1 - j0 + 1) << 24);
+                        flags = tri_flags(xa, ya, xb, yb, xc, yc);
+                        iwa = __int_as_float(p0.z);
+                        iwb = __int_as_float(p2.z);
+                        iwc = __int_as_float(p1.z);
+                        area = (float)(-A);
+                        tri_id = L.ol_tbase[sl] + t;
                     }
                 }
             }
@@ -434,145 +286,98 @@ __device__ void raster_shade_tile(const RenderArgs &a, int item, const Lds &L) {
             }
             __syncthreads();
             const int nb = L.misc[0];
-            if (nb > cap - kBlock || (base + kBlock >= n_cand && c0 + kBlock >= fi.n_obj && nb > 0)) {
+            if (nb > cap - kBlock) {
                 flush_bin(L, nb, tx0, ty0, TW);
                 if (tid == 0) L.misc[0] = 0;
                 __syncthreads();
             }
         }
-        if (tid == 0) L.misc[2] = 0;
-        __syncthreads();
     }
-    // a bin left non-empty by a chunk without candidates in its last round
-    if (L.misc[0] > 0) {
-        flush_bin(L, L.misc[0], tx0, ty0, TW);
+    {
+        const int nb = L.misc[0];
+        if (nb > 0) flush_bin(L, nb, tx0, ty0, TW);
     }
 
     // ---- deferred shading of the tile ----
-    const float *K = a.intr + 4 * (int64_t)f;
-    const float cx = K[2], cy = K[3];
-    const float ifx = (float)(1.0 / (double)K[0]), ify = (float)(1.0 / (double)K[1]);
-    const float expo = a.exposure[f];
+    const bool lds_objs = fi.n_obj <= kBlock;  // the (single) object list is still in LDS
+    const CamF cam = frame_camera(a, f);
     const int64_t HW = (int64_t)fi.width * fi.height, po = fi.pixel_offset;
     const float inv_tw = __builtin_amdgcn_rcpf((float)tw);
-    const int nl = fi.n_lights;
     for (int p = tid; p < tw * th; p += kBlock) {
-        const int lj = (int)(((float)p + 0.5f) * inv_tw);
+        const int lj = (int)(((float)p + 0.5f) * inv_tw);  // exact: p < 4096, tw <= 64
         const int li = p - lj * tw;
         const int i = tx0 + li, j = ty0 + lj;
         const int64_t pix = (int64_t)j * fi.width + i;
         const unsigned long long key = L.vis[lj * TW + li];
-        float r0 = 0.f, r1 = 0.f, r2 = 0.f, z = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+        PixelOut o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float z = 0.f;
         int segv = -1, triv = -1;
         if (key != kEmptyKey) {
             const int tri = (int)(unsigned)(key & 0xffffffffu);
             z = __uint_as_float((unsigned)(key >> 32));
-            int lo = 0, hi = fi.n_obj;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (a.objs[fi.obj_begin + mid].scene_tbase <= tri) lo = mid; else hi = mid;
+            int obj, tbase, mtb, mvb;
+            int64_t vb;
+            float R[9];
+            if (lds_objs) {
+                const int sl = find_slot(L.ol_tbase, n_ol, tri);
+                obj = L.ol_obj[sl];
+                tbase = L.ol_tbase[sl];
+                mtb = L.ol_mtb[sl];
+                mvb = L.ol_mvb[sl];
+                vb = vbase + L.ol_vb[sl];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) R[q] = L.ol_R[sl][q];
+            } else {
+                int lo = 0, hi = fi.n_obj;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (a.objs[fi.obj_begin + mid].scene_tbase <= tri) lo = mid; else hi = mid;
+                }
+                const ObjInfo ob = a.objs[fi.obj_begin + lo];
+                obj = fi.obj_begin + lo;
+                tbase = ob.scene_tbase;
+                mtb = ob.mesh_tbegin;
+                mvb = ob.mesh_vbegin;
+                vb = vbase + ob.scene_vbase;
+                const float4 *rot = a.obj_rot + 3 * (int64_t)(fi.oi_base + lo);
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const float4 q = rot[r];
+                    R[3 * r + 0] = q.x;
+                    R[3 * r + 1] = q.y;
+                    R[3 * r + 2] = q.z;
+                }
             }
-            const int o = fi.obj_begin + lo;
-            const ObjInfo ob = a.objs[o];
-            const int4 tv = a.mesh_tri[ob.mesh_tbegin + (tri - ob.scene_tbase)];
-            const int64_t vb = vbase + ob.scene_vbase;
-            // the winning triangle is front-facing: same swap as in set-up
+            const int4 tv = a.mesh_tri[mtb + (tri - tbase)];
+            // the winning triangle is front-facing: same vertex order as in set-up
             const int4 pa = a.vtx_pos[vb + tv.x], pb = a.vtx_pos[vb + tv.z], pc = a.vtx_pos[vb + tv.y];
-            const float4 na = a.vtx_nrm[vb + tv.x], nb = a.vtx_nrm[vb + tv.z], nc = a.vtx_nrm[vb + tv.y];
-            const int xmin = min(pa.x, min(pb.x, pc.x)), xmax = max(pa.x, max(pb.x, pc.x));
-            const int ymin = min(pa.y, min(pb.y, pc.y)), ymax = max(pa.y, max(pb.y, pc.y));
-            const int flags = (max(xmax - xmin, ymax - ymin) > kSmallExtent) ? 8 : 0;
-            const Edges e = edge_eval(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, (i << 8) + 128, (j << 8) + 128, flags);
-            // perspective-correct weights are proportional to E_k / w_k
-            const float t0 = e.e0 * __int_as_float(pa.z), t1 = e.e1 * __int_as_float(pb.z), t2 = e.e2 * __int_as_float(pc.z);
-            float3 n = f3(fmaf(t0, na.x, fmaf(t1, nb.x, t2 * nc.x)), fmaf(t0, na.y, fmaf(t1, nb.y, t2 * nc.y)),
-                          fmaf(t0, na.z, fmaf(t1, nb.z, t2 * nc.z)));
-            const float ninv = rsqrtf(dot3(n, n));
-            n = f3(n.x * ninv, n.y * ninv, n.z * ninv);
-            const float3 pp = f3(z * ((float)i + 0.5f - cx) * ifx, -z * ((float)j + 0.5f - cy) * ify, -z);
-            const float pinv = rsqrtf(dot3(pp, pp));
-            const float3 v = f3(-pp.x * pinv, -pp.y * pinv, -pp.z * pinv);
-            const float rough = a.roughness[o], ks = a.specular[o];
-            const float mexp = 2.0f / (rough * rough) - 2.0f;
-            const float al0 = a.albedo[3 * o + 0], al1 = a.albedo[3 * o + 1], al2 = a.albedo[3 * o + 2];
-            for (int l = 0; l < nl; ++l) {
-                const float4 Lq = L.light[l];
-                float3 ld;
-                float A;
-                if (L.light_type[l] == 0) {
-                    const float3 d = f3(Lq.x - pp.x, Lq.y - pp.y, Lq.z - pp.z);
-                    const float D = dot3(d, d);
-                    const float dinv = rsqrtf(D);
-                    ld = f3(d.x * dinv, d.y * dinv, d.z * dinv);
-                    A = Lq.w / fmaxf(D, 1e-4f);
-                } else {
-                    ld = f3(Lq.x, Lq.y, Lq.z);
-                    A = Lq.w;
-                }
-                const float ndl = dot3(n, ld);
-                if (ndl <= 0.f) continue;
-                float s = 0.f;
-                const float3 hh = f3(ld.x + v.x, ld.y + v.y, ld.z + v.z);
-                const float H2 = dot3(hh, hh);
-                if (H2 >= 1e-12f) {
-                    const float hinv = rsqrtf(H2);
-                    const float3 dd = f3(n.x - hh.x * hinv, n.y - hh.y * hinv, n.z - hh.z * hinv);
-                    // 1 - n.h evaluated as |n - h|^2 / 2: no cancellation near the highlight
-                    const float u = 0.5f * dot3(dd, dd);
-                    if (u < 1.0f) s = (mexp == 0.f) ? 1.0f : expf(mexp * log1pf(-u));
-                }
-                const float An = A * ndl;
-                r0 = fmaf(An, fmaf(ks, s, al0), r0);
-                r1 = fmaf(An, fmaf(ks, s, al1), r1);
-                r2 = fmaf(An, fmaf(ks, s, al2), r2);
-            }
-            r0 *= expo;
-            r1 *= expo;
-            r2 *= expo;
-            n0 = n.x;
-            n1 = n.y;
-            n2 = n.z;
-            segv = a.seg[o];
+            o = shade_pixel(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, __int_as_float(pa.z), __int_as_float(pb.z),
+                            __int_as_float(pc.z), a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], R,
+                            i, j, z, cam, L.light, L.light_type, fi.n_lights, object_material(a, obj));
+            segv = a.seg[obj];
             triv = tri;
         }
-        if (a.out_rgb) {
-            __builtin_nontemporal_store(r0, a.out_rgb + 3 * po + pix);
-            __builtin_nontemporal_store(r1, a.out_rgb + 3 * po + HW + pix);
-            __builtin_nontemporal_store(r2, a.out_rgb + 3 * po + 2 * HW + pix);
-        }
-        if (a.out_depth) __builtin_nontemporal_store(z, a.out_depth + po + pix);
-        if (a.out_normal) {
-            __builtin_nontemporal_store(n0, a.out_normal + 3 * po + pix);
-            __builtin_nontemporal_store(n1, a.out_normal + 3 * po + HW + pix);
-            __builtin_nontemporal_store(n2, a.out_normal + 3 * po + 2 * HW + pix);
-        }
-        if (a.out_seg) __builtin_nontemporal_store(segv, a.out_seg + po + pix);
-        if (a.out_tri) a.out_tri[po + pix] = triv;
-        if (a.out_vis) a.out_vis[po + pix] = key;
+        store_pixel(a, po, HW, pix, o, z, segv, triv, key);
     }
 }
 
 // Work-item index of workgroup `bid` among `n`, grouping consecutive items on the same
 // XCD (workgroups are dispatched to the 8 XCDs round-robin), so the tiles of one frame
 // share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int bid, int n) {
+ORRB_INLINE int xcd_remap(int bid, int n) {
     const int q = n >> 3, r = n & 7, xcd = bid & 7, local = bid >> 3;
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+template <int VIS, int CAP>
 __global__ __launch_bounds__(kBlock) void k_raster_shade(RenderArgs a) {
-    extern __shared__ __align__(16) char smem[];
-    Lds L;
-    lds_layout(a.tile_w, a.tile_h, a.bin_cap, smem, &L);
-    if (threadIdx.x == 0) L.misc[2] = 0;
+    __shared__ TileLds<VIS, CAP> L;
     if (!a.persistent) {
-        __syncthreads();
         raster_shade_tile(a, xcd_remap(blockIdx.x, gridDim.x), L);
         return;
     }
     int item = blockIdx.x;
     while (item < a.n_titems) {
-        __syncthreads();
         raster_shade_tile(a, item, L);
         __syncthreads();
         if (threadIdx.x == 0) L.misc[1] = (int)gridDim.x + (int)atomicAdd(a.queue, 1u);
@@ -581,28 +386,317 @@ __global__ __launch_bounds__(kBlock) void k_raster_shade(RenderArgs a) {
     }
 }
 
+// ------------------------------------------------------------------------------------
+// frame path: k_frame
+// ------------------------------------------------------------------------------------
+
+constexpr int kFT = 1024;           // threads of a frame workgroup
+constexpr int kFW = kFT / kWave;    // 16 waves
+constexpr int kFVMax = 7040;        // scene vertices held in LDS
+constexpr int kFOMax = 64;          // scene objects
+constexpr int kFTile = 16;          // wave tile edge (pixels)
+constexpr int kFTilesMax = 256;     // frames up to 256 x 256
+constexpr int kFBinMax = 16384;     // (tile, triangle) bin entries
+constexpr int kInvalidX = (int)0x80000000;
+
+struct FrameLds {
+    int X[kFVMax], Y[kFVMax];
+    float iw[kFVMax];
+    union {
+        double M[kFOMax][12];                         // vertex phase
+        unsigned long long vis[kFW][kFTile * kFTile];  // tile phase
+    } u;
+    unsigned short bin[kFBinMax];
+    int cnt[kFTilesMax + 1], off[kFTilesMax + 1];
+    int o_tbase[kFOMax], o_vbase[kFOMax], o_mtb[kFOMax], o_mvb[kFOMax], o_nt[kFOMax], o_seg[kFOMax], o_vis[kFOMax];
+    float o_R[kFOMax][9];
+    Material o_mat[kFOMax];
+    float4 light[kMaxLights];
+    int light_type[kMaxLights];
+    int misc[8];  // [0] next tile, [1] bin overflow, [2] total entries
+};
+static_assert(sizeof(FrameLds) <= 160 * 1024, "frame LDS exceeds 160 KB");
+
+bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height) {
+    const int tiles = ((width + kFTile - 1) / kFTile) * ((height + kFTile - 1) / kFTile);
+    return n_verts <= kFVMax && n_obj <= kFOMax && n_tris < 65536 && tiles <= kFTilesMax;
+}
+
+// Set-up of scene triangle t: front-facing, valid, with pixel centres in
+// [cx0, cx1] x [cy0, cy1].  Vertices in positive-area order a, b, c.
+struct TriSetup {
+    int xa, ya, xb, yb, xc, yc;
+    int i0, j0, i1, j1;  // pixel-centre range inside the clip box
+    int va, vb, vc;      // LDS vertex indices
+    int obj;
+    long long area;
+};
+
+ORRB_INLINE bool frame_setup(const RenderArgs &a, const FrameLds &S, int n_obj, int t, int cx0, int cy0, int cx1, int cy1,
+                             TriSetup &T) {
+    const int k = find_slot(S.o_tbase, n_obj, t);
+    if (!S.o_vis[k]) return false;
+    const int4 tri = a.mesh_tri[S.o_mtb[k] + (t - S.o_tbase[k])];
+    const int vb = S.o_vbase[k];
+    const int i0v = vb + tri.x, i1v = vb + tri.y, i2v = vb + tri.z;
+    const int x0 = S.X[i0v], x1 = S.X[i1v], x2 = S.X[i2v];
+    if (x0 == kInvalidX || x1 == kInvalidX || x2 == kInvalidX) return false;
+    const int y0 = S.Y[i0v], y1 = S.Y[i1v], y2 = S.Y[i2v];
+    const int xmin = min(x0, min(x1, x2)), xmax = max(x0, max(x1, x2));
+    const int ymin = min(y0, min(y1, y2)), ymax = max(y0, max(y1, y2));
+    T.i0 = max(ceil256(xmin - 128), cx0);
+    T.i1 = min(floor256(xmax - 128), cx1);
+    T.j0 = max(ceil256(ymin - 128), cy0);
+    T.j1 = min(floor256(ymax - 128), cy1);
+    if (T.i0 > T.i1 || T.j0 > T.j1) return false;
+    const long long A = (long long)(x1 - x0) * (y2 - y0) - (long long)(y1 - y0) * (x2 - x0);
+    if (A >= 0) return false;
+    T.xa = x0; T.ya = y0; T.xb = x2; T.yb = y2; T.xc = x1; T.yc = y1;
+    T.va = i0v; T.vb = i2v; T.vc = i1v;
+    T.obj = k;
+    T.area = -A;
+    return true;
+}
+
+__global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
+    __shared__ FrameLds S;
+    const int f = a.fitems[blockIdx.x];
+    const FrameInfo fi = a.frames[f];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int n_obj = fi.n_obj, W = fi.width, H = fi.height;
+    const int ntx = (W + kFTile - 1) / kFTile, nty = (H + kFTile - 1) / kFTile, n_tiles = ntx * nty;
+
+    // ---- phase 0: per-object tables, matrices, lights ----
+    if (tid < n_obj) {
+        const int o = fi.obj_begin + tid;
+        const ObjInfo ob = a.objs[o];
+        S.o_tbase[tid] = ob.scene_tbase;
+        S.o_vbase[tid] = ob.scene_vbase;
+        S.o_mtb[tid] = ob.mesh_tbegin;
+        S.o_mvb[tid] = ob.mesh_vbegin;
+        S.o_nt[tid] = ob.n_tris;
+        S.o_seg[tid] = a.seg[o];
+        S.o_vis[tid] = a.visible[o];
+        S.o_mat[tid] = object_material(a, o);
+    }
+    for (int e = tid; e < 12 * n_obj; e += kFT) {
+        const int k = e / 12, q = e - 12 * k;
+        const double m = compose_entry(a.view + 12 * (int64_t)f, a.pose + 12 * (int64_t)(fi.obj_begin + k), q);
+        S.u.M[k][q] = m;
+        if ((q & 3) != 3) S.o_R[k][(q >> 2) * 3 + (q & 3)] = (float)m;
+    }
+    if (tid < fi.n_lights) {
+        const int l = fi.light_begin + tid;
+        S.light[tid] = view_light(a.view + 12 * (int64_t)f, a.light_vec + 3 * (int64_t)l, a.light_type[l], a.light_intensity[l]);
+        S.light_type[tid] = a.light_type[l];
+    }
+    for (int t = tid; t <= n_tiles; t += kFT) S.cnt[t] = 0;
+    if (tid < 8) S.misc[tid] = 0;
+    __syncthreads();
+
+    // ---- phase 1: vertices ----
+    const int n_verts = n_obj > 0 ? S.o_vbase[n_obj - 1] + a.objs[fi.obj_begin + n_obj - 1].n_verts : 0;
+    const int n_tris = n_obj > 0 ? S.o_tbase[n_obj - 1] + S.o_nt[n_obj - 1] : 0;
+    {
+        const float *K = a.intr + 4 * (int64_t)f;
+        const double fx = K[0], fy = K[1], cx = K[2], cy = K[3], nearp = a.near_plane[f];
+        for (int v = tid; v < n_verts; v += kFT) {
+            const int k = find_slot(S.o_vbase, n_obj, v);
+            int X = kInvalidX, Y = 0;
+            float iw = 0.f;
+            if (S.o_vis[k]) {
+                double M[12];
+#pragma unroll
+                for (int q = 0; q < 12; ++q) M[q] = S.u.M[k][q];
+                const Snapped s = snap_vertex(M, a.mesh_pos[S.o_mvb[k] + (v - S.o_vbase[k])], fx, fy, cx, cy, nearp);
+                if (s.valid) {
+                    X = s.X;
+                    Y = s.Y;
+                    iw = s.iw;
+                }
+            }
+            S.X[v] = X;
+            S.Y[v] = Y;
+            S.iw[v] = iw;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 2: set-up and per-tile counts ----
+    for (int t = tid; t < n_tris; t += kFT) {
+        TriSetup T;
+        if (!frame_setup(a, S, n_obj, t, 0, 0, W - 1, H - 1, T)) continue;
+        for (int ty = T.j0 >> 4; ty <= (T.j1 >> 4); ++ty)
+            for (int tx = T.i0 >> 4; tx <= (T.i1 >> 4); ++tx) atomicAdd(&S.cnt[ty * ntx + tx], 1);
+    }
+    __syncthreads();
+    if (wave == 0) {  // exclusive scan of n_tiles <= 256 counts, 4 per lane
+        int c[4], local = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = lane * 4 + q;
+            c[q] = t < n_tiles ? S.cnt[t] : 0;
+            local += c[q];
+        }
+        int incl = local;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        int run = incl - local;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = lane * 4 + q;
+            if (t < n_tiles) {
+                S.off[t] = run;
+                S.cnt[t] = run;  // becomes the scatter cursor
+            }
+            run += c[q];
+        }
+        if (lane == kWave - 1) {
+            S.off[n_tiles] = incl;
+            S.misc[2] = incl;
+            S.misc[1] = incl > kFBinMax;
+        }
+    }
+    __syncthreads();
+    const bool overflow = S.misc[1] != 0;
+
+    // ---- phase 3: scatter triangle IDs into the tile bins ----
+    if (!overflow) {
+        for (int t = tid; t < n_tris; t += kFT) {
+            TriSetup T;
+            if (!frame_setup(a, S, n_obj, t, 0, 0, W - 1, H - 1, T)) continue;
+            for (int ty = T.j0 >> 4; ty <= (T.j1 >> 4); ++ty)
+                for (int tx = T.i0 >> 4; tx <= (T.i1 >> 4); ++tx)
+                    S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)t;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 4: waves raster, shade and write tiles ----
+    const CamF cam = frame_camera(a, f);
+    const int64_t HW = (int64_t)W * H, po = fi.pixel_offset;
+    unsigned long long *vis = S.u.vis[wave];
+    while (true) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(&S.misc[0], 1);
+        t = __shfl(t, 0);
+        if (t >= n_tiles) break;
+        const int tyi = t / ntx, txi = t - tyi * ntx;
+        const int x0 = txi * kFTile, y0 = tyi * kFTile;
+        const int x1 = min(x0 + kFTile, W) - 1, y1 = min(y0 + kFTile, H) - 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vis[lane + 64 * q] = kEmptyKey;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // without bins (overflow) the wave scans every triangle of the scene
+        const int e0 = overflow ? 0 : S.off[t], e1 = overflow ? n_tris : S.off[t + 1];
+        for (int e = e0 + lane; e < e1; e += kWave) {
+            const int tri = overflow ? e : (int)S.bin[e];
+            TriSetup T;
+            if (!frame_setup(a, S, n_obj, tri, x0, y0, x1, y1, T)) continue;
+            const int flags = tri_flags(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc);
+            const float iwa = S.iw[T.va], iwb = S.iw[T.vb], iwc = S.iw[T.vc];
+            const float area = (float)T.area;
+            for (int j = T.j0; j <= T.j1; ++j) {
+                for (int i = T.i0; i <= T.i1; ++i) {
+                    const Edges ed = edge_eval(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc, (i << 8) + 128, (j << 8) + 128, flags);
+                    if (!ed.covered) continue;
+                    atomicMin(&vis[(j - y0) * kFTile + (i - x0)], vis_key(fragment_depth(ed, iwa, iwb, iwc, area), tri));
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int p = lane + 64 * q;
+            const int li = p & (kFTile - 1), lj = p >> 4;
+            const int i = x0 + li, j = y0 + lj;
+            if (i > x1 || j > y1) continue;
+            const int64_t pix = (int64_t)j * W + i;
+            const unsigned long long key = vis[p];
+            PixelOut o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float z = 0.f;
+            int segv = -1, triv = -1;
+            if (key != kEmptyKey) {
+                const int tri = (int)(unsigned)(key & 0xffffffffu);
+                z = __uint_as_float((unsigned)(key >> 32));
+                const int k = find_slot(S.o_tbase, n_obj, tri);
+                const int4 tv = a.mesh_tri[S.o_mtb[k] + (tri - S.o_tbase[k])];
+                const int vb = S.o_vbase[k], mvb = S.o_mvb[k];
+                const int va = vb + tv.x, vbb = vb + tv.z, vc = vb + tv.y;  // positive-area order
+                o = shade_pixel(S.X[va], S.Y[va], S.X[vbb], S.Y[vbb], S.X[vc], S.Y[vc], S.iw[va], S.iw[vbb], S.iw[vc],
+                                a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], S.o_R[k], i, j, z,
+                                cam, S.light, S.light_type, fi.n_lights, S.o_mat[k]);
+                segv = S.o_seg[k];
+                triv = tri;
+            }
+            store_pixel(a, po, HW, pix, o, z, segv, triv, key);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------
+
+size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap) {
+    const size_t vis = sizeof(unsigned long long) * (size_t)tile_w * tile_h;
+    const size_t bin = sizeof(int) * (size_t)bin_cap * 14 + sizeof(int);
+    const size_t rest = sizeof(int) * (7 * kBlock + 1) + sizeof(float) * 9 * kBlock + sizeof(float4) * kMaxLights +
+                        sizeof(int) * (kMaxLights + 16);
+    return vis + bin + rest;
+}
+
 hipError_t launch_vertex(const RenderArgs &a, hipStream_t stream) {
     hipLaunchKernelGGL(k_vertex, dim3(a.n_vitems > 0 ? a.n_vitems : 1), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu) {
-    hipError_t e = hipSuccess;
-    if (a.n_titems <= 0) return hipSuccess;
-    const size_t lds = raster_lds_bytes(a.tile_w, a.tile_h, a.bin_cap);
-    if (lds > 64 * 1024) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_raster_shade),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+template <int VIS, int CAP>
+static hipError_t launch_raster_t(const RenderArgs &a, hipStream_t stream, int n_cu) {
     int grid = a.n_titems;
     if (a.persistent) {
+        const size_t lds = sizeof(TileLds<VIS, CAP>);
         int per_cu = (int)((160 * 1024) / (lds + 1024));
         per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
         grid = n_cu * per_cu;
         if (grid > a.n_titems) grid = a.n_titems;
     }
-    hipLaunchKernelGGL(k_raster_shade, dim3(grid), dim3(kBlock), lds, stream, a);
+    hipLaunchKernelGGL((k_raster_shade<VIS, CAP>), dim3(grid), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <int VIS>
+static hipError_t launch_raster_cap(const RenderArgs &a, hipStream_t stream, int n_cu) {
+    switch (a.bin_cap) {
+        case 256: return launch_raster_t<VIS, 256>(a, stream, n_cu);
+        case 512: return launch_raster_t<VIS, 512>(a, stream, n_cu);
+        case 1024: return launch_raster_t<VIS, 1024>(a, stream, n_cu);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu) {
+    if (a.n_titems <= 0) return hipSuccess;
+    switch (a.tile_w * a.tile_h) {
+        case 256: return launch_raster_cap<256>(a, stream, n_cu);
+        case 512: return launch_raster_cap<512>(a, stream, n_cu);
+        case 1024: return launch_raster_cap<1024>(a, stream, n_cu);
+        case 2048: return launch_raster_cap<2048>(a, stream, n_cu);
+        case 4096: return launch_raster_cap<4096>(a, stream, n_cu);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_frame(const RenderArgs &a, hipStream_t stream) {
+    if (a.n_fitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_frame, dim3(a.n_fitems), dim3(kFT), 0, stream, a);
     return hipGetLastError();
 }
 

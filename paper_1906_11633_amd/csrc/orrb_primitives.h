@@ -1,0 +1,288 @@
+// Device arithmetic primitives shared by every kernel of the batched renderer (vertex
+// snapping, exact edge functions, fragment depth, shading, stores).  All kernels use
+// these same inline functions, compiled with contraction off where the result bits
+// matter, so every path produces bit-identical results.
+#pragma once
+
+#include "orrb_device.h"
+
+namespace orrb {
+
+#define ORRB_INLINE __device__ __attribute__((always_inline)) inline
+
+// ------------------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------------------
+
+ORRB_INLINE int lane_id() { return __lane_id(); }
+
+ORRB_INLINE int lanes_below(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// floor(a / 256) and ceil(a / 256) for int32 (arithmetic shift floors)
+ORRB_INLINE int floor256(int a) { return a >> 8; }
+ORRB_INLINE int ceil256(int a) { return -((-a) >> 8); }
+
+ORRB_INLINE float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+ORRB_INLINE float dot3(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+
+ORRB_INLINE int find_slot(const int *base, int n, int x) {  // largest k < n with base[k] <= x
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------------------------
+// vertex stage (FP64, the oracle's fma order, no contraction)
+// ------------------------------------------------------------------------------------
+
+// One entry e = 4 i + j of M = V o W (3x4 affine, row-major).
+ORRB_INLINE double compose_entry(const float *V, const float *Wp, int e) {
+#pragma clang fp contract(off)
+    const int i = e >> 2, j = e & 3;
+    const double v0 = V[i * 4 + 0], v1 = V[i * 4 + 1], v2 = V[i * 4 + 2], v3 = V[i * 4 + 3];
+    if (j < 3) {
+        double t = v2 * (double)Wp[2 * 4 + j];
+        t = fma(v1, (double)Wp[1 * 4 + j], t);
+        return fma(v0, (double)Wp[0 * 4 + j], t);
+    }
+    return fma(v0, (double)Wp[3], fma(v1, (double)Wp[7], fma(v2, (double)Wp[11], v3)));
+}
+
+struct Snapped {
+    int X, Y, valid;
+    float iw;  // fp32 1 / w
+};
+
+// Transform, project and snap one vertex: X = rint(256 sx), Y = rint(256 sy), valid if
+// w >= near and both inside the +-2^24 guard band.
+ORRB_INLINE Snapped snap_vertex(const double *M, float4 p, double fx, double fy, double cx, double cy, double nearp) {
+#pragma clang fp contract(off)
+    const double x = p.x, y = p.y, z = p.z;
+    const double e0 = fma(M[0], x, fma(M[1], y, fma(M[2], z, M[3])));
+    const double e1 = fma(M[4], x, fma(M[5], y, fma(M[6], z, M[7])));
+    const double e2 = fma(M[8], x, fma(M[9], y, fma(M[10], z, M[11])));
+    const double w = -e2;
+    Snapped s;
+    s.valid = 0;
+    s.X = s.Y = 0;
+    s.iw = 0.f;
+    if (w >= nearp) {
+        const double qx = e0 / w, qy = e1 / w;  // IEEE division, round to nearest
+        const double sx = fma(fx, qx, cx), sy = fma(-fy, qy, cy);
+        const double Xd = rint(256.0 * sx), Yd = rint(256.0 * sy);  // half to even
+        if (fabs(Xd) <= (double)kGuard && fabs(Yd) <= (double)kGuard) {
+            s.valid = 1;
+            s.X = (int)Xd;
+            s.Y = (int)Yd;
+            s.iw = 1.0f / (float)w;
+        }
+    }
+    return s;
+}
+
+// ------------------------------------------------------------------------------------
+// triangle set-up and edge functions
+// ------------------------------------------------------------------------------------
+
+// Exact edge functions of the positive-area triangle a, b, c at pixel centre (PX, PY).
+// Small triangles (extent <= 2^14) use 24-bit integer products, larger ones FP64
+// products (exact below 2^53).  E_k is the edge opposite vertex k.
+struct Edges {
+    float e0, e1, e2;
+    bool covered;
+};
+
+ORRB_INLINE Edges edge_eval(int xa, int ya, int xb, int yb, int xc, int yc, int PX, int PY, int flags) {
+    Edges r;
+    const int b0 = (flags & 1) ? 0 : 1, b1 = (flags & 2) ? 0 : 1, b2 = (flags & 4) ? 0 : 1;
+    if (!(flags & 8)) {
+        const int E0 = __mul24(xc - xb, PY - yb) - __mul24(yc - yb, PX - xb);
+        const int E1 = __mul24(xa - xc, PY - yc) - __mul24(ya - yc, PX - xc);
+        const int E2 = __mul24(xb - xa, PY - ya) - __mul24(yb - ya, PX - xa);
+        r.covered = ((E0 - b0) | (E1 - b1) | (E2 - b2)) >= 0;  // top-left rule
+        r.e0 = (float)E0;
+        r.e1 = (float)E1;
+        r.e2 = (float)E2;
+    } else {
+        const double E0 = fma((double)(xc - xb), (double)(PY - yb), -((double)(yc - yb) * (double)(PX - xb)));
+        const double E1 = fma((double)(xa - xc), (double)(PY - yc), -((double)(ya - yc) * (double)(PX - xc)));
+        const double E2 = fma((double)(xb - xa), (double)(PY - ya), -((double)(yb - ya) * (double)(PX - xa)));
+        r.covered = (E0 - b0) >= 0 && (E1 - b1) >= 0 && (E2 - b2) >= 0;
+        r.e0 = (float)E0;
+        r.e1 = (float)E1;
+        r.e2 = (float)E2;
+    }
+    return r;
+}
+
+ORRB_INLINE int top_left(int dX, int dY) { return dY < 0 || (dY == 0 && dX > 0); }
+
+ORRB_INLINE int extent_flag(int xa, int ya, int xb, int yb, int xc, int yc) {
+    const int ext = max(max(xa, max(xb, xc)) - min(xa, min(xb, xc)), max(ya, max(yb, yc)) - min(ya, min(yb, yc)));
+    return ext > kSmallExtent ? 8 : 0;
+}
+
+// bit k = the edge opposite vertex k is top-left; bit 3 = large triangle (FP64 edges)
+ORRB_INLINE int tri_flags(int xa, int ya, int xb, int yb, int xc, int yc) {
+    return top_left(xc - xb, yc - yb) | (top_left(xa - xc, ya - yc) << 1) | (top_left(xb - xa, yb - ya) << 2) |
+           extent_flag(xa, ya, xb, yb, xc, yc);
+}
+
+// Perspective-correct eye depth of a covered fragment: z = A / sum_k E_k / w_k.
+ORRB_INLINE float fragment_depth(const Edges &e, float iwa, float iwb, float iwc, float area) {
+#pragma clang fp contract(off)
+    const float T = fmaf(e.e0, iwa, fmaf(e.e1, iwb, e.e2 * iwc));
+    return area / T;
+}
+
+ORRB_INLINE unsigned long long vis_key(float z, int tri) {
+    return ((unsigned long long)__float_as_uint(z) << 32) | (unsigned)tri;
+}
+
+// ------------------------------------------------------------------------------------
+// shading (shared by both paths)
+// ------------------------------------------------------------------------------------
+
+// A scene light in the frame's view space: point lights as a position, directional
+// lights as the unit direction toward the light; w = intensity.
+ORRB_INLINE float4 view_light(const float *V, const float *u, int type, float intensity) {
+    double q[3];
+    for (int r = 0; r < 3; ++r) {
+        const double d = (double)V[r * 4 + 0] * u[0] + (double)V[r * 4 + 1] * u[1] + (double)V[r * 4 + 2] * u[2];
+        q[r] = type == 0 ? d + (double)V[r * 4 + 3] : -d;
+    }
+    if (type != 0) {
+        const double inv = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        q[0] *= inv;
+        q[1] *= inv;
+        q[2] *= inv;
+    }
+    return make_float4((float)q[0], (float)q[1], (float)q[2], intensity);
+}
+
+struct Material {
+    float rough, ks, al0, al1, al2;
+};
+
+struct CamF {
+    float cx, cy, ifx, ify, expo;
+};
+
+struct PixelOut {
+    float r0, r1, r2, n0, n1, n2;
+};
+
+ORRB_INLINE float3 rotate_normal(const float *R, float4 q) {
+#pragma clang fp contract(off)
+    const float3 r = f3(fmaf(R[0], q.x, fmaf(R[1], q.y, R[2] * q.z)), fmaf(R[3], q.x, fmaf(R[4], q.y, R[5] * q.z)),
+                        fmaf(R[6], q.x, fmaf(R[7], q.y, R[8] * q.z)));
+    const float s = rsqrtf(dot3(r, r));
+    return f3(r.x * s, r.y * s, r.z * s);
+}
+
+// Shade the covered pixel (i, j) at eye depth z of the positive-area triangle a, b, c:
+// perspective-correct smooth normal from the object-space vertex normals rotated by R,
+// then exposure * sum over lights of A * max(0, n.l) * (albedo + k_s * max(0, n.h)^m).
+ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc, float iwa, float iwb, float iwc,
+                                 float4 na4, float4 nb4, float4 nc4, const float *R, int i, int j, float z,
+                                 const CamF &cam, const float4 *light, const int *ltype, int nl, const Material &m) {
+#pragma clang fp contract(off)
+    const Edges e = edge_eval(xa, ya, xb, yb, xc, yc, (i << 8) + 128, (j << 8) + 128, extent_flag(xa, ya, xb, yb, xc, yc));
+    // perspective-correct weights are proportional to E_k / w_k
+    const float t0 = e.e0 * iwa, t1 = e.e1 * iwb, t2 = e.e2 * iwc;
+    const float3 na = rotate_normal(R, na4), nb = rotate_normal(R, nb4), nc = rotate_normal(R, nc4);
+    float3 n = f3(fmaf(t0, na.x, fmaf(t1, nb.x, t2 * nc.x)), fmaf(t0, na.y, fmaf(t1, nb.y, t2 * nc.y)),
+                  fmaf(t0, na.z, fmaf(t1, nb.z, t2 * nc.z)));
+    const float ninv = rsqrtf(dot3(n, n));
+    n = f3(n.x * ninv, n.y * ninv, n.z * ninv);
+    const float3 pp = f3(z * (((float)i + 0.5f - cam.cx) * cam.ifx), -z * (((float)j + 0.5f - cam.cy) * cam.ify), -z);
+    const float pinv = rsqrtf(dot3(pp, pp));
+    const float3 v = f3(-pp.x * pinv, -pp.y * pinv, -pp.z * pinv);
+    const float mexp = 2.0f / (m.rough * m.rough) - 2.0f;
+    float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+    for (int l = 0; l < nl; ++l) {
+        const float4 Lq = light[l];
+        float3 ld;
+        float A;
+        if (ltype[l] == 0) {
+            const float3 d = f3(Lq.x - pp.x, Lq.y - pp.y, Lq.z - pp.z);
+            const float D = dot3(d, d);
+            const float dinv = rsqrtf(D);
+            ld = f3(d.x * dinv, d.y * dinv, d.z * dinv);
+            A = Lq.w / fmaxf(D, 1e-4f);
+        } else {
+            ld = f3(Lq.x, Lq.y, Lq.z);
+            A = Lq.w;
+        }
+        const float ndl = dot3(n, ld);
+        if (ndl <= 0.f) continue;
+        float s = 0.f;
+        const float3 hh = f3(ld.x + v.x, ld.y + v.y, ld.z + v.z);
+        const float H2 = dot3(hh, hh);
+        if (H2 >= 1e-12f) {
+            const float hinv = rsqrtf(H2);
+            const float3 dd = f3(n.x - hh.x * hinv, n.y - hh.y * hinv, n.z - hh.z * hinv);
+            // 1 - n.h evaluated as |n - h|^2 / 2: no cancellation near the highlight
+            const float u = 0.5f * dot3(dd, dd);
+            if (u < 1.0f) s = (mexp == 0.f) ? 1.0f : expf(mexp * log1pf(-u));
+        }
+        const float An = A * ndl;
+        r0 = fmaf(An, fmaf(m.ks, s, m.al0), r0);
+        r1 = fmaf(An, fmaf(m.ks, s, m.al1), r1);
+        r2 = fmaf(An, fmaf(m.ks, s, m.al2), r2);
+    }
+    PixelOut o;
+    o.r0 = r0 * cam.expo;
+    o.r1 = r1 * cam.expo;
+    o.r2 = r2 * cam.expo;
+    o.n0 = n.x;
+    o.n1 = n.y;
+    o.n2 = n.z;
+    return o;
+}
+
+ORRB_INLINE void store_pixel(const RenderArgs &a, int64_t po, int64_t HW, int64_t pix, const PixelOut &o, float z, int seg,
+                             int tri, unsigned long long key) {
+    if (a.out_rgb) {
+        __builtin_nontemporal_store(o.r0, a.out_rgb + 3 * po + pix);
+        __builtin_nontemporal_store(o.r1, a.out_rgb + 3 * po + HW + pix);
+        __builtin_nontemporal_store(o.r2, a.out_rgb + 3 * po + 2 * HW + pix);
+    }
+    if (a.out_depth) __builtin_nontemporal_store(z, a.out_depth + po + pix);
+    if (a.out_normal) {
+        __builtin_nontemporal_store(o.n0, a.out_normal + 3 * po + pix);
+        __builtin_nontemporal_store(o.n1, a.out_normal + 3 * po + HW + pix);
+        __builtin_nontemporal_store(o.n2, a.out_normal + 3 * po + 2 * HW + pix);
+    }
+    if (a.out_seg) __builtin_nontemporal_store(seg, a.out_seg + po + pix);
+    if (a.out_tri) a.out_tri[po + pix] = tri;
+    if (a.out_vis) a.out_vis[po + pix] = key;
+}
+
+ORRB_INLINE CamF frame_camera(const RenderArgs &a, int f) {
+    const float *K = a.intr + 4 * (int64_t)f;
+    CamF c;
+    c.cx = K[2];
+    c.cy = K[3];
+    c.ifx = (float)(1.0 / (double)K[0]);
+    c.ify = (float)(1.0 / (double)K[1]);
+    c.expo = a.exposure[f];
+    return c;
+}
+
+ORRB_INLINE Material object_material(const RenderArgs &a, int o) {
+    Material m;
+    m.rough = a.roughness[o];
+    m.ks = a.specular[o];
+    m.al0 = a.albedo[3 * o + 0];
+    m.al1 = a.albedo[3 * o + 1];
+    m.al2 = a.albedo[3 * o + 2];
+    return m;
+}
+
+}  // namespace orrb

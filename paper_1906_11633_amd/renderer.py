@@ -104,8 +104,8 @@ class Layout:
         L.check(self.ctx.lib.orrb_layout_info_get(self.handle, C.byref(inf)))
         return inf
 
-    def set_tuning(self, tile_w=32, tile_h=32, bin_cap=512, persistent=0):
-        t = L.Tuning(tile_w, tile_h, bin_cap, persistent)
+    def set_tuning(self, tile_w=32, tile_h=32, bin_cap=256, persistent=0, path=0):
+        t = L.Tuning(tile_w, tile_h, bin_cap, persistent, path)
         L.check(self.ctx.lib.orrb_layout_set_tuning(self.handle, C.byref(t)))
 
     def close(self):
@@ -194,6 +194,41 @@ def render_batch(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], o
     st = stream if stream is not None else torch.cuda.current_stream(ctx.device)
     L.check(ctx.lib.orrb_render_batch(ctx.handle, layout.handle, C.byref(sc), C.byref(cam), C.byref(par), C.byref(o),
                                       _ptr(workspace), int(workspace.numel()), C.c_void_p(st.cuda_stream)))
+
+
+def shade_backward(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], vis: torch.Tensor,
+                   grad_rgb: torch.Tensor, workspace: Optional[torch.Tensor] = None, stream=None) -> Dict[str, torch.Tensor]:
+    """orrb_shade_backward: gradients of the loss with respect to albedo [O,3],
+    roughness [O], specular [O], light_pos [L,3] (world), light_intensity [L] and
+    exposure [F], given dL/d(rgb) and the forward visibility keys."""
+    s = state
+    dev = vis.device
+    inf = layout.info
+    if workspace is None or workspace.numel() < inf.grad_workspace_bytes:
+        workspace = torch.empty(max(int(inf.grad_workspace_bytes), 256), dtype=torch.uint8, device=dev)
+    O, Lc, F = int(inf.n_objects), int(inf.n_lights), int(inf.n_frames)
+    g = dict(albedo=torch.empty((O, 3), dtype=torch.float32, device=dev),
+             roughness=torch.empty(O, dtype=torch.float32, device=dev),
+             specular=torch.empty(O, dtype=torch.float32, device=dev),
+             light_pos=torch.empty((Lc, 3), dtype=torch.float32, device=dev),
+             light_intensity=torch.empty(Lc, dtype=torch.float32, device=dev),
+             exposure=torch.empty(F, dtype=torch.float32, device=dev))
+    sc = L.Scenes(_ptr(s["object_pose"]), _ptr(s["object_seg"]), _ptr(s["object_visible"]))
+    cam = L.Cameras(_ptr(s["view"]), _ptr(s["intr"]), _ptr(s["near"]))
+    par = L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
+                   _ptr(s["light_intensity"]), _ptr(s["exposure"]))
+    gr = L.Grads(_ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]), _ptr(g["light_pos"]),
+                 _ptr(g["light_intensity"]), _ptr(g["exposure"]))
+    grad_rgb = grad_rgb.contiguous()
+    if grad_rgb.dtype != torch.float32 or grad_rgb.numel() != 3 * int(inf.total_pixels):
+        raise ValueError("grad_rgb must be float32 with 3 * total_pixels elements")
+    if vis.dtype != torch.int64 or vis.numel() != int(inf.total_pixels):
+        raise ValueError("vis must be int64 with total_pixels elements")
+    st = stream if stream is not None else torch.cuda.current_stream(ctx.device)
+    L.check(ctx.lib.orrb_shade_backward(ctx.handle, layout.handle, C.byref(sc), C.byref(cam), C.byref(par), _ptr(vis),
+                                        _ptr(grad_rgb), C.byref(gr), _ptr(workspace), int(workspace.numel()),
+                                        C.c_void_p(st.cuda_stream)))
+    return g
 
 
 def frame_planes(arr: torch.Tensor, pixel_offset, f: int, width: int, height: int, planes: int = 1) -> torch.Tensor:

@@ -53,14 +53,47 @@ def test_config2_subset(renderer, res):
     assert st["covered"] > 1000
 
 
-@pytest.mark.parametrize("tuning", [(8, 8, 256, 0), (16, 16, 256, 0), (64, 64, 1024, 0), (64, 16, 512, 1), (32, 32, 512, 1)])
+@pytest.mark.parametrize("tuning", [(16, 16, 256, 0, 1), (16, 32, 256, 0, 1), (32, 32, 512, 0, 1), (64, 64, 1024, 0, 1),
+                                    (64, 16, 512, 1, 1), (32, 32, 256, 1, 1)])
 def test_tunings_bit_identical(renderer, tuning):
-    """Every tuning gives bit-identical outputs (and each meets the oracle bar)."""
+    """Every tuning of the tiled path gives bit-identical outputs to the frame path."""
     b = S.config2(2, 2, 96)
-    ref_gpu, _ = _render(renderer, b)
-    gpu, _ = _render(renderer, b, tuning)
+    ref_gpu, job = _render(renderer, b)
+    assert job.layout.info.frame_path_frames == b.n_frames
+    gpu, job = _render(renderer, b, tuning)
+    assert job.layout.info.frame_path_frames == 0
     for k in ("rgb", "depth", "normal", "seg", "tri_id", "vis"):
         assert np.array_equal(gpu[k], ref_gpu[k]), k
+
+
+def test_tiled_path_config2(renderer):
+    _check(renderer, S.config2(2, 3, 200), tuning=(32, 32, 256, 0, 1))
+
+
+def test_frame_path_bin_overflow(renderer):
+    """Three overlapping screen-filling planes put more (tile, triangle) pairs in the
+    frame than the LDS bins hold: the frame path falls back to scanning every
+    triangle per tile, with the same result."""
+    mesh = S.plane_mesh(47, 47, 3.2, 3.2)
+    R = S.rot_axis("x", 0.2)
+    extra = [(mesh, S.make_pose(R, (0.02, -0.03, -2.2), 1.0)), (mesh, S.make_pose(R.T, (-0.01, 0.02, -2.4), 1.0))]
+    b = S.single_object_batch(mesh, S.make_pose(np.eye(3), (0.0, 0.0, -2.0), 1.0), res=(256, 256), extra_objects=extra,
+                              lights=((0, (0.3, 0.4, 0.5), 1.5),), spec=0.4, rough=0.5)
+    gpu, job = _render(renderer, b)
+    assert job.layout.info.frame_path_frames == 1
+    stats = parity.compare(b, gpu, oracle.render(b))
+    print(stats)
+    assert stats["covered"] > 50000
+
+
+def test_mixed_paths_uneven_batch(renderer):
+    """An uneven batch (resolutions 64..256, 2k-50k triangles): scenes that fit LDS take
+    the frame path, the others the tiled path, in one call."""
+    b = S.config3(3, 6)
+    gpu, job = _render(renderer, b)
+    inf = job.layout.info
+    assert 0 < inf.frame_path_frames < b.n_frames
+    parity.compare(b, gpu, oracle.render(b))
 
 
 def test_fixtures_exact_edges(renderer):
