@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PIXEL = 32  # rgb 12 + depth 4 + normal 12 + seg 4
-METRIC = "randomized 4-channel 200x200 frames/sec on 1 MI355X"
+METRIC = "randomized 4-channel 200x200 frames/sec on 1 MI355X; shading-grad/sec; p99 ms"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_frame_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1906_11633_amd", "csrc", "orrb_kernels.hip")
 
@@ -75,6 +75,91 @@ def cpu_baseline(batch_fn, n_scenes_total: int, target_s: float, threads: int):
                        f"(OpenMP over frames) in {dt:.1f} s")
 
 
+def _timed(fn, reps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def measure_extras(args, r, S):
+    """Shading-gradient throughput (64 scenes x 3 cameras at 200x200), the serving loop
+    (Poisson 2000 req/s of 1-32 scenes at 64/128/200 px), and the uneven batch (1024
+    scenes, 64-256 px, 2k-50k triangles) autotuned and replayed from a HIP graph
+    against its one-scene-per-launch form."""
+    import torch
+    import oracle
+    from paper_1906_11633_amd.renderer import Graph, Layout, autotune, render_batch, shade_backward
+    from paper_1906_11633_amd.serving import ScenePool, Server, poisson_trace
+    ex = {}
+    # shading gradient
+    base, target = S.config4(4, 64, 200)
+    job = r.prepare(base)
+    out = r.render(job, vis=True)
+    tgt = torch.from_numpy(oracle.render(target)["rgb"].astype("float32")).cuda()
+    grad_rgb = (2.0 * (out["rgb"] - tgt)).contiguous()
+    ws = torch.empty(int(job.layout.info.grad_workspace_bytes), dtype=torch.uint8, device="cuda")
+    step = lambda: shade_backward(r.ctx, job.layout, job.state, out["vis"], grad_rgb, ws)
+    step()
+    dt = _timed(step, 10, torch)
+    ex["shading_grad"] = dict(frames=base.n_frames, ms_per_backward=round(dt * 1e3, 3),
+                              grad_frames_per_s=round(base.n_frames / dt, 1))
+    print(f"[bench] backward {dt * 1e3:.3f} ms for {base.n_frames} frames", file=sys.stderr, flush=True)
+    del job, out, grad_rgb, ws
+    # serving
+    pool = ScenePool(r.ctx, 256)
+    warm = Server(r.ctx, pool)
+    warm.run(poisson_trace(pool, 2000.0, 0.3, seed=99))
+    srv = Server(r.ctx, pool)
+    srv.layouts = warm.layouts
+    st = srv.run(poisson_trace(pool, 2000.0, args.serving_seconds, 0.5), warmup=0.5)
+    ex["serving"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    ex["serving"].update(rate_req_per_s=2000.0, budget_gb=64)
+    print(f"[bench] serving p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
+    del srv, warm, pool
+    # uneven batch: autotuned, one graph replay per step, vs one scene per launch
+    b3 = S.config3(3, 1024)
+    job3 = r.prepare(b3)
+    out3 = r.alloc_outputs(job3)
+    tuning, _ = autotune(r.ctx, job3.layout, job3.state, out3, job3.workspace)
+    stream = torch.cuda.Stream()
+    g = Graph(r.ctx, job3.layout, job3.state, out3, job3.workspace, stream)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            g.replay(stream)
+        dt3 = _timed(lambda: g.replay(stream), 20, torch)
+    g.close()
+    bytes3 = BYTES_PER_PIXEL * b3.total_pixels
+    plain = []
+    st3 = job3.state
+    po = b3.pixel_offset
+    for s in range(b3.n_scenes):
+        ob, oe = int(b3.scene_object_begin[s]), int(b3.scene_object_begin[s + 1])
+        lb, le = int(b3.scene_light_begin[s]), int(b3.scene_light_begin[s + 1])
+        f0, f1 = 3 * s, 3 * s + 3
+        sst = dict(object_pose=st3["object_pose"][ob:oe], object_seg=st3["object_seg"][ob:oe],
+                   object_visible=st3["object_visible"][ob:oe], albedo=st3["albedo"][ob:oe],
+                   roughness=st3["roughness"][ob:oe], specular=st3["specular"][ob:oe],
+                   light_vec=st3["light_vec"][lb:le], light_intensity=st3["light_intensity"][lb:le],
+                   view=st3["view"][f0:f1], intr=st3["intr"][f0:f1], near=st3["near"][f0:f1],
+                   exposure=st3["exposure"][f0:f1])
+        p0, p1 = int(po[f0]), int(po[f1])
+        sout = dict(rgb=out3["rgb"][3 * p0:3 * p1], depth=out3["depth"][p0:p1], normal=out3["normal"][3 * p0:3 * p1],
+                    seg=out3["seg"][p0:p1])
+        plain.append((Layout(r.ctx, b3.select_scenes([s])), sst, sout))
+    run_plain = lambda: [render_batch(r.ctx, lay, sst, sout, job3.workspace) for lay, sst, sout in plain]
+    run_plain()
+    dtp = _timed(run_plain, 3, torch)
+    ex["uneven_batch"] = dict(frames=b3.n_frames, pixels=b3.total_pixels, tuning=list(tuning),
+                              ms_per_step=round(dt3 * 1e3, 3), frames_per_s=round(b3.n_frames / dt3, 1),
+                              hbm_frac=round(bytes3 / dt3 / 1e9 / HBM_PEAK_GBS, 4),
+                              plain_frames_per_s=round(b3.n_frames / dtp, 1), batched_over_plain=round(dtp / dt3, 2))
+    print(f"[bench] uneven batch {dt3 * 1e3:.3f} ms/step (graph), plain {dtp * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    return ex
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +171,8 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the gradient, serving and uneven-batch parts")
+    ap.add_argument("--serving-seconds", type=float, default=2.0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
@@ -186,6 +273,9 @@ def main(argv=None):
         plain_fps = F * plain_steps / (time.perf_counter() - t0)
         extra["plain_form_frames_per_s"] = round(plain_fps, 1)
         extra["batched_over_plain"] = round(value / plain_fps, 2)
+
+    if not args.no_extras:
+        extra.update(measure_extras(args, r, S))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -45,7 +45,9 @@
  *
  * Thread safety: a context may be used from several threads if calls on the same
  * layout are serialized by the caller; calls on different layouts and streams may
- * run concurrently.
+ * run concurrently.  orrb_layout_set_tuning and orrb_layout_destroy rewrite or free
+ * device tables: no work that uses the layout may still be in flight.  The first
+ * orrb_shade_backward call on a layout uploads its adjoint tables synchronously.
  */
 #ifndef ORRB_H
 #define ORRB_H
@@ -201,6 +203,40 @@ typedef struct {                  /* destinations; rgb, depth, normal, seg may e
 orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
                               const orrb_cameras *cameras, const orrb_params *params, const orrb_outputs *out,
                               void *workspace, size_t workspace_bytes, void *stream);
+
+/* --------------------------------------------------------------------------------- */
+/* batched form: autotuning and graph replay                                          */
+/* --------------------------------------------------------------------------------- */
+
+/* Measure candidate tunings (frame/tiled path, tile size, bin capacity, persistent
+ * grid) by rendering this batch on `stream` a few times each with HIP events, and set
+ * the fastest on the layout (*chosen and *best_ms receive it; either may be NULL).
+ * Every tuning gives bit-identical outputs, so tuning changes speed only.  The
+ * workspace must hold orrb_layout_info.workspace_bytes_any.  `cache_path` (may be
+ * NULL) names a JSON-lines file: an entry for this device and batch structure is used
+ * without measuring; a new result is appended.  Synchronizes `stream`.  No work that
+ * uses the layout may be in flight on other streams. */
+orrb_status orrb_autotune(orrb_context *ctx, orrb_layout *layout, const orrb_scenes *scenes, const orrb_cameras *cameras,
+                          const orrb_params *params, const orrb_outputs *out, void *workspace, size_t workspace_bytes,
+                          void *stream, const char *cache_path, orrb_tuning *chosen, double *best_ms);
+
+typedef struct orrb_graph orrb_graph;
+
+/* Capture one orrb_render_batch with these exact buffers into a HIP graph and
+ * instantiate it.  Replays (orrb_graph_launch) render whatever the buffers hold at
+ * replay time, so a caller updates scene state, cameras and parameters in place and
+ * replays; the layout's tuning is frozen into the graph.  `stream` must not be the
+ * null stream (it is used for capture only).  The layout, buffers and workspace must
+ * outlive the graph. */
+orrb_status orrb_graph_create(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
+                              const orrb_cameras *cameras, const orrb_params *params, const orrb_outputs *out,
+                              void *workspace, size_t workspace_bytes, void *stream, orrb_graph **graph);
+
+/* Enqueue a replay of the captured render on `stream` (NULL: the null stream). */
+orrb_status orrb_graph_launch(orrb_graph *graph, void *stream);
+
+/* Destroy a graph (the caller must have synchronized its replays).  NULL is ignored. */
+void orrb_graph_destroy(orrb_graph *graph);
 
 /* --------------------------------------------------------------------------------- */
 /* shading adjoint (gradients with respect to the randomization parameters)           */

@@ -87,6 +87,12 @@ SIGNATURES = {
     "orrb_layout_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
     "orrb_render_batch": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params),
                                     C.POINTER(Outputs), P, C.c_size_t, P]),
+    "orrb_autotune": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params), C.POINTER(Outputs),
+                                P, C.c_size_t, P, C.c_char_p, C.POINTER(Tuning), C.POINTER(C.c_double)]),
+    "orrb_graph_create": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params),
+                                    C.POINTER(Outputs), P, C.c_size_t, P, C.POINTER(P)]),
+    "orrb_graph_launch": (C.c_int, [P, P]),
+    "orrb_graph_destroy": (None, [P]),
     "orrb_shade_backward": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params), P, P,
                                       C.POINTER(Grads), P, C.c_size_t, P]),
     "orrb_profile_enable": (C.c_int, [P, C.c_int]),

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/orrb.h"
+
 namespace orrb {
 
 constexpr int kWave = 64;
@@ -89,6 +91,19 @@ struct GradArgs {
 hipError_t launch_grad(const GradArgs &g, hipStream_t stream);
 int grad_tile_size();
 int grad_max_objects();
+
+}  // namespace orrb
+
+struct orrb_layout;
+struct orrb_context;
+
+namespace orrb {
+// host-runtime internals used by the autotuner and graph code (orrb_tune.cpp)
+orrb_status set_error(orrb_status st, const char *msg);
+uint64_t layout_signature(const orrb_layout *L);
+int context_device(const orrb_context *ctx);
+bool context_profiling(const orrb_context *ctx);
+void context_set_profiling(orrb_context *ctx, bool on);
 hipError_t launch_vertex(const RenderArgs &a, hipStream_t stream);
 hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu);
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream);

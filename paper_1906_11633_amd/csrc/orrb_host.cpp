@@ -68,6 +68,24 @@ struct DevBuf {
     }
 };
 
+// Several host tables packed into one device allocation (one malloc, one copy).
+struct Packed {
+    std::vector<char> host;
+    DevBuf dev;
+    size_t add(const void *src, size_t n) {
+        const size_t off = (host.size() + 255) & ~size_t(255);
+        host.resize(off + n);
+        if (n) memcpy(host.data() + off, src, n);
+        return off;
+    }
+    template <class T>
+    size_t add(const std::vector<T> &v) { return add(v.data(), sizeof(T) * v.size()); }
+    hipError_t upload() { return dev.upload(host.data(), host.size()); }
+    template <class T>
+    const T *at(size_t off) const { return (const T *)((const char *)dev.p + off); }
+    void clear() { host.clear(); }
+};
+
 struct ScopedDevice {
     int prev = -1;
     explicit ScopedDevice(int dev) {
@@ -146,7 +164,8 @@ struct orrb_layout {
     std::vector<int2> vitems, titems;
     std::vector<int32_t> fitems;
     std::vector<int32_t> light_type;
-    DevBuf d_frames, d_objs, d_vitems, d_titems, d_fitems, d_light_type;
+    Packed tab;  // frames, objs, vitems, titems, fitems, light_type
+    size_t o_frames = 0, o_objs = 0, o_vitems = 0, o_titems = 0, o_fitems = 0, o_light_type = 0;
     orrb_tuning tuning{32, 32, 256, 0, 0};
     // shading adjoint: every frame on the tiled-path vertex tables, gradient tiles
     std::vector<FrameInfo> frames_all;
@@ -154,10 +173,14 @@ struct orrb_layout {
     std::vector<int64_t> gitem_pbase;
     std::vector<int32_t> frame_item_begin, scene_frame_begin, scene_frames, obj_scene, obj_local, light_scene,
         light_local;
+    uint64_t signature = 0;  // hash of the batch structure (autotuner cache key)
     int64_t grad_partials = 0;
     int max_scene_objects = 0;
-    DevBuf d_frames_all, d_vitems_all, d_gitems, d_gitem_pbase, d_frame_item_begin, d_scene_frame_begin,
-        d_scene_frames, d_obj_scene, d_obj_local, d_light_scene, d_light_local;
+    bool grad_ready = false;  // tables uploaded on the first backward call
+    Packed gtab;
+    size_t g_frames_all = 0, g_vitems_all = 0, g_gitems = 0, g_gitem_pbase = 0, g_frame_item_begin = 0,
+           g_scene_frame_begin = 0, g_scene_frames = 0, g_obj_scene = 0, g_obj_local = 0, g_light_scene = 0,
+           g_light_local = 0;
 };
 
 // --------------------------------------------------------------------------------------
@@ -278,17 +301,21 @@ static void build_grad_tables(orrb_layout *L, const orrb_layout_desc *d) {
 
 static orrb_status upload_grad_tables(orrb_layout *L) {
     ScopedDevice sd(L->ctx->device);
-    HIP_TRY(L->d_frames_all.upload(L->frames_all.data(), sizeof(FrameInfo) * L->frames_all.size()));
-    HIP_TRY(L->d_vitems_all.upload(L->vitems_all.data(), sizeof(int2) * L->vitems_all.size()));
-    HIP_TRY(L->d_gitems.upload(L->gitems.data(), sizeof(int2) * L->gitems.size()));
-    HIP_TRY(L->d_gitem_pbase.upload(L->gitem_pbase.data(), sizeof(int64_t) * L->gitem_pbase.size()));
-    HIP_TRY(L->d_frame_item_begin.upload(L->frame_item_begin.data(), sizeof(int32_t) * L->frame_item_begin.size()));
-    HIP_TRY(L->d_scene_frame_begin.upload(L->scene_frame_begin.data(), sizeof(int32_t) * L->scene_frame_begin.size()));
-    HIP_TRY(L->d_scene_frames.upload(L->scene_frames.data(), sizeof(int32_t) * L->scene_frames.size()));
-    HIP_TRY(L->d_obj_scene.upload(L->obj_scene.data(), sizeof(int32_t) * L->obj_scene.size()));
-    HIP_TRY(L->d_obj_local.upload(L->obj_local.data(), sizeof(int32_t) * L->obj_local.size()));
-    HIP_TRY(L->d_light_scene.upload(L->light_scene.data(), sizeof(int32_t) * L->light_scene.size()));
-    HIP_TRY(L->d_light_local.upload(L->light_local.data(), sizeof(int32_t) * L->light_local.size()));
+    Packed &P = L->gtab;
+    P.clear();
+    L->g_frames_all = P.add(L->frames_all);
+    L->g_vitems_all = P.add(L->vitems_all);
+    L->g_gitems = P.add(L->gitems);
+    L->g_gitem_pbase = P.add(L->gitem_pbase);
+    L->g_frame_item_begin = P.add(L->frame_item_begin);
+    L->g_scene_frame_begin = P.add(L->scene_frame_begin);
+    L->g_scene_frames = P.add(L->scene_frames);
+    L->g_obj_scene = P.add(L->obj_scene);
+    L->g_obj_local = P.add(L->obj_local);
+    L->g_light_scene = P.add(L->light_scene);
+    L->g_light_local = P.add(L->light_local);
+    HIP_TRY(P.upload());
+    L->grad_ready = true;
     return ORRB_OK;
 }
 
@@ -299,14 +326,28 @@ static size_t grad_workspace(const orrb_layout *L) {
 
 static orrb_status upload_layout(orrb_layout *L) {
     ScopedDevice sd(L->ctx->device);
-    HIP_TRY(L->d_frames.upload(L->frames.data(), sizeof(FrameInfo) * L->frames.size()));
-    HIP_TRY(L->d_objs.upload(L->objs.data(), sizeof(ObjInfo) * L->objs.size()));
-    HIP_TRY(L->d_vitems.upload(L->vitems.data(), sizeof(int2) * L->vitems.size()));
-    HIP_TRY(L->d_titems.upload(L->titems.data(), sizeof(int2) * L->titems.size()));
-    HIP_TRY(L->d_fitems.upload(L->fitems.data(), sizeof(int32_t) * L->fitems.size()));
-    HIP_TRY(L->d_light_type.upload(L->light_type.data(), sizeof(int32_t) * L->light_type.size()));
+    Packed &P = L->tab;
+    P.clear();
+    L->o_frames = P.add(L->frames);
+    L->o_objs = P.add(L->objs);
+    L->o_vitems = P.add(L->vitems);
+    L->o_titems = P.add(L->titems);
+    L->o_fitems = P.add(L->fitems);
+    L->o_light_type = P.add(L->light_type);
+    HIP_TRY(P.upload());
     return ORRB_OK;
 }
+
+namespace orrb {
+orrb_status set_error(orrb_status st, const char *msg) {
+    g_last_error = msg;
+    return st;
+}
+uint64_t layout_signature(const orrb_layout *L) { return L->signature; }
+int context_device(const orrb_context *ctx) { return ctx->device; }
+bool context_profiling(const orrb_context *ctx) { return ctx->timer.enabled; }
+void context_set_profiling(orrb_context *ctx, bool on) { ctx->timer.enabled = on; }
+}  // namespace orrb
 
 // --------------------------------------------------------------------------------------
 // C ABI
@@ -315,8 +356,8 @@ static orrb_status upload_layout(orrb_layout *L) {
 static void fill_args(const orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
                       const orrb_params *par, RenderArgs *a) {
     memset(a, 0, sizeof(*a));
-    a->objs = (const ObjInfo *)L->d_objs.p;
-    a->light_type = (const int32_t *)L->d_light_type.p;
+    a->objs = L->tab.at<ObjInfo>(L->o_objs);
+    a->light_type = L->tab.at<int32_t>(L->o_light_type);
     a->mesh_pos = (const float4 *)ctx->d_pos.p;
     a->mesh_nrm = (const float4 *)ctx->d_nrm.p;
     a->mesh_tri = (const int4 *)ctx->d_tri.p;
@@ -528,8 +569,26 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
         return fail(ORRB_ERR_UNSUPPORTED, "too many tiles");
     }
     build_grad_tables(L, d);
+    {   // FNV-1a over the structure: frame sizes, scenes' mesh sizes and light counts
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&h](int64_t x) {
+            for (int b = 0; b < 8; ++b) {
+                h ^= (uint64_t)((x >> (8 * b)) & 0xff);
+                h *= 1099511628211ull;
+            }
+        };
+        mix(L->n_frames);
+        for (const FrameInfo &fi : L->frames) {
+            mix(fi.width);
+            mix(fi.height);
+            mix(fi.n_obj);
+            mix(fi.n_lights);
+            mix(L->scene_verts[fi.scene]);
+            mix(L->scene_tris[fi.scene]);
+        }
+        L->signature = h;
+    }
     orrb_status st = upload_layout(L);
-    if (st == ORRB_OK) st = upload_grad_tables(L);
     if (st != ORRB_OK) {
         delete L;
         return st;
@@ -598,13 +657,11 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
     if ((uintptr_t)workspace % 16 != 0) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace must be 16-byte aligned");
     RenderArgs a;
     fill_args(ctx, L, sc, cam, par, &a);
-    a.frames = (const FrameInfo *)L->d_frames.p;
-    a.objs = (const ObjInfo *)L->d_objs.p;
-    a.vitems = (const int2 *)L->d_vitems.p;
-    a.titems = (const int2 *)L->d_titems.p;
-    a.fitems = (const int32_t *)L->d_fitems.p;
+    a.frames = L->tab.at<FrameInfo>(L->o_frames);
+    a.vitems = L->tab.at<int2>(L->o_vitems);
+    a.titems = L->tab.at<int2>(L->o_titems);
+    a.fitems = L->tab.at<int32_t>(L->o_fitems);
     a.n_fitems = (int32_t)L->fitems.size();
-    a.light_type = (const int32_t *)L->d_light_type.p;
     a.n_vitems = (int32_t)L->vitems.size();
     a.n_titems = (int32_t)L->titems.size();
     a.tile_w = L->tuning.tile_w;
@@ -668,13 +725,17 @@ orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const o
     if (workspace_bytes < need)
         return fail(ORRB_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", workspace_bytes, need);
     if ((uintptr_t)workspace % 16 != 0) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace must be 16-byte aligned");
+    if (!L->grad_ready) {
+        const orrb_status st = upload_grad_tables(const_cast<orrb_layout *>(L));
+        if (st != ORRB_OK) return st;
+    }
     GradArgs g;
     memset(&g, 0, sizeof(g));
     fill_args(ctx, L, sc, cam, par, &g.r);
     const WsLayout w = ws_layout(L->all_vertex_instances, L->all_object_instances);
     char *ws = (char *)workspace;
-    g.r.frames = (const FrameInfo *)L->d_frames_all.p;
-    g.r.vitems = (const int2 *)L->d_vitems_all.p;
+    g.r.frames = L->gtab.at<FrameInfo>(L->g_frames_all);
+    g.r.vitems = L->gtab.at<int2>(L->g_vitems_all);
     g.r.n_vitems = (int32_t)L->vitems_all.size();
     g.r.vtx_pos = (int4 *)(ws + w.vtx_pos);
     g.r.obj_rot = (float4 *)(ws + w.obj_rot);
@@ -682,17 +743,17 @@ orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const o
     g.r.queue = (unsigned int *)(ws + w.queue);
     g.vis = (const unsigned long long *)vis;
     g.grad_rgb = grad_rgb;
-    g.gitems = (const int2 *)L->d_gitems.p;
-    g.gitem_pbase = (const int64_t *)L->d_gitem_pbase.p;
+    g.gitems = L->gtab.at<int2>(L->g_gitems);
+    g.gitem_pbase = L->gtab.at<int64_t>(L->g_gitem_pbase);
     g.n_gitems = (int32_t)L->gitems.size();
     g.partial = (double *)(ws + al256(w.total));
-    g.scene_frames = (const int32_t *)L->d_scene_frames.p;
-    g.scene_frame_begin = (const int32_t *)L->d_scene_frame_begin.p;
-    g.frame_item_begin = (const int32_t *)L->d_frame_item_begin.p;
-    g.obj_scene = (const int32_t *)L->d_obj_scene.p;
-    g.obj_local = (const int32_t *)L->d_obj_local.p;
-    g.light_scene = (const int32_t *)L->d_light_scene.p;
-    g.light_local = (const int32_t *)L->d_light_local.p;
+    g.scene_frames = L->gtab.at<int32_t>(L->g_scene_frames);
+    g.scene_frame_begin = L->gtab.at<int32_t>(L->g_scene_frame_begin);
+    g.frame_item_begin = L->gtab.at<int32_t>(L->g_frame_item_begin);
+    g.obj_scene = L->gtab.at<int32_t>(L->g_obj_scene);
+    g.obj_local = L->gtab.at<int32_t>(L->g_obj_local);
+    g.light_scene = L->gtab.at<int32_t>(L->g_light_scene);
+    g.light_local = L->gtab.at<int32_t>(L->g_light_local);
     g.g_albedo = gr->albedo;
     g.g_rough = gr->roughness;
     g.g_spec = gr->specular;

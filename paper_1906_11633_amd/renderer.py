@@ -196,6 +196,60 @@ def render_batch(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], o
                                       _ptr(workspace), int(workspace.numel()), C.c_void_p(st.cuda_stream)))
 
 
+def _structs(state, out):
+    s = state
+    sc = L.Scenes(_ptr(s["object_pose"]), _ptr(s["object_seg"]), _ptr(s["object_visible"]))
+    cam = L.Cameras(_ptr(s["view"]), _ptr(s["intr"]), _ptr(s["near"]))
+    par = L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
+                   _ptr(s["light_intensity"]), _ptr(s["exposure"]))
+    o = L.Outputs(_ptr(out.get("rgb")), _ptr(out.get("depth")), _ptr(out.get("normal")), _ptr(out.get("seg")),
+                  _ptr(out.get("tri_id")), _ptr(out.get("vis")))
+    return sc, cam, par, o
+
+
+def autotune(ctx: Context, layout: Layout, state, out, workspace, stream=None, cache_path=None):
+    """orrb_autotune: measure candidate tunings on this batch and keep the fastest.
+    Returns (tuning tuple, ms per render)."""
+    sc, cam, par, o = _structs(state, out)
+    st = stream if stream is not None else torch.cuda.current_stream(ctx.device)
+    t = L.Tuning()
+    ms = C.c_double()
+    L.check(ctx.lib.orrb_autotune(ctx.handle, layout.handle, C.byref(sc), C.byref(cam), C.byref(par), C.byref(o),
+                                  _ptr(workspace), int(workspace.numel()), C.c_void_p(st.cuda_stream),
+                                  None if cache_path is None else str(cache_path).encode(), C.byref(t), C.byref(ms)))
+    return t.as_tuple(), ms.value
+
+
+class Graph:
+    """orrb_graph_*: one render call captured with fixed buffers; replay() re-renders
+    whatever those buffers hold."""
+
+    def __init__(self, ctx: Context, layout: Layout, state, out, workspace, stream):
+        self.ctx = ctx
+        self._keep = (layout, state, out, workspace)
+        sc, cam, par, o = _structs(state, out)
+        h = C.c_void_p()
+        L.check(ctx.lib.orrb_graph_create(ctx.handle, layout.handle, C.byref(sc), C.byref(cam), C.byref(par),
+                                          C.byref(o), _ptr(workspace), int(workspace.numel()),
+                                          C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def replay(self, stream=None):
+        st = stream if stream is not None else torch.cuda.current_stream(self.ctx.device)
+        L.check(self.ctx.lib.orrb_graph_launch(self.handle, C.c_void_p(st.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.ctx.lib.orrb_graph_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def shade_backward(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], vis: torch.Tensor,
                    grad_rgb: torch.Tensor, workspace: Optional[torch.Tensor] = None, stream=None) -> Dict[str, torch.Tensor]:
     """orrb_shade_backward: gradients of the loss with respect to albedo [O,3],
