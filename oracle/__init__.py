@@ -54,7 +54,7 @@ def _load():
             inputs = [P] * 17 + [C.c_int32] + [P] * 8
             lib.oracle_render.argtypes = inputs + [P] * 7 + [C.c_int32]
             lib.oracle_render.restype = C.c_int
-            lib.oracle_shade_grad.argtypes = inputs + [C.c_int32, P, P, P, P, P, P, P, P, P, C.c_int32]
+            lib.oracle_shade_grad.argtypes = inputs + [C.c_int32, P, P, P, P, P, P, P, P, P, P, C.c_int32]
             lib.oracle_shade_grad.restype = C.c_int
             _lib = lib
     return _lib
@@ -143,16 +143,28 @@ def render(batch, threads: int = 0) -> dict:
     return out
 
 
-def shade_grad(batch, target_rgb, pixel_weight=None, threads: int = 0):
+def shade_grad(batch, target_rgb=None, pixel_weight=None, threads: int = 0, dl_drgb=None):
     """FP64 loss sum w_px (rgb - target)^2 and its gradient over the fixed visibility.
+
+    With ``dl_drgb`` (planar like rgb, [3 * total_pixels]) the loss is the linear
+    sum w_px dl_drgb . rgb instead and ``target_rgb`` is ignored.
 
     Returns (loss, dict(albedo [O,3], roughness [O], specular [O], light_pos [L,3],
     light_intensity [L], exposure [F]))."""
     pk = _pack(batch)
     P = pk.total_pixels
-    target = np.ascontiguousarray(target_rgb, np.float64).reshape(-1)
-    if target.shape[0] != 3 * P:
-        raise ValueError("target must hold 3 * total_pixels values")
+    if dl_drgb is not None:
+        upstream = np.ascontiguousarray(dl_drgb, np.float64).reshape(-1)
+        if upstream.shape[0] != 3 * P:
+            raise ValueError("dl_drgb must hold 3 * total_pixels values")
+        target = None
+    else:
+        upstream = None
+        if target_rgb is None:
+            raise ValueError("target_rgb or dl_drgb is required")
+        target = np.ascontiguousarray(target_rgb, np.float64).reshape(-1)
+        if target.shape[0] != 3 * P:
+            raise ValueError("target must hold 3 * total_pixels values")
     wmask = None if pixel_weight is None else np.ascontiguousarray(pixel_weight, np.uint8).reshape(-1)
     if wmask is not None and wmask.shape[0] != P:
         raise ValueError("pixel_weight must hold total_pixels values")
@@ -161,8 +173,8 @@ def shade_grad(batch, target_rgb, pixel_weight=None, threads: int = 0):
     g = dict(albedo=np.zeros((O, 3)), roughness=np.zeros(O), specular=np.zeros(O),
              light_pos=np.zeros((L, 3)), light_intensity=np.zeros(L), exposure=np.zeros(pk.n_frames))
     loss = np.zeros(1)
-    rc = _load().oracle_shade_grad(*pk.args(), pk.n_scenes, _ptr(target), _ptr(wmask), _ptr(loss),
-                                   _ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]),
+    rc = _load().oracle_shade_grad(*pk.args(), pk.n_scenes, _ptr(target), _ptr(wmask), _ptr(upstream),
+                                   _ptr(loss), _ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]),
                                    _ptr(g["light_pos"]), _ptr(g["light_intensity"]), _ptr(g["exposure"]),
                                    int(threads))
     if rc != 0:

@@ -471,10 +471,13 @@ int oracle_render(INPUT_ARGS, double *rgb, double *depth, double *normal, int32_
  * analytic gradient over the fixed visibility with respect to per-object albedo (3),
  * roughness and specular, per-light position (world, 3) and intensity, and per-frame
  * exposure.  w_px is pixel_weight[px] (0/1, NULL = all 1).  Gradients are overwritten.
+ * When dl_drgb is not NULL the loss is linear instead, L = sum w_px dl_drgb . rgb
+ * (planar like rgb, target ignored): the adjoint is then that of a fixed upstream
+ * gradient, which is what a backward pass receives from the layers above it.
  * Scenes are processed in parallel; within a scene, frames and pixels are summed in
  * order, so the result is deterministic. */
 int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const uint8_t *pixel_weight,
-                      double *loss_out, double *g_albedo, double *g_rough, double *g_spec, double *g_lightpos,
+                      const double *dl_drgb, double *loss_out, double *g_albedo, double *g_rough, double *g_spec, double *g_lightpos,
                       double *g_intensity, double *g_exposure, int32_t n_threads) {
     FILL_INPUTS(in);
     int err = 0;
@@ -512,7 +515,8 @@ int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const 
                     const Pix *q = fw.pix + p;
                     if (pixel_weight && !pixel_weight[po + p]) continue;
                     if (q->tri < 0) { /* background renders 0: constant loss, no gradient */
-                        for (int c = 0; c < 3; c++) scene_loss[s] += target[3 * po + c * HW + p] * target[3 * po + c * HW + p];
+                        if (!dl_drgb)
+                            for (int c = 0; c < 3; c++) scene_loss[s] += target[3 * po + c * HW + p] * target[3 * po + c * HW + p];
                         continue;
                     }
                     Frag fr;
@@ -529,9 +533,14 @@ int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const 
                     double g[3], G = 0;
                     for (int c = 0; c < 3; c++) {
                         double rgbc = e * U[c];
-                        double d = rgbc - target[3 * po + c * HW + p];
-                        scene_loss[s] += d * d;
-                        g[c] = 2.0 * d;
+                        if (dl_drgb) {
+                            g[c] = dl_drgb[3 * po + c * HW + p];
+                            scene_loss[s] += g[c] * rgbc;
+                        } else {
+                            double d = rgbc - target[3 * po + c * HW + p];
+                            scene_loss[s] += d * d;
+                            g[c] = 2.0 * d;
+                        }
                         G += g[c];
                     }
                     /* exposure */

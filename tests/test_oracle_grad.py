@@ -116,3 +116,38 @@ def test_pixel_weight_mask_and_determinism():
     # the loss is the plain sum of squared errors over all pixels and channels
     out = oracle.render(b)
     np.testing.assert_allclose(L1, ((out["rgb"] - tgt) ** 2).sum(), rtol=1e-12)
+
+
+def _linear_fd(b, c, mask, name, idx, h):
+    """Central difference of L = sum w c . rgb from two forward renders (no adjoint
+    code involved)."""
+    w3 = np.concatenate([np.tile(mask[b.pixel_offset[f]:b.pixel_offset[f + 1]], 3)
+                         for f in range(b.n_frames)]).astype(np.float64)
+    lp = (c * w3 * oracle.render(fd.perturbed(b, name, idx, h))["rgb"]).sum()
+    lm = (c * w3 * oracle.render(fd.perturbed(b, name, idx, -h))["rgb"]).sum()
+    return (lp - lm) / (2 * h)
+
+
+def test_upstream_gradient_mode():
+    """With a fixed upstream gradient c the loss is sum w c . rgb: its value is that
+    sum over the forward render, and its gradient matches central differences of
+    that sum; with c = 2 (rgb - target) it equals the squared-error gradient."""
+    b, tgt = _small_problem(res=32)
+    out = oracle.render(b)
+    mask = fd.smooth_mask(b, out)
+    c = np.random.default_rng(7).uniform(-1, 1, 3 * b.total_pixels)
+    L, g = oracle.shade_grad(b, dl_drgb=c, pixel_weight=mask)
+    w3 = np.concatenate([np.tile(mask[b.pixel_offset[f]:b.pixel_offset[f + 1]], 3)
+                         for f in range(b.n_frames)]).astype(np.float64)
+    np.testing.assert_allclose(L, (c * w3 * out["rgb"]).sum(), rtol=1e-12)
+    rng = np.random.default_rng(1)
+    for name in PARAMS:
+        flat = g[name].reshape(-1)
+        cand = np.nonzero(np.abs(flat) >= 1e-3 * np.abs(flat).max())[0]
+        for idx in rng.choice(cand, size=min(2, cand.size), replace=False):
+            d = _linear_fd(b, c, mask, name, idx, 1e-4)
+            assert abs(flat[idx] - d) <= 1e-6 * abs(d) + 1e-9 * np.abs(flat).max(), (name, idx, flat[idx], d)
+    _, gq = oracle.shade_grad(b, tgt)
+    _, gl = oracle.shade_grad(b, dl_drgb=2.0 * (out["rgb"] - tgt))
+    for k in PARAMS:
+        np.testing.assert_allclose(gl[k], gq[k], rtol=1e-12, atol=1e-15 * np.abs(gq[k]).max())
