@@ -173,6 +173,8 @@ def main(argv=None):
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient, serving and uneven-batch parts")
     ap.add_argument("--serving-seconds", type=float, default=2.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="only run a plain device copy of this many MiB 5 times (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
@@ -188,6 +190,15 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "launches": 5}), flush=True)
+        return 0
     t_gen = time.perf_counter()
     batch = S.config2(2, args.scenes, args.res)
     print(f"[bench] generated {batch.n_frames} frames in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
@@ -283,6 +294,12 @@ def main(argv=None):
         cpu = cpu_baseline(lambda n: S.config2(2, n, args.res), args.scenes, args.cpu_seconds, threads)
         cpu["value"] = round(cpu["value"], 3)
 
+    try:
+        paper = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_throughput.json")))
+        extra["paper_context"] = dict(images_per_s_1gpu=paper["table2_gpu_scaling"]["1"], hardware="1x V100 + 96 vCPU",
+                                      output="200x200 RGB8 only, Unity/OpenGL", source=paper["source"])
+    except (OSError, ValueError, KeyError):
+        pass
     line = {
         "metric": METRIC,
         "value": round(value, 1),

@@ -440,7 +440,10 @@ orrb_status orrb_add_mesh(orrb_context *ctx, const float *pos, const float *nrm,
     const size_t v0 = ctx->pos.size(), t0 = ctx->tri.size();
     for (int64_t v = 0; v < n_verts; ++v) {
         ctx->pos.push_back(make_float4(pos[3 * v], pos[3 * v + 1], pos[3 * v + 2], 0.f));
-        ctx->nrm.push_back(make_float4(nrm[3 * v], nrm[3 * v + 1], nrm[3 * v + 2], 0.f));
+        // stored unit length: shading interpolates object-space normals, then rotates
+        const double nx = nrm[3 * v], ny = nrm[3 * v + 1], nz = nrm[3 * v + 2];
+        const double inv = 1.0 / std::sqrt(nx * nx + ny * ny + nz * nz);
+        ctx->nrm.push_back(make_float4((float)(nx * inv), (float)(ny * inv), (float)(nz * inv), 0.f));
     }
     for (int64_t t = 0; t < n_tris; ++t) ctx->tri.push_back(make_int4(idx[3 * t], idx[3 * t + 1], idx[3 * t + 2], 0));
     ScopedDevice sd(ctx->device);

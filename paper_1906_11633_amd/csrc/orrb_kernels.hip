@@ -397,6 +397,7 @@ constexpr int kFOMax = 64;          // scene objects
 constexpr int kFTile = 16;          // wave tile edge (pixels)
 constexpr int kFTilesMax = 256;     // frames up to 256 x 256
 constexpr int kFBinMax = 16384;     // (tile, triangle) bin entries
+constexpr int kFSurvMax = 8192;     // survivors remembered between set-up and scatter
 constexpr int kInvalidX = (int)0x80000000;
 
 struct FrameLds {
@@ -404,6 +405,7 @@ struct FrameLds {
     float iw[kFVMax];
     union {
         double M[kFOMax][12];                         // vertex phase
+        unsigned int surv[kFSurvMax];                 // set-up -> scatter: (tri << 16) | tile range
         unsigned long long vis[kFW][kFTile * kFTile];  // tile phase
     } u;
     unsigned short bin[kFBinMax];
@@ -413,13 +415,13 @@ struct FrameLds {
     Material o_mat[kFOMax];
     float4 light[kMaxLights];
     int light_type[kMaxLights];
-    int misc[8];  // [0] next tile, [1] bin overflow, [2] total entries
+    int misc[8];  // [0] next tile, [1] bin overflow, [2] total entries, [3] survivors
 };
 static_assert(sizeof(FrameLds) <= 160 * 1024, "frame LDS exceeds 160 KB");
 
 bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height) {
-    const int tiles = ((width + kFTile - 1) / kFTile) * ((height + kFTile - 1) / kFTile);
-    return n_verts <= kFVMax && n_obj <= kFOMax && n_tris < 65536 && tiles <= kFTilesMax;
+    // <= 16 x 16 tiles: a tile range packs into 4-bit fields
+    return n_verts <= kFVMax && n_obj <= kFOMax && n_tris < 65536 && width <= 16 * kFTile && height <= 16 * kFTile;
 }
 
 // Set-up of scene triangle t: front-facing, valid, with pixel centres in
@@ -522,12 +524,26 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     }
     __syncthreads();
 
-    // ---- phase 2: set-up and per-tile counts ----
-    for (int t = tid; t < n_tris; t += kFT) {
+    // ---- phase 2: set-up, per-tile counts, survivor list ----
+    for (int base = 0; base < n_tris; base += kFT) {
+        const int t = base + tid;
         TriSetup T;
-        if (!frame_setup(a, S, n_obj, t, 0, 0, W - 1, H - 1, T)) continue;
-        for (int ty = T.j0 >> 4; ty <= (T.j1 >> 4); ++ty)
-            for (int tx = T.i0 >> 4; tx <= (T.i1 >> 4); ++tx) atomicAdd(&S.cnt[ty * ntx + tx], 1);
+        const bool keep = t < n_tris && frame_setup(a, S, n_obj, t, 0, 0, W - 1, H - 1, T);
+        unsigned entry = 0;
+        if (keep) {
+            const int tx0 = T.i0 >> 4, tx1 = T.i1 >> 4, ty0 = T.j0 >> 4, ty1 = T.j1 >> 4;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&S.cnt[ty * ntx + tx], 1);
+            entry = ((unsigned)t << 16) | (unsigned)(tx0 | (tx1 << 4) | (ty0 << 8) | (ty1 << 12));
+        }
+        const unsigned long long m = __ballot(keep);
+        int wb = 0;
+        if (lane == 0 && m) wb = atomicAdd(&S.misc[3], __popcll(m));
+        wb = __shfl(wb, 0);
+        if (keep) {
+            const int slot = wb + lanes_below(m);
+            if (slot < kFSurvMax) S.u.surv[slot] = entry;
+        }
     }
     __syncthreads();
     if (wave == 0) {  // exclusive scan of n_tiles <= 256 counts, 4 per lane
@@ -564,7 +580,15 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     const bool overflow = S.misc[1] != 0;
 
     // ---- phase 3: scatter triangle IDs into the tile bins ----
-    if (!overflow) {
+    const int n_surv = S.misc[3];
+    if (!overflow && n_surv <= kFSurvMax) {
+        for (int k = tid; k < n_surv; k += kFT) {
+            const unsigned e = S.u.surv[k];
+            const int tx0 = e & 15, tx1 = (e >> 4) & 15, ty0 = (e >> 8) & 15, ty1 = (e >> 12) & 15;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)(e >> 16);
+        }
+    } else if (!overflow) {  // too many survivors to remember: set them up again
         for (int t = tid; t < n_tris; t += kFT) {
             TriSetup T;
             if (!frame_setup(a, S, n_obj, t, 0, 0, W - 1, H - 1, T)) continue;

@@ -133,11 +133,13 @@ ORRB_INLINE int tri_flags(int xa, int ya, int xb, int yb, int xc, int yc) {
            extent_flag(xa, ya, xb, yb, xc, yc);
 }
 
-// Perspective-correct eye depth of a covered fragment: z = A / sum_k E_k / w_k.
+// Perspective-correct eye depth of a covered fragment: z = A / sum_k E_k / w_k.  All
+// terms are non-negative, so the only error is rounding (< 3e-7 relative with the
+// hardware reciprocal).
 ORRB_INLINE float fragment_depth(const Edges &e, float iwa, float iwb, float iwc, float area) {
 #pragma clang fp contract(off)
     const float T = fmaf(e.e0, iwa, fmaf(e.e1, iwb, e.e2 * iwc));
-    return area / T;
+    return area * __builtin_amdgcn_rcpf(T);
 }
 
 ORRB_INLINE unsigned long long vis_key(float z, int tri) {
@@ -186,7 +188,7 @@ ORRB_INLINE float3 rotate_normal(const float *R, float4 q) {
 }
 
 // Shade the covered pixel (i, j) at eye depth z of the positive-area triangle a, b, c:
-// perspective-correct smooth normal from the object-space vertex normals rotated by R,
+// perspective-correct smooth normal from the unit object-space vertex normals and R,
 // then exposure * sum over lights of A * max(0, n.l) * (albedo + k_s * max(0, n.h)^m).
 ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc, float iwa, float iwb, float iwc,
                                  float4 na4, float4 nb4, float4 nc4, const float *R, int i, int j, float z,
@@ -195,15 +197,16 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
     const Edges e = edge_eval(xa, ya, xb, yb, xc, yc, (i << 8) + 128, (j << 8) + 128, extent_flag(xa, ya, xb, yb, xc, yc));
     // perspective-correct weights are proportional to E_k / w_k
     const float t0 = e.e0 * iwa, t1 = e.e1 * iwb, t2 = e.e2 * iwc;
-    const float3 na = rotate_normal(R, na4), nb = rotate_normal(R, nb4), nc = rotate_normal(R, nc4);
-    float3 n = f3(fmaf(t0, na.x, fmaf(t1, nb.x, t2 * nc.x)), fmaf(t0, na.y, fmaf(t1, nb.y, t2 * nc.y)),
-                  fmaf(t0, na.z, fmaf(t1, nb.z, t2 * nc.z)));
-    const float ninv = rsqrtf(dot3(n, n));
-    n = f3(n.x * ninv, n.y * ninv, n.z * ninv);
+    // R = s * Rotation (rigid + uniform scale) and unit object-space vertex normals, so
+    // normalize(sum t_k normalize(R n_k)) = normalize(R sum t_k n_k): interpolate in
+    // object space, rotate once, normalize once.
+    const float4 no = make_float4(fmaf(t0, na4.x, fmaf(t1, nb4.x, t2 * nc4.x)), fmaf(t0, na4.y, fmaf(t1, nb4.y, t2 * nc4.y)),
+                                  fmaf(t0, na4.z, fmaf(t1, nb4.z, t2 * nc4.z)), 0.f);
+    const float3 n = rotate_normal(R, no);
     const float3 pp = f3(z * (((float)i + 0.5f - cam.cx) * cam.ifx), -z * (((float)j + 0.5f - cam.cy) * cam.ify), -z);
     const float pinv = rsqrtf(dot3(pp, pp));
     const float3 v = f3(-pp.x * pinv, -pp.y * pinv, -pp.z * pinv);
-    const float mexp = 2.0f / (m.rough * m.rough) - 2.0f;
+    const float mexp = 2.0f * __builtin_amdgcn_rcpf(m.rough * m.rough) - 2.0f;
     float r0 = 0.f, r1 = 0.f, r2 = 0.f;
     for (int l = 0; l < nl; ++l) {
         const float4 Lq = light[l];
@@ -214,7 +217,7 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
             const float D = dot3(d, d);
             const float dinv = rsqrtf(D);
             ld = f3(d.x * dinv, d.y * dinv, d.z * dinv);
-            A = Lq.w / fmaxf(D, 1e-4f);
+            A = Lq.w * __builtin_amdgcn_rcpf(fmaxf(D, 1e-4f));
         } else {
             ld = f3(Lq.x, Lq.y, Lq.z);
             A = Lq.w;

@@ -85,3 +85,12 @@ def test_null_arguments_rejected(lib):
     assert lib.orrb_layout_info_get(None, None) == 1
     lib.orrb_destroy(None)
     lib.orrb_layout_destroy(None)
+
+
+def test_paper_context_fixture():
+    """The paper's printed throughput (Sec. 5, Tables 2-3) used as bench context."""
+    import json
+    d = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_throughput.json")))
+    assert d["table2_gpu_scaling"] == {"1": 1342, "2": 2870, "3": 3395, "4": 3514}
+    t3 = [d["table3_render_servers_on_8_gpus"][k] for k in sorted(d["table3_render_servers_on_8_gpus"], key=int)]
+    assert t3 == sorted(t3) and t3[0] == 736 and t3[-1] == 3438
