@@ -29,11 +29,16 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PIXEL = 32  # rgb 12 + depth 4 + normal 12 + seg 4
 METRIC = "randomized 4-channel 200x200 frames/sec on 1 MI355X; shading-grad/sec; p99 ms"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_frame_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1906_11633_amd", "csrc", "orrb_kernels.hip")
+# the frame kernel's source: its file and the headers it includes
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1906_11633_amd", "csrc", f)
+               for f in ("orrb_kernels.hip", "orrb_primitives.h", "orrb_device.h")]
 
 
 def kernel_source_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():

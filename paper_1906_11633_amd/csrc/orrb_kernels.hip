@@ -8,7 +8,7 @@
 // renders a whole frame with no intermediate data in global memory:
 //   1. transform and snap every vertex of the scene (FP64) into LDS;
 //   2. set up every triangle once (exact area, back-face and range cull) and count, per
-//      16x16 screen tile, the triangles whose pixel-centre range touches it;
+//      64x4 screen tile, the triangles whose pixel-centre range touches it;
 //   3. scan the counts and scatter 16-bit triangle IDs into per-tile LDS bins;
 //   4. each wave takes tiles from an LDS counter, rasterizes the tile's bin into its own
 //      256-key LDS visibility tile (ds_min_u64), then shades and writes the tile.
@@ -394,10 +394,13 @@ constexpr int kFT = 1024;           // threads of a frame workgroup
 constexpr int kFW = kFT / kWave;    // 16 waves
 constexpr int kFVMax = 7040;        // scene vertices held in LDS
 constexpr int kFOMax = 64;          // scene objects
-constexpr int kFTile = 16;          // wave tile edge (pixels)
-constexpr int kFTilesMax = 256;     // frames up to 256 x 256
+constexpr int kFTileW = 64;         // wave tile: 64 x 4 pixels, so that a wave's store
+constexpr int kFTileH = 4;          // instruction writes 256-byte row segments
+constexpr int kFTilesMax = 256;     // frames up to 256 x 256 (4 x 64 tiles)
 constexpr int kFBinMax = 16384;     // (tile, triangle) bin entries
 constexpr int kFSurvMax = 8192;     // survivors remembered between set-up and scatter
+constexpr int kFHint = 64;          // elements per object-lookup hint
+constexpr int kFStoreWaves = 4;     // waves that start with the tiles no triangle touches
 constexpr int kInvalidX = (int)0x80000000;
 
 struct FrameLds {
@@ -406,39 +409,53 @@ struct FrameLds {
     union {
         double M[kFOMax][12];                         // vertex phase
         unsigned int surv[kFSurvMax];                 // set-up -> scatter: (tri << 16) | tile range
-        unsigned long long vis[kFW][kFTile * kFTile];  // tile phase
+        unsigned long long vis[kFW][kFTileW * kFTileH];  // tile phase
     } u;
     unsigned short bin[kFBinMax];
     int cnt[kFTilesMax + 1], off[kFTilesMax + 1];
+    unsigned char order[kFTilesMax];                 // tile order: tiles with bin entries first
+    unsigned char cov[kFW][kFTileW * kFTileH];       // per wave: covered pixels of its tile
+    unsigned char tri_hint[65536 / kFHint];          // object of triangle 64 b
+    unsigned char vtx_hint[(kFVMax + kFHint - 1) / kFHint];
     int o_tbase[kFOMax], o_vbase[kFOMax], o_mtb[kFOMax], o_mvb[kFOMax], o_nt[kFOMax], o_seg[kFOMax], o_vis[kFOMax];
     float o_R[kFOMax][9];
     Material o_mat[kFOMax];
     float4 light[kMaxLights];
     int light_type[kMaxLights];
-    int misc[8];  // [0] next tile, [1] bin overflow, [2] total entries, [3] survivors
+    int misc[8];  // [0] next tile with entries, [1] bin overflow, [2] total entries, [3] survivors,
+                  // [4] tiles with entries, [5] next tile without entries
 };
 static_assert(sizeof(FrameLds) <= 160 * 1024, "frame LDS exceeds 160 KB");
 
 bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height) {
-    // <= 16 x 16 tiles: a tile range packs into 4-bit fields
-    return n_verts <= kFVMax && n_obj <= kFOMax && n_tris < 65536 && width <= 16 * kFTile && height <= 16 * kFTile;
+    // <= 4 x 64 tiles: a tile range packs into 2-bit x and 6-bit y fields
+    return n_verts <= kFVMax && n_obj <= kFOMax && n_tris < 65536 && width <= 4 * kFTileW && height <= 64 * kFTileH;
 }
 
-// Set-up of scene triangle t: front-facing, valid, with pixel centres in
-// [cx0, cx1] x [cy0, cy1].  Vertices in positive-area order a, b, c.
+// Object owning element x (a scene triangle or vertex): start from the hint of x's
+// 64-element block and step forward over the objects that begin at or before x.
+ORRB_INLINE int slot_hint(const int *base, int n, const unsigned char *hint, int x) {
+    int k = hint[x / kFHint];
+    while (k + 1 < n && base[k + 1] <= x) ++k;
+    return k;
+}
+
+// Scene triangle t of object k and its mesh triangle (mesh-local vertex indices).
+ORRB_INLINE int4 frame_tri(const RenderArgs &a, const FrameLds &S, int k, int t) {
+    return a.mesh_tri[S.o_mtb[k] + (t - S.o_tbase[k])];
+}
+
+// Set-up of scene triangle t (object k, mesh triangle tri): front-facing, valid, with
+// pixel centres in [cx0, cx1] x [cy0, cy1].  Vertices in positive-area order a, b, c.
 struct TriSetup {
     int xa, ya, xb, yb, xc, yc;
     int i0, j0, i1, j1;  // pixel-centre range inside the clip box
     int va, vb, vc;      // LDS vertex indices
-    int obj;
     long long area;
 };
 
-ORRB_INLINE bool frame_setup(const RenderArgs &a, const FrameLds &S, int n_obj, int t, int cx0, int cy0, int cx1, int cy1,
-                             TriSetup &T) {
-    const int k = find_slot(S.o_tbase, n_obj, t);
+ORRB_INLINE bool frame_setup(const FrameLds &S, int k, int4 tri, int cx0, int cy0, int cx1, int cy1, TriSetup &T) {
     if (!S.o_vis[k]) return false;
-    const int4 tri = a.mesh_tri[S.o_mtb[k] + (t - S.o_tbase[k])];
     const int vb = S.o_vbase[k];
     const int i0v = vb + tri.x, i1v = vb + tri.y, i2v = vb + tri.z;
     const int x0 = S.X[i0v], x1 = S.X[i1v], x2 = S.X[i2v];
@@ -455,9 +472,100 @@ ORRB_INLINE bool frame_setup(const RenderArgs &a, const FrameLds &S, int n_obj, 
     if (A >= 0) return false;
     T.xa = x0; T.ya = y0; T.xb = x2; T.yb = y2; T.xc = x1; T.yc = y1;
     T.va = i0v; T.vb = i2v; T.vc = i1v;
-    T.obj = k;
     T.area = -A;
     return true;
+}
+
+// Snap vertex v (object k, object-space position p) into the LDS vertex arrays.
+ORRB_INLINE void frame_vertex(FrameLds &S, int v, int k, float4 p, double fx, double fy, double cx, double cy,
+                              double nearp) {
+    int X = kInvalidX, Y = 0;
+    float iw = 0.f;
+    if (S.o_vis[k]) {
+        double M[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) M[q] = S.u.M[k][q];
+        const Snapped s = snap_vertex(M, p, fx, fy, cx, cy, nearp);
+        if (s.valid) {
+            X = s.X;
+            Y = s.Y;
+            iw = s.iw;
+        }
+    }
+    S.X[v] = X;
+    S.Y[v] = Y;
+    S.iw[v] = iw;
+}
+
+// Per-tile counts and the survivor entry of a set-up triangle.
+ORRB_INLINE unsigned frame_count(FrameLds &S, int t, const TriSetup &T, int ntx) {
+    const int tx0 = T.i0 / kFTileW, tx1 = T.i1 / kFTileW, ty0 = T.j0 / kFTileH, ty1 = T.j1 / kFTileH;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&S.cnt[ty * ntx + tx], 1);
+    return ((unsigned)t << 16) | (unsigned)(tx0 | (tx1 << 2) | (ty0 << 4) | (ty1 << 10));
+}
+
+ORRB_INLINE void frame_append(FrameLds &S, bool keep, unsigned entry, int lane) {
+    const unsigned long long m = __ballot(keep);
+    int wb = 0;
+    if (lane == 0 && m) wb = atomicAdd(&S.misc[3], __popcll(m));
+    wb = __shfl(wb, 0);
+    if (keep) {
+        const int slot = wb + lanes_below(m);
+        if (slot < kFSurvMax) S.u.surv[slot] = entry;
+    }
+}
+
+// Four horizontally adjacent pixels of one plane: one 16-byte store when the group is
+// whole and 16-byte aligned, else one store per pixel inside the frame.  Plain stores:
+// the L2 merges a tile's 256-byte row segments with its neighbours' into whole lines,
+// which non-temporal stores forgo.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+ORRB_INLINE void store4f(float *p, const float *v, bool vec, int n) {
+    if (vec) {
+        *reinterpret_cast<f32x4 *>(p) = f32x4{v[0], v[1], v[2], v[3]};
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < n) p[q] = v[q];
+    }
+}
+
+ORRB_INLINE void store4i(int *p, const int *v, bool vec, int n) {
+    if (vec) {
+        *reinterpret_cast<i32x4 *>(p) = i32x4{v[0], v[1], v[2], v[3]};
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < n) p[q] = v[q];
+    }
+}
+
+// Background (no fragment) for four adjacent pixels: rgb, depth, normal 0, seg and
+// tri_id -1, vis the empty key.
+ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, int64_t pix, bool vec, int n) {
+    const float zf[4] = {0.f, 0.f, 0.f, 0.f};
+    const int mi[4] = {-1, -1, -1, -1};
+    if (a.out_rgb) {
+        store4f(a.out_rgb + 3 * po + pix, zf, vec, n);
+        store4f(a.out_rgb + 3 * po + HW + pix, zf, vec, n);
+        store4f(a.out_rgb + 3 * po + 2 * HW + pix, zf, vec, n);
+    }
+    if (a.out_depth) store4f(a.out_depth + po + pix, zf, vec, n);
+    if (a.out_normal) {
+        store4f(a.out_normal + 3 * po + pix, zf, vec, n);
+        store4f(a.out_normal + 3 * po + HW + pix, zf, vec, n);
+        store4f(a.out_normal + 3 * po + 2 * HW + pix, zf, vec, n);
+    }
+    if (a.out_seg) store4i(a.out_seg + po + pix, mi, vec, n);
+    if (a.out_tri) store4i(a.out_tri + po + pix, mi, vec, n);
+    if (a.out_vis) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < n) a.out_vis[po + pix + q] = kEmptyKey;
+    }
 }
 
 __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
@@ -466,7 +574,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     const FrameInfo fi = a.frames[f];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const int n_obj = fi.n_obj, W = fi.width, H = fi.height;
-    const int ntx = (W + kFTile - 1) / kFTile, nty = (H + kFTile - 1) / kFTile, n_tiles = ntx * nty;
+    const int ntx = (W + kFTileW - 1) / kFTileW, nty = (H + kFTileH - 1) / kFTileH, n_tiles = ntx * nty;
 
     // ---- phase 0: per-object tables, matrices, lights ----
     if (tid < n_obj) {
@@ -494,86 +602,114 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     }
     for (int t = tid; t <= n_tiles; t += kFT) S.cnt[t] = 0;
     if (tid < 8) S.misc[tid] = 0;
+    const int n_verts = n_obj > 0 ? a.objs[fi.obj_begin + n_obj - 1].scene_vbase + a.objs[fi.obj_begin + n_obj - 1].n_verts : 0;
+    __syncthreads();
+    const int n_tris = n_obj > 0 ? S.o_tbase[n_obj - 1] + S.o_nt[n_obj - 1] : 0;
+    for (int b = tid; b * kFHint < n_tris; b += kFT) S.tri_hint[b] = (unsigned char)find_slot(S.o_tbase, n_obj, b * kFHint);
+    for (int b = tid; b * kFHint < n_verts; b += kFT) S.vtx_hint[b] = (unsigned char)find_slot(S.o_vbase, n_obj, b * kFHint);
     __syncthreads();
 
-    // ---- phase 1: vertices ----
-    const int n_verts = n_obj > 0 ? S.o_vbase[n_obj - 1] + a.objs[fi.obj_begin + n_obj - 1].n_verts : 0;
-    const int n_tris = n_obj > 0 ? S.o_tbase[n_obj - 1] + S.o_nt[n_obj - 1] : 0;
+    // ---- phase 1: vertices, two per thread per pass; the next pass's positions are
+    // loaded before the current pass is transformed, hiding the load latency ----
     {
         const float *K = a.intr + 4 * (int64_t)f;
         const double fx = K[0], fy = K[1], cx = K[2], cy = K[3], nearp = a.near_plane[f];
-        for (int v = tid; v < n_verts; v += kFT) {
-            const int k = find_slot(S.o_vbase, n_obj, v);
-            int X = kInvalidX, Y = 0;
-            float iw = 0.f;
-            if (S.o_vis[k]) {
-                double M[12];
-#pragma unroll
-                for (int q = 0; q < 12; ++q) M[q] = S.u.M[k][q];
-                const Snapped s = snap_vertex(M, a.mesh_pos[S.o_mvb[k] + (v - S.o_vbase[k])], fx, fy, cx, cy, nearp);
-                if (s.valid) {
-                    X = s.X;
-                    Y = s.Y;
-                    iw = s.iw;
-                }
+        // vertex v (clamped to the last one) of object k: its mesh position
+        auto vload = [&](int v, int &k) {
+            const int u = min(v, n_verts - 1);
+            k = slot_hint(S.o_vbase, n_obj, S.vtx_hint, u);
+            return a.mesh_pos[S.o_mvb[k] + (u - S.o_vbase[k])];
+        };
+        int kn0 = 0, kn1 = 0;
+        float4 pn0 = make_float4(0.f, 0.f, 0.f, 0.f), pn1 = pn0;
+        if (n_verts > 0) {
+            pn0 = vload(tid, kn0);
+            pn1 = vload(tid + kFT, kn1);
+        }
+        for (int v0 = tid; v0 - tid < n_verts; v0 += 2 * kFT) {
+            const int v1 = v0 + kFT;
+            const float4 p0 = pn0, p1 = pn1;
+            const int k0 = kn0, k1 = kn1;
+            if (v0 - tid + 2 * kFT < n_verts) {
+                pn0 = vload(v0 + 2 * kFT, kn0);
+                pn1 = vload(v1 + 2 * kFT, kn1);
             }
-            S.X[v] = X;
-            S.Y[v] = Y;
-            S.iw[v] = iw;
+            if (v0 < n_verts) frame_vertex(S, v0, k0, p0, fx, fy, cx, cy, nearp);
+            if (v1 < n_verts) frame_vertex(S, v1, k1, p1, fx, fy, cx, cy, nearp);
         }
     }
     __syncthreads();
 
-    // ---- phase 2: set-up, per-tile counts, survivor list ----
-    for (int base = 0; base < n_tris; base += kFT) {
-        const int t = base + tid;
-        TriSetup T;
-        const bool keep = t < n_tris && frame_setup(a, S, n_obj, t, 0, 0, W - 1, H - 1, T);
-        unsigned entry = 0;
-        if (keep) {
-            const int tx0 = T.i0 >> 4, tx1 = T.i1 >> 4, ty0 = T.j0 >> 4, ty1 = T.j1 >> 4;
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&S.cnt[ty * ntx + tx], 1);
-            entry = ((unsigned)t << 16) | (unsigned)(tx0 | (tx1 << 4) | (ty0 << 8) | (ty1 << 12));
+    // ---- phase 2: set-up, per-tile counts, survivor list; two triangles per thread per
+    // pass, the next pass's mesh triangles loaded ahead ----
+    {
+        auto tload = [&](int t, int &k) {
+            const int u = min(t, n_tris - 1);  // out-of-range lanes load the last triangle
+            k = slot_hint(S.o_tbase, n_obj, S.tri_hint, u);
+            return frame_tri(a, S, k, u);
+        };
+        int kn0 = 0, kn1 = 0;
+        int4 tn0 = make_int4(0, 0, 0, 0), tn1 = tn0;
+        if (n_tris > 0) {
+            tn0 = tload(tid, kn0);
+            tn1 = tload(tid + kFT, kn1);
         }
-        const unsigned long long m = __ballot(keep);
-        int wb = 0;
-        if (lane == 0 && m) wb = atomicAdd(&S.misc[3], __popcll(m));
-        wb = __shfl(wb, 0);
-        if (keep) {
-            const int slot = wb + lanes_below(m);
-            if (slot < kFSurvMax) S.u.surv[slot] = entry;
+        for (int base = 0; base < n_tris; base += 2 * kFT) {
+            const int t0 = base + tid, t1 = t0 + kFT;
+            const int4 tr0 = tn0, tr1 = tn1;
+            const int k0 = kn0, k1 = kn1;
+            if (base + 2 * kFT < n_tris) {
+                tn0 = tload(t0 + 2 * kFT, kn0);
+                tn1 = tload(t1 + 2 * kFT, kn1);
+            }
+            TriSetup T0, T1;
+            const bool keep0 = t0 < n_tris && frame_setup(S, k0, tr0, 0, 0, W - 1, H - 1, T0);
+            const bool keep1 = t1 < n_tris && frame_setup(S, k1, tr1, 0, 0, W - 1, H - 1, T1);
+            const unsigned e0 = keep0 ? frame_count(S, t0, T0, ntx) : 0u;
+            const unsigned e1 = keep1 ? frame_count(S, t1, T1, ntx) : 0u;
+            frame_append(S, keep0, e0, lane);
+            frame_append(S, keep1, e1, lane);
         }
     }
     __syncthreads();
-    if (wave == 0) {  // exclusive scan of n_tiles <= 256 counts, 4 per lane
-        int c[4], local = 0;
+    if (wave == 0) {  // exclusive scan of n_tiles <= 256 counts (4 per lane) and the tile order
+        int c[4], local = 0, ne = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int t = lane * 4 + q;
             c[q] = t < n_tiles ? S.cnt[t] : 0;
             local += c[q];
+            ne += c[q] > 0;
         }
-        int incl = local;
+        int incl = local, incl_ne = ne;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
-            const int y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
+            const int y = __shfl_up(incl, o), yn = __shfl_up(incl_ne, o);
+            if (lane >= o) {
+                incl += y;
+                incl_ne += yn;
+            }
         }
-        int run = incl - local;
+        const int total_ne = __shfl(incl_ne, kWave - 1);
+        const bool overflow = __shfl(incl, kWave - 1) > kFBinMax;
+        int run = incl - local, run_ne = incl_ne - ne;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int t = lane * 4 + q;
             if (t < n_tiles) {
                 S.off[t] = run;
                 S.cnt[t] = run;  // becomes the scatter cursor
+                // without bins every tile is rasterized, in plain order
+                S.order[overflow ? t : (c[q] > 0 ? run_ne : total_ne + t - run_ne)] = (unsigned char)t;
             }
             run += c[q];
+            run_ne += c[q] > 0;
         }
         if (lane == kWave - 1) {
             S.off[n_tiles] = incl;
             S.misc[2] = incl;
-            S.misc[1] = incl > kFBinMax;
+            S.misc[1] = overflow;
+            S.misc[4] = overflow ? n_tiles : total_ne;
         }
     }
     __syncthreads();
@@ -584,33 +720,63 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     if (!overflow && n_surv <= kFSurvMax) {
         for (int k = tid; k < n_surv; k += kFT) {
             const unsigned e = S.u.surv[k];
-            const int tx0 = e & 15, tx1 = (e >> 4) & 15, ty0 = (e >> 8) & 15, ty1 = (e >> 12) & 15;
+            const int tx0 = e & 3, tx1 = (e >> 2) & 3, ty0 = (e >> 4) & 63, ty1 = (e >> 10) & 63;
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)(e >> 16);
         }
     } else if (!overflow) {  // too many survivors to remember: set them up again
         for (int t = tid; t < n_tris; t += kFT) {
+            const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, t);
             TriSetup T;
-            if (!frame_setup(a, S, n_obj, t, 0, 0, W - 1, H - 1, T)) continue;
-            for (int ty = T.j0 >> 4; ty <= (T.j1 >> 4); ++ty)
-                for (int tx = T.i0 >> 4; tx <= (T.i1 >> 4); ++tx)
+            if (!frame_setup(S, k, frame_tri(a, S, k, t), 0, 0, W - 1, H - 1, T)) continue;
+            for (int ty = T.j0 / kFTileH; ty <= T.j1 / kFTileH; ++ty)
+                for (int tx = T.i0 / kFTileW; tx <= T.i1 / kFTileW; ++tx)
                     S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)t;
         }
     }
     __syncthreads();
 
-    // ---- phase 4: waves raster, shade and write tiles ----
+    // ---- phase 4: waves take tiles (those with bin entries first), rasterize, shade and
+    // write them.  A wave issues all loads of a tile before its stores, and tiles without
+    // entries are written with stores alone, so no load waits behind earlier stores of
+    // the same wave except at the start of a tile with entries.
     const CamF cam = frame_camera(a, f);
     const int64_t HW = (int64_t)W * H, po = fi.pixel_offset;
+    const int n_busy = S.misc[4];
+    const uintptr_t align = (uintptr_t)a.out_rgb | (uintptr_t)a.out_depth | (uintptr_t)a.out_normal |
+                            (uintptr_t)a.out_seg | (uintptr_t)a.out_tri;
+    const bool vec_frame = ((W | (int)(po & 3)) & 3) == 0 && (align & 15) == 0;
+    const int lj = lane / (kFTileW / 4), li0 = (lane % (kFTileW / 4)) * 4;  // the lane's 4-pixel row group
     unsigned long long *vis = S.u.vis[wave];
+    // The last kFStoreWaves waves first write the tiles without entries (stores only),
+    // the others first rasterize and shade the tiles with entries, so the background
+    // stores drain while the busy tiles compute; each wave then helps with the other kind.
+    const bool store_first = wave >= kFW - kFStoreWaves;
     while (true) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(&S.misc[0], 1);
-        t = __shfl(t, 0);
-        if (t >= n_tiles) break;
+        int slot = -1;
+        if (lane == 0) {
+            const int n_empty = n_tiles - n_busy;
+            int q = atomicAdd(&S.misc[store_first ? 5 : 0], 1);
+            if (store_first ? q < n_empty : q < n_busy) {
+                slot = store_first ? n_busy + q : q;
+            } else {
+                q = atomicAdd(&S.misc[store_first ? 0 : 5], 1);
+                if (store_first ? q < n_busy : q < n_empty) slot = store_first ? q : n_busy + q;
+            }
+        }
+        slot = __shfl(slot, 0);
+        if (slot < 0) break;
+        const int t = S.order[slot];
         const int tyi = t / ntx, txi = t - tyi * ntx;
-        const int x0 = txi * kFTile, y0 = tyi * kFTile;
-        const int x1 = min(x0 + kFTile, W) - 1, y1 = min(y0 + kFTile, H) - 1;
+        const int x0 = txi * kFTileW, y0 = tyi * kFTileH;
+        const int x1 = min(x0 + kFTileW, W) - 1, y1 = min(y0 + kFTileH, H) - 1;
+        const int j = y0 + lj, i0 = x0 + li0;
+        const int n_in = j <= y1 ? max(0, min(4, x1 - i0 + 1)) : 0;
+        const int64_t gpix = (int64_t)j * W + i0;
+        if (slot >= n_busy) {  // no triangle touches the tile
+            if (n_in > 0) store_background4(a, po, HW, gpix, vec_frame && n_in == 4, n_in);
+            continue;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) vis[lane + 64 * q] = kEmptyKey;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -619,49 +785,110 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         const int e0 = overflow ? 0 : S.off[t], e1 = overflow ? n_tris : S.off[t + 1];
         for (int e = e0 + lane; e < e1; e += kWave) {
             const int tri = overflow ? e : (int)S.bin[e];
+            const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, tri);
             TriSetup T;
-            if (!frame_setup(a, S, n_obj, tri, x0, y0, x1, y1, T)) continue;
+            if (!frame_setup(S, k, frame_tri(a, S, k, tri), x0, y0, x1, y1, T)) continue;
             const int flags = tri_flags(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc);
             const float iwa = S.iw[T.va], iwb = S.iw[T.vb], iwc = S.iw[T.vc];
             const float area = (float)T.area;
-            for (int j = T.j0; j <= T.j1; ++j) {
-                for (int i = T.i0; i <= T.i1; ++i) {
-                    const Edges ed = edge_eval(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc, (i << 8) + 128, (j << 8) + 128, flags);
-                    if (!ed.covered) continue;
-                    atomicMin(&vis[(j - y0) * kFTile + (i - x0)], vis_key(fragment_depth(ed, iwa, iwb, iwc, area), tri));
+            if (!(flags & 8)) {  // small triangle: step the integer edge functions
+                const int b0 = (flags & 1) ? 0 : 1, b1 = (flags & 2) ? 0 : 1, b2 = (flags & 4) ? 0 : 1;
+                EdgeStep es = edge_start(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc, (T.i0 << 8) + 128, (T.j0 << 8) + 128);
+                for (int jj = T.j0; jj <= T.j1; ++jj) {
+                    int e0 = es.e0, e1 = es.e1, e2 = es.e2;
+                    for (int ii = T.i0; ii <= T.i1; ++ii) {
+                        if (((e0 - b0) | (e1 - b1) | (e2 - b2)) >= 0) {
+                            Edges ed;
+                            ed.e0 = (float)e0;
+                            ed.e1 = (float)e1;
+                            ed.e2 = (float)e2;
+                            atomicMin(&vis[(jj - y0) * kFTileW + (ii - x0)], vis_key(fragment_depth(ed, iwa, iwb, iwc, area), tri));
+                        }
+                        e0 += es.dx0;
+                        e1 += es.dx1;
+                        e2 += es.dx2;
+                    }
+                    es.e0 += es.dy0;
+                    es.e1 += es.dy1;
+                    es.e2 += es.dy2;
+                }
+            } else {
+                for (int jj = T.j0; jj <= T.j1; ++jj) {
+                    for (int ii = T.i0; ii <= T.i1; ++ii) {
+                        const Edges ed = edge_eval(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc, (ii << 8) + 128, (jj << 8) + 128, flags);
+                        if (!ed.covered) continue;
+                        atomicMin(&vis[(jj - y0) * kFTileW + (ii - x0)], vis_key(fragment_depth(ed, iwa, iwb, iwc, area), tri));
+                    }
                 }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
+
+        // covered pixels of the lane's group, then the wave's list of covered pixels
+        int covq = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < n_in && vis[lj * kFTileW + li0 + q] != kEmptyKey) covq |= 1 << q;
+        unsigned char *list = S.cov[wave];
+        int n_cov = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int p = lane + 64 * q;
-            const int li = p & (kFTile - 1), lj = p >> 4;
-            const int i = x0 + li, j = y0 + lj;
-            if (i > x1 || j > y1) continue;
-            const int64_t pix = (int64_t)j * W + i;
-            const unsigned long long key = vis[p];
-            PixelOut o = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            float z = 0.f;
-            int segv = -1, triv = -1;
-            if (key != kEmptyKey) {
-                const int tri = (int)(unsigned)(key & 0xffffffffu);
-                z = __uint_as_float((unsigned)(key >> 32));
-                const int k = find_slot(S.o_tbase, n_obj, tri);
-                const int4 tv = a.mesh_tri[S.o_mtb[k] + (tri - S.o_tbase[k])];
-                const int vb = S.o_vbase[k], mvb = S.o_mvb[k];
-                const int va = vb + tv.x, vbb = vb + tv.z, vc = vb + tv.y;  // positive-area order
-                o = shade_pixel(S.X[va], S.Y[va], S.X[vbb], S.Y[vbb], S.X[vc], S.Y[vc], S.iw[va], S.iw[vbb], S.iw[vc],
-                                a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], S.o_R[k], i, j, z,
-                                cam, S.light, S.light_type, fi.n_lights, S.o_mat[k]);
-                segv = S.o_seg[k];
-                triv = tri;
-            }
-            store_pixel(a, po, HW, pix, o, z, segv, triv, key);
+            const bool c = (covq >> q) & 1;
+            const unsigned long long m = __ballot(c);
+            if (c) list[n_cov + lanes_below(m)] = (unsigned char)(lj * kFTileW + li0 + q);
+            n_cov += __popcll(m);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
+
+        // shade the covered pixels, lane-compacted (lane takes list[lane + 64 r]); all
+        // loads of the tile precede its stores
+        // two passes of (up to) two pixels per lane: loads and shading, then stores
+        for (int r0 = 0; r0 * kWave < n_cov; r0 += 2) {
+            PixelOut o[2];
+            unsigned long long kk[2];
+            int sg[2], pxl[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                kk[h] = kEmptyKey;
+                sg[h] = -1;
+                pxl[h] = 0;
+                const int c = (r0 + h) * kWave + lane;
+                if (c >= n_cov) continue;
+                const int p = list[c];
+                const int pi = x0 + p % kFTileW, pj = y0 + p / kFTileW;
+                const unsigned long long key = vis[p];
+                const int tri = (int)(unsigned)(key & 0xffffffffu);
+                const float z = __uint_as_float((unsigned)(key >> 32));
+                const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, tri);
+                const int4 tv = frame_tri(a, S, k, tri);
+                const int vb = S.o_vbase[k], mvb = S.o_mvb[k];
+                const int va = vb + tv.x, vbb = vb + tv.z, vc = vb + tv.y;  // positive-area order
+                o[h] = shade_pixel(S.X[va], S.Y[va], S.X[vbb], S.Y[vbb], S.X[vc], S.Y[vc], S.iw[va], S.iw[vbb], S.iw[vc],
+                                   a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], S.o_R[k], pi, pj,
+                                   z, cam, S.light, S.light_type, fi.n_lights, S.o_mat[k]);
+                kk[h] = key;
+                sg[h] = S.o_seg[k];
+                pxl[h] = pj * W + pi;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (kk[h] == kEmptyKey) continue;
+                store_pixel(a, po, HW, pxl[h], o[h], __uint_as_float((unsigned)(kk[h] >> 32)), sg[h],
+                            (int)(unsigned)(kk[h] & 0xffffffffu), kk[h]);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (covq == 0) {
+            if (n_in > 0) store_background4(a, po, HW, gpix, vec_frame && n_in == 4, n_in);
+        } else {
+            const PixelOut bg = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q < n_in && !((covq >> q) & 1)) store_pixel(a, po, HW, gpix + q, bg, 0.f, -1, -1, kEmptyKey);
+        }
     }
 }
 

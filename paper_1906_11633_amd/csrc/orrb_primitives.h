@@ -120,6 +120,28 @@ ORRB_INLINE Edges edge_eval(int xa, int ya, int xb, int yb, int xc, int yc, int 
     return r;
 }
 
+// The integer edge functions of edge_eval (small triangles) at pixel centre (PX, PY)
+// and their steps per pixel in x and y.  Stepping adds exact int32 differences, so at
+// every pixel centre of the triangle's range the values equal edge_eval's.
+struct EdgeStep {
+    int e0, e1, e2;
+    int dx0, dx1, dx2, dy0, dy1, dy2;
+};
+
+ORRB_INLINE EdgeStep edge_start(int xa, int ya, int xb, int yb, int xc, int yc, int PX, int PY) {
+    EdgeStep s;
+    s.e0 = __mul24(xc - xb, PY - yb) - __mul24(yc - yb, PX - xb);
+    s.e1 = __mul24(xa - xc, PY - yc) - __mul24(ya - yc, PX - xc);
+    s.e2 = __mul24(xb - xa, PY - ya) - __mul24(yb - ya, PX - xa);
+    s.dx0 = (yb - yc) * 256;
+    s.dx1 = (yc - ya) * 256;
+    s.dx2 = (ya - yb) * 256;
+    s.dy0 = (xc - xb) * 256;
+    s.dy1 = (xa - xc) * 256;
+    s.dy2 = (xb - xa) * 256;
+    return s;
+}
+
 ORRB_INLINE int top_left(int dX, int dY) { return dY < 0 || (dY == 0 && dX > 0); }
 
 ORRB_INLINE int extent_flag(int xa, int ya, int xb, int yb, int xc, int yc) {
@@ -187,6 +209,28 @@ ORRB_INLINE float3 rotate_normal(const float *R, float4 q) {
     return f3(r.x * s, r.y * s, r.z * s);
 }
 
+// (1 - u)^m for 0 <= u < 1, m > 0, as 2^(m log2(1 - u)).  log2(1 - u) comes from the
+// Taylor series of ln(1 - u) (through u^7, truncation below 5e-10 relative) when
+// u < 1/16, where forming 1 - u would lose the low bits of u, and from the hardware
+// log2 otherwise (1 - u is then within 2^-25 of exact).  Against the exact power the
+// error stays below 3e-7 absolute and, where the power exceeds 1e-5, 1e-5 relative.
+ORRB_INLINE float spec_pow(float u, float m) {
+#pragma clang fp contract(off)
+    float l2;  // log2(1 - u)
+    if (u < 0.0625f) {
+        float p = fmaf(u, 1.0f / 7.0f, 1.0f / 6.0f);
+        p = fmaf(u, p, 0.2f);
+        p = fmaf(u, p, 0.25f);
+        p = fmaf(u, p, 1.0f / 3.0f);
+        p = fmaf(u, p, 0.5f);
+        p = fmaf(u, p, 1.0f);
+        l2 = -(u * p) * 1.44269504088896341f;
+    } else {
+        l2 = __builtin_amdgcn_logf(1.0f - u);
+    }
+    return __builtin_amdgcn_exp2f(m * l2);
+}
+
 // Shade the covered pixel (i, j) at eye depth z of the positive-area triangle a, b, c:
 // perspective-correct smooth normal from the unit object-space vertex normals and R,
 // then exposure * sum over lights of A * max(0, n.l) * (albedo + k_s * max(0, n.h)^m).
@@ -232,7 +276,7 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
             const float3 dd = f3(n.x - hh.x * hinv, n.y - hh.y * hinv, n.z - hh.z * hinv);
             // 1 - n.h evaluated as |n - h|^2 / 2: no cancellation near the highlight
             const float u = 0.5f * dot3(dd, dd);
-            if (u < 1.0f) s = (mexp == 0.f) ? 1.0f : expf(mexp * log1pf(-u));
+            if (u < 1.0f) s = (mexp == 0.f) ? 1.0f : spec_pow(u, mexp);
         }
         const float An = A * ndl;
         r0 = fmaf(An, fmaf(m.ks, s, m.al0), r0);
@@ -249,20 +293,22 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
     return o;
 }
 
+// Plain stores: non-temporal ones bypass the L2 merging of neighbouring row segments
+// and measured at about half the write bandwidth for tiled output.
 ORRB_INLINE void store_pixel(const RenderArgs &a, int64_t po, int64_t HW, int64_t pix, const PixelOut &o, float z, int seg,
                              int tri, unsigned long long key) {
     if (a.out_rgb) {
-        __builtin_nontemporal_store(o.r0, a.out_rgb + 3 * po + pix);
-        __builtin_nontemporal_store(o.r1, a.out_rgb + 3 * po + HW + pix);
-        __builtin_nontemporal_store(o.r2, a.out_rgb + 3 * po + 2 * HW + pix);
+        a.out_rgb[3 * po + pix] = o.r0;
+        a.out_rgb[3 * po + HW + pix] = o.r1;
+        a.out_rgb[3 * po + 2 * HW + pix] = o.r2;
     }
-    if (a.out_depth) __builtin_nontemporal_store(z, a.out_depth + po + pix);
+    if (a.out_depth) a.out_depth[po + pix] = z;
     if (a.out_normal) {
-        __builtin_nontemporal_store(o.n0, a.out_normal + 3 * po + pix);
-        __builtin_nontemporal_store(o.n1, a.out_normal + 3 * po + HW + pix);
-        __builtin_nontemporal_store(o.n2, a.out_normal + 3 * po + 2 * HW + pix);
+        a.out_normal[3 * po + pix] = o.n0;
+        a.out_normal[3 * po + HW + pix] = o.n1;
+        a.out_normal[3 * po + 2 * HW + pix] = o.n2;
     }
-    if (a.out_seg) __builtin_nontemporal_store(seg, a.out_seg + po + pix);
+    if (a.out_seg) a.out_seg[po + pix] = seg;
     if (a.out_tri) a.out_tri[po + pix] = tri;
     if (a.out_vis) a.out_vis[po + pix] = key;
 }
