@@ -695,7 +695,7 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
             e1 = T.get();
             if (e0) e = hipEventRecord(e0, st);
         }
-        if (e == hipSuccess) e = k == 0 ? launch_vertex(a, st) : k == 1 ? launch_raster(a, st, ctx->n_cu) : launch_frame(a, st);
+        if (e == hipSuccess) e = k == 0 ? launch_vertex(a, st) : k == 1 ? launch_raster(a, st, ctx->n_cu) : launch_frame(a, st, ctx->n_cu);
         if (T.enabled && e0 && e1 && e == hipSuccess) {
             e = hipEventRecord(e1, st);
             T.pending[k].push_back({e0, e1});

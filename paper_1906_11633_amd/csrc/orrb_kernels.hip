@@ -397,11 +397,29 @@ constexpr int kFOMax = 64;          // scene objects
 constexpr int kFTileW = 64;         // wave tile: 64 x 4 pixels, so that a wave's store
 constexpr int kFTileH = 4;          // instruction writes 256-byte row segments
 constexpr int kFTilesMax = 256;     // frames up to 256 x 256 (4 x 64 tiles)
-constexpr int kFBinMax = 16384;     // (tile, triangle) bin entries
-constexpr int kFSurvMax = 8192;     // survivors remembered between set-up and scatter
+constexpr int kFBinMax = 8192;      // (tile, triangle) bin entries (hand scenes: < 7,000)
+constexpr int kFSurvMax = 6144;     // survivors remembered between set-up and scatter (< 5,200)
 constexpr int kFHint = 64;          // elements per object-lookup hint
-constexpr int kFStoreWaves = 4;     // waves that start with the tiles no triangle touches
+constexpr int kFCW = 14;            // compute waves: geometry, raster, shading
+constexpr int kFCT = kFCW * kWave;  // compute threads
+constexpr int kFSlots = 4;          // frames whose background tiles may be pending at once
+constexpr int kFStage = 2;          // staged busy tiles (compute -> store waves)
+constexpr int kFPace = 32;          // store instructions in flight per store wave
+constexpr bool kFHeavyFirst = false;  // order tiles with entries by entry count
+constexpr unsigned kFSpinCap = 1u << 16;  // bound on every wait loop (about 5 ms)
 constexpr int kInvalidX = (int)0x80000000;
+
+struct BgFrame {
+    long long po;  // pixel offset of the frame
+    int W, H, ntx, vec;
+    int n;         // background tiles of the frame
+    int pad;
+};
+
+struct StageInfo {
+    long long po;  // pixel offset of the frame
+    int W, H, x0, y0, vec, pad;
+};
 
 struct FrameLds {
     int X[kFVMax], Y[kFVMax];
@@ -409,12 +427,12 @@ struct FrameLds {
     union {
         double M[kFOMax][12];                         // vertex phase
         unsigned int surv[kFSurvMax];                 // set-up -> scatter: (tri << 16) | tile range
-        unsigned long long vis[kFW][kFTileW * kFTileH];  // tile phase
+        unsigned long long vis[kFCW][kFTileW * kFTileH];  // tile phase
     } u;
     unsigned short bin[kFBinMax];
     int cnt[kFTilesMax + 1], off[kFTilesMax + 1];
     unsigned char order[kFTilesMax];                 // tile order: tiles with bin entries first
-    unsigned char cov[kFW][kFTileW * kFTileH];       // per wave: covered pixels of its tile
+    unsigned char cov[kFCW][kFTileW * kFTileH];      // per compute wave: covered pixels of its tile
     unsigned char tri_hint[65536 / kFHint];          // object of triangle 64 b
     unsigned char vtx_hint[(kFVMax + kFHint - 1) / kFHint];
     int o_tbase[kFOMax], o_vbase[kFOMax], o_mtb[kFOMax], o_mvb[kFOMax], o_nt[kFOMax], o_seg[kFOMax], o_vis[kFOMax];
@@ -423,7 +441,21 @@ struct FrameLds {
     float4 light[kMaxLights];
     int light_type[kMaxLights];
     int misc[8];  // [0] next tile with entries, [1] bin overflow, [2] total entries, [3] survivors,
-                  // [4] tiles with entries, [5] next tile without entries
+                  // [4] tiles with entries
+    // Background tiles (no triangle touches them) handed from the compute waves to the
+    // store waves, for the last kFSlots frames this workgroup published.
+    unsigned char bg_tile[kFSlots][kFTilesMax];
+    BgFrame bgf[kFSlots];
+    int bg_next[kFSlots], bg_done[kFSlots];  // tiles taken / written, per slot
+    int cons_seq[kFW];                       // frame each store wave takes tiles from
+    int published, all_published;            // frames published; 1 once no more will be
+    int cbar;                                // compute-wave barrier arrivals
+    // Busy tiles rendered by a compute wave and written out by a store wave: planes
+    // r, g, b, nx, ny, nz, seg (as bits) and the visibility key per tile pixel.
+    alignas(16) unsigned int stage_val[kFStage][7][kFTileW * kFTileH];
+    alignas(16) unsigned long long stage_key[kFStage][kFTileW * kFTileH];
+    StageInfo stage_info[kFStage];
+    int stage_state[kFStage];  // 0 free, 2 being filled, 1 full, 3 being written
 };
 static_assert(sizeof(FrameLds) <= 160 * 1024, "frame LDS exceeds 160 KB");
 
@@ -453,6 +485,34 @@ struct TriSetup {
     int va, vb, vc;      // LDS vertex indices
     long long area;
 };
+
+// Set-up of a binned triangle (front-facing with valid vertices, as checked when it was
+// binned) clipped to the tile [x0, x1] x [y0, y1]: false if its pixel-centre range
+// misses the tile.  Also returns the edge flags and the area as a float, the area from
+// 24-bit products when the triangle is small (the same integer as the 64-bit form).
+ORRB_INLINE bool tile_setup(const FrameLds &S, int k, int4 tri, int x0, int y0, int x1, int y1, TriSetup &T, int &flags,
+                            float &area) {
+    const int vb = S.o_vbase[k];
+    const int i0v = vb + tri.x, i1v = vb + tri.y, i2v = vb + tri.z;
+    const int xa = S.X[i0v], xb = S.X[i2v], xc = S.X[i1v];
+    const int ya = S.Y[i0v], yb = S.Y[i2v], yc = S.Y[i1v];
+    const int xmin = min(xa, min(xb, xc)), xmax = max(xa, max(xb, xc));
+    const int ymin = min(ya, min(yb, yc)), ymax = max(ya, max(yb, yc));
+    T.i0 = max(ceil256(xmin - 128), x0);
+    T.i1 = min(floor256(xmax - 128), x1);
+    T.j0 = max(ceil256(ymin - 128), y0);
+    T.j1 = min(floor256(ymax - 128), y1);
+    if (T.i0 > T.i1 || T.j0 > T.j1) return false;
+    T.xa = xa; T.ya = ya; T.xb = xb; T.yb = yb; T.xc = xc; T.yc = yc;
+    T.va = i0v; T.vb = i2v; T.vc = i1v;
+    flags = top_left(xc - xb, yc - yb) | (top_left(xa - xc, ya - yc) << 1) | (top_left(xb - xa, yb - ya) << 2) |
+            (max(xmax - xmin, ymax - ymin) > kSmallExtent ? 8 : 0);
+    if (!(flags & 8))
+        area = (float)(__mul24(xb - xa, yc - ya) - __mul24(yb - ya, xc - xa));
+    else
+        area = (float)((long long)(xb - xa) * (yc - ya) - (long long)(yb - ya) * (xc - xa));
+    return true;
+}
 
 ORRB_INLINE bool frame_setup(const FrameLds &S, int k, int4 tri, int cx0, int cy0, int cx1, int cy1, TriSetup &T) {
     if (!S.o_vis[k]) return false;
@@ -546,8 +606,14 @@ ORRB_INLINE void store4i(int *p, const int *v, bool vec, int n) {
 // Background (no fragment) for four adjacent pixels: rgb, depth, normal 0, seg and
 // tri_id -1, vis the empty key.
 ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, int64_t pix, bool vec, int n) {
-    const float zf[4] = {0.f, 0.f, 0.f, 0.f};
-    const int mi[4] = {-1, -1, -1, -1};
+    // materialized at each use: hoisted out of the tile loops these constants get
+    // spilled, and their reloads would wait for every earlier store of the wave
+    float z;
+    int m;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    asm volatile("v_mov_b32 %0, -1" : "=v"(m));
+    const float zf[4] = {z, z, z, z};
+    const int mi[4] = {m, m, m, m};
     if (a.out_rgb) {
         store4f(a.out_rgb + 3 * po + pix, zf, vec, n);
         store4f(a.out_rgb + 3 * po + HW + pix, zf, vec, n);
@@ -568,11 +634,275 @@ ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, 
     }
 }
 
+// ---- synchronization of the persistent frame workgroup ----
+//
+// The 12 compute waves render the workgroup's frames one after another and
+// synchronize among themselves with an LDS counter (the 4 store waves never join, so
+// the hardware barrier cannot be used).  After each frame's tile scan, wave 0 publishes
+// the frame's background tiles into one of kFSlots slots; the store waves take them
+// from per-slot counters and write them while the compute waves go on.  Every wait is
+// bounded by kFSpinCap polls.
+
+ORRB_INLINE int lds_load(const int *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP); }
+ORRB_INLINE void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); }
+
+ORRB_INLINE void frame_barrier(FrameLds &S, int &gen) {
+    gen += kFCW;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    if (lane_id() == 0) {
+        atomicAdd(&S.cbar, 1);
+        for (unsigned spin = 0; lds_load(&S.cbar) < gen && spin < kFSpinCap; ++spin) __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// 16-byte stores possible for the frame: width and offset multiples of 4 pixels and
+// every output 16-byte aligned.
+ORRB_INLINE bool frame_vec(const RenderArgs &a, int W, int64_t po) {
+    const uintptr_t align = (uintptr_t)a.out_rgb | (uintptr_t)a.out_depth | (uintptr_t)a.out_normal |
+                            (uintptr_t)a.out_seg | (uintptr_t)a.out_tri;
+    return ((W | (int)(po & 3)) & 3) == 0 && (align & 15) == 0;
+}
+
+// Wave 0: hand frame seq's background tiles, order[n_busy .. n_tiles), to the store
+// waves.  The slot is reused only after every store wave has moved past the frame that
+// held it before (so none still takes from it) and all its tiles are written.
+ORRB_INLINE void frame_publish(const RenderArgs &a, FrameLds &S, int seq, int64_t po, int W, int H, int ntx, int n_busy,
+                               int n_tiles, int lane) {
+    const int slot = seq % kFSlots, n_empty = n_tiles - n_busy;
+    if (lane == 0 && seq >= kFSlots) {
+        for (unsigned spin = 0; spin < kFSpinCap; ++spin) {
+            bool free = lds_load(&S.bg_done[slot]) >= S.bgf[slot].n;
+            for (int w = kFCW; w < kFW; ++w) free = free && lds_load(&S.cons_seq[w]) > seq - kFSlots;
+            if (free) break;
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    for (int i = lane; i < n_empty; i += kWave) S.bg_tile[slot][i] = S.order[n_busy + i];
+    if (lane == 0) {
+        BgFrame &b = S.bgf[slot];
+        b.po = po;
+        b.W = W;
+        b.H = H;
+        b.ntx = ntx;
+        b.vec = frame_vec(a, W, po);
+        b.n = n_empty;
+        S.bg_next[slot] = 0;
+        S.bg_done[slot] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) lds_store(&S.published, seq + 1);
+}
+
+// ---- staged busy tiles: a compute wave fills a slot, a store wave writes it out ----
+
+// Claim a free staging slot and fill it with the background for the whole tile (each
+// lane its 4-pixel group).  Waits while both slots are in use.
+ORRB_INLINE int stage_begin(FrameLds &S, int lane, int lj, int li0) {
+    int s = 0;
+    if (lane == 0) {
+        for (unsigned spin = 0; spin < kFSpinCap; ++spin) {
+            int k = 0;
+            for (; k < kFStage; ++k)
+                if (lds_load(&S.stage_state[k]) == 0 && atomicCAS(&S.stage_state[k], 0, 2) == 0) break;
+            if (k < kFStage) {
+                s = k;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    s = __shfl(s, 0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    const int p = lj * kFTileW + li0;
+    uint4 z4;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z4.x));
+    z4.y = z4.z = z4.w = z4.x;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) *reinterpret_cast<uint4 *>(&S.stage_val[s][c][p]) = z4;
+    *reinterpret_cast<uint4 *>(&S.stage_val[s][6][p]) = make_uint4(~z4.x, ~z4.x, ~z4.x, ~z4.x);  // seg -1
+    *reinterpret_cast<uint4 *>(&S.stage_key[s][p]) = make_uint4(~z4.x, ~z4.x, ~z4.x, ~z4.x);
+    *reinterpret_cast<uint4 *>(&S.stage_key[s][p + 2]) = make_uint4(~z4.x, ~z4.x, ~z4.x, ~z4.x);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return s;
+}
+
+ORRB_INLINE void stage_pixel(FrameLds &S, int s, int p, const PixelOut &o, int seg, unsigned long long key) {
+    S.stage_val[s][0][p] = __float_as_uint(o.r0);
+    S.stage_val[s][1][p] = __float_as_uint(o.r1);
+    S.stage_val[s][2][p] = __float_as_uint(o.r2);
+    S.stage_val[s][3][p] = __float_as_uint(o.n0);
+    S.stage_val[s][4][p] = __float_as_uint(o.n1);
+    S.stage_val[s][5][p] = __float_as_uint(o.n2);
+    S.stage_val[s][6][p] = (unsigned)seg;
+    S.stage_key[s][p] = key;
+}
+
+// Hand the filled slot to the store waves, with where the tile goes.
+ORRB_INLINE void stage_end(FrameLds &S, int s, int64_t po, int W, int H, int x0, int y0, bool vec, int lane) {
+    if (lane == 0) {
+        StageInfo &in = S.stage_info[s];
+        in.po = po;
+        in.W = W;
+        in.H = H;
+        in.x0 = x0;
+        in.y0 = y0;
+        in.vec = vec;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) lds_store(&S.stage_state[s], 1);
+}
+
+// Store wave: write staged tile s (every output plane) and free the slot.
+ORRB_INLINE void stage_write(const RenderArgs &a, FrameLds &S, int s, int lj, int li0, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    const StageInfo in = S.stage_info[s];
+    const int p = lj * kFTileW + li0;
+    const int x1 = min(in.x0 + kFTileW, in.W) - 1, y1 = min(in.y0 + kFTileH, in.H) - 1;
+    const int j = in.y0 + lj, i0 = in.x0 + li0;
+    const int n = j <= y1 ? max(0, min(4, x1 - i0 + 1)) : 0;
+    float v[7][4];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        const uint4 u = *reinterpret_cast<const uint4 *>(&S.stage_val[s][c][p]);
+        v[c][0] = __uint_as_float(u.x);
+        v[c][1] = __uint_as_float(u.y);
+        v[c][2] = __uint_as_float(u.z);
+        v[c][3] = __uint_as_float(u.w);
+    }
+    unsigned long long key[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) key[q] = S.stage_key[s][p + q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");  // slot contents read
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) lds_store(&S.stage_state[s], 0);
+    if (n == 0) return;
+    const bool vec = in.vec && n == 4;
+    const int64_t HW = (int64_t)in.W * in.H, po = in.po, pix = (int64_t)j * in.W + i0;
+    float z[4];
+    int seg[4], tri[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool e = key[q] == kEmptyKey;
+        z[q] = e ? 0.f : __uint_as_float((unsigned)(key[q] >> 32));
+        tri[q] = e ? -1 : (int)(unsigned)(key[q] & 0xffffffffu);
+        seg[q] = __float_as_int(v[6][q]);
+    }
+    if (a.out_rgb) {
+        store4f(a.out_rgb + 3 * po + pix, v[0], vec, n);
+        store4f(a.out_rgb + 3 * po + HW + pix, v[1], vec, n);
+        store4f(a.out_rgb + 3 * po + 2 * HW + pix, v[2], vec, n);
+    }
+    if (a.out_depth) store4f(a.out_depth + po + pix, z, vec, n);
+    if (a.out_normal) {
+        store4f(a.out_normal + 3 * po + pix, v[3], vec, n);
+        store4f(a.out_normal + 3 * po + HW + pix, v[4], vec, n);
+        store4f(a.out_normal + 3 * po + 2 * HW + pix, v[5], vec, n);
+    }
+    if (a.out_seg) store4i(a.out_seg + po + pix, seg, vec, n);
+    if (a.out_tri) store4i(a.out_tri + po + pix, tri, vec, n);
+    if (a.out_vis) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < n) a.out_vis[po + pix + q] = key[q];
+    }
+}
+
+// Pace a store wave: at most kFPace store instructions in flight, so the CU's memory
+// queue does not fill with stores ahead of the compute waves' loads.
+ORRB_INLINE void store_pace() { asm volatile("s_waitcnt vmcnt(%0)" ::"n"(kFPace) : "memory"); }
+
+// Write the background of published tiles until every frame is published and taken.
+// Store waves run this from the start; compute waves join after their last frame,
+// starting at the oldest frame that may still have tiles.
+ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj, int li0, int lane) {
+    const bool store_wave = wave >= kFCW;
+    int my = store_wave ? 0 : max(0, lds_load(&S.published) - kFSlots);
+    while (true) {
+        // 1: staged tile st claimed, 2: frame my is published, 0: nothing more will come
+        int action = 0, st = 0;
+        if (lane == 0) {
+            for (unsigned spin = 0; spin < kFSpinCap; ++spin) {
+                for (int k = 0; k < kFStage && !action; ++k)
+                    if (lds_load(&S.stage_state[k]) == 1 && atomicCAS(&S.stage_state[k], 1, 3) == 1) {
+                        action = 1;
+                        st = k;
+                    }
+                if (action) break;
+                const int fin = lds_load(&S.all_published);
+                if (my < lds_load(&S.published)) {
+                    action = 2;
+                    break;
+                }
+                if (fin) {  // compute waves are done: only full slots may remain
+                    bool pending = false;
+                    for (int k = 0; k < kFStage; ++k) pending = pending || lds_load(&S.stage_state[k]) == 1;
+                    if (!pending) break;
+                    continue;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        action = __shfl(action, 0);
+        if (!action) break;
+        if (action == 1) {
+            stage_write(a, S, __shfl(st, 0), lj, li0, lane);
+            if (store_wave) store_pace();
+            continue;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        const int slot = my % kFSlots;
+        int i = 0;
+        if (lane == 0) i = atomicAdd(&S.bg_next[slot], 1);
+        i = __shfl(i, 0);
+        const BgFrame b = S.bgf[slot];
+        if (i >= b.n) {  // the frame's tiles are all taken
+            ++my;
+            if (store_wave && lane == 0) lds_store(&S.cons_seq[wave], my);
+            continue;
+        }
+        const int t = S.bg_tile[slot][i];
+        const int tyi = t / b.ntx, txi = t - tyi * b.ntx;
+        const int x0 = txi * kFTileW, y0 = tyi * kFTileH;
+        const int x1 = min(x0 + kFTileW, b.W) - 1, y1 = min(y0 + kFTileH, b.H) - 1;
+        const int j = y0 + lj, i0 = x0 + li0;
+        const int n_in = j <= y1 ? max(0, min(4, x1 - i0 + 1)) : 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) atomicAdd(&S.bg_done[slot], 1);
+        if (n_in > 0)
+            store_background4(a, b.po, (int64_t)b.W * b.H, (int64_t)j * b.W + i0, b.vec && n_in == 4, n_in);
+        if (store_wave) store_pace();
+    }
+}
+
 __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     __shared__ FrameLds S;
-    const int f = a.fitems[blockIdx.x];
-    const FrameInfo fi = a.frames[f];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    if (tid == 0) {
+        S.published = S.all_published = S.cbar = 0;
+        for (int k = 0; k < kFSlots; ++k) S.bgf[k].n = S.bg_next[k] = S.bg_done[k] = 0;
+        for (int k = 0; k < kFStage; ++k) S.stage_state[k] = 0;
+        for (int w = 0; w < kFW; ++w) S.cons_seq[w] = 0;
+    }
+    __syncthreads();  // the only barrier of all 16 waves; compute waves use frame_barrier
+    if (wave < kFCW) {
+    int gen = 0;  // compute-wave barrier generation
+    for (int item = blockIdx.x, seq = 0; item < a.n_fitems; item += gridDim.x, ++seq) {
+    // Thread indices made opaque per frame: address arithmetic derived from them is
+    // recomputed inside the frame instead of being hoisted (and spilled) across frames.
+    int tid = threadIdx.x, lane = tid & (kWave - 1);
+    asm volatile("" : "+v"(tid), "+v"(lane));
+    const int wave = __builtin_amdgcn_readfirstlane(tid) / kWave;
+    const int lj = lane / (kFTileW / 4), li0 = (lane % (kFTileW / 4)) * 4;  // the lane's 4-pixel row group
+    const int f = a.fitems[item];
+    const FrameInfo fi = a.frames[f];
     const int n_obj = fi.n_obj, W = fi.width, H = fi.height;
     const int ntx = (W + kFTileW - 1) / kFTileW, nty = (H + kFTileH - 1) / kFTileH, n_tiles = ntx * nty;
 
@@ -589,7 +919,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         S.o_vis[tid] = a.visible[o];
         S.o_mat[tid] = object_material(a, o);
     }
-    for (int e = tid; e < 12 * n_obj; e += kFT) {
+    for (int e = tid; e < 12 * n_obj; e += kFCT) {
         const int k = e / 12, q = e - 12 * k;
         const double m = compose_entry(a.view + 12 * (int64_t)f, a.pose + 12 * (int64_t)(fi.obj_begin + k), q);
         S.u.M[k][q] = m;
@@ -600,14 +930,14 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         S.light[tid] = view_light(a.view + 12 * (int64_t)f, a.light_vec + 3 * (int64_t)l, a.light_type[l], a.light_intensity[l]);
         S.light_type[tid] = a.light_type[l];
     }
-    for (int t = tid; t <= n_tiles; t += kFT) S.cnt[t] = 0;
+    for (int t = tid; t <= n_tiles; t += kFCT) S.cnt[t] = 0;
     if (tid < 8) S.misc[tid] = 0;
     const int n_verts = n_obj > 0 ? a.objs[fi.obj_begin + n_obj - 1].scene_vbase + a.objs[fi.obj_begin + n_obj - 1].n_verts : 0;
-    __syncthreads();
+    frame_barrier(S, gen);
     const int n_tris = n_obj > 0 ? S.o_tbase[n_obj - 1] + S.o_nt[n_obj - 1] : 0;
-    for (int b = tid; b * kFHint < n_tris; b += kFT) S.tri_hint[b] = (unsigned char)find_slot(S.o_tbase, n_obj, b * kFHint);
-    for (int b = tid; b * kFHint < n_verts; b += kFT) S.vtx_hint[b] = (unsigned char)find_slot(S.o_vbase, n_obj, b * kFHint);
-    __syncthreads();
+    for (int b = tid; b * kFHint < n_tris; b += kFCT) S.tri_hint[b] = (unsigned char)find_slot(S.o_tbase, n_obj, b * kFHint);
+    for (int b = tid; b * kFHint < n_verts; b += kFCT) S.vtx_hint[b] = (unsigned char)find_slot(S.o_vbase, n_obj, b * kFHint);
+    frame_barrier(S, gen);
 
     // ---- phase 1: vertices, two per thread per pass; the next pass's positions are
     // loaded before the current pass is transformed, hiding the load latency ----
@@ -624,21 +954,21 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         float4 pn0 = make_float4(0.f, 0.f, 0.f, 0.f), pn1 = pn0;
         if (n_verts > 0) {
             pn0 = vload(tid, kn0);
-            pn1 = vload(tid + kFT, kn1);
+            pn1 = vload(tid + kFCT, kn1);
         }
-        for (int v0 = tid; v0 - tid < n_verts; v0 += 2 * kFT) {
-            const int v1 = v0 + kFT;
+        for (int v0 = tid; v0 - tid < n_verts; v0 += 2 * kFCT) {
+            const int v1 = v0 + kFCT;
             const float4 p0 = pn0, p1 = pn1;
             const int k0 = kn0, k1 = kn1;
-            if (v0 - tid + 2 * kFT < n_verts) {
-                pn0 = vload(v0 + 2 * kFT, kn0);
-                pn1 = vload(v1 + 2 * kFT, kn1);
+            if (v0 - tid + 2 * kFCT < n_verts) {
+                pn0 = vload(v0 + 2 * kFCT, kn0);
+                pn1 = vload(v1 + 2 * kFCT, kn1);
             }
             if (v0 < n_verts) frame_vertex(S, v0, k0, p0, fx, fy, cx, cy, nearp);
             if (v1 < n_verts) frame_vertex(S, v1, k1, p1, fx, fy, cx, cy, nearp);
         }
     }
-    __syncthreads();
+    frame_barrier(S, gen);
 
     // ---- phase 2: set-up, per-tile counts, survivor list; two triangles per thread per
     // pass, the next pass's mesh triangles loaded ahead ----
@@ -652,15 +982,15 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         int4 tn0 = make_int4(0, 0, 0, 0), tn1 = tn0;
         if (n_tris > 0) {
             tn0 = tload(tid, kn0);
-            tn1 = tload(tid + kFT, kn1);
+            tn1 = tload(tid + kFCT, kn1);
         }
-        for (int base = 0; base < n_tris; base += 2 * kFT) {
-            const int t0 = base + tid, t1 = t0 + kFT;
+        for (int base = 0; base < n_tris; base += 2 * kFCT) {
+            const int t0 = base + tid, t1 = t0 + kFCT;
             const int4 tr0 = tn0, tr1 = tn1;
             const int k0 = kn0, k1 = kn1;
-            if (base + 2 * kFT < n_tris) {
-                tn0 = tload(t0 + 2 * kFT, kn0);
-                tn1 = tload(t1 + 2 * kFT, kn1);
+            if (base + 2 * kFCT < n_tris) {
+                tn0 = tload(t0 + 2 * kFCT, kn0);
+                tn1 = tload(t1 + 2 * kFCT, kn1);
             }
             TriSetup T0, T1;
             const bool keep0 = t0 < n_tris && frame_setup(S, k0, tr0, 0, 0, W - 1, H - 1, T0);
@@ -671,7 +1001,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             frame_append(S, keep1, e1, lane);
         }
     }
-    __syncthreads();
+    frame_barrier(S, gen);
     if (wave == 0) {  // exclusive scan of n_tiles <= 256 counts (4 per lane) and the tile order
         int c[4], local = 0, ne = 0;
 #pragma unroll
@@ -699,11 +1029,27 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             if (t < n_tiles) {
                 S.off[t] = run;
                 S.cnt[t] = run;  // becomes the scatter cursor
-                // without bins every tile is rasterized, in plain order
-                S.order[overflow ? t : (c[q] > 0 ? run_ne : total_ne + t - run_ne)] = (unsigned char)t;
+                // without bins every tile is rasterized, in plain order; tiles without
+                // entries go last
+                if (overflow || c[q] == 0 || !kFHeavyFirst)
+                    S.order[overflow ? t : (c[q] > 0 ? run_ne : total_ne + t - run_ne)] = (unsigned char)t;
             }
             run += c[q];
             run_ne += c[q] > 0;
+        }
+        if (!overflow && kFHeavyFirst) {
+            // tiles with entries by decreasing power-of-two class of their entry count, so
+            // the longest tiles start first and the waves finish together
+            int at = 0;
+            for (int cls = 13; cls >= 0; --cls) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool in = c[q] > 0 && 31 - __clz(c[q]) == cls;
+                    const unsigned long long m = __ballot(in);
+                    if (in) S.order[at + lanes_below(m)] = (unsigned char)(lane * 4 + q);
+                    at += __popcll(m);
+                }
+            }
         }
         if (lane == kWave - 1) {
             S.off[n_tiles] = incl;
@@ -711,21 +1057,24 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             S.misc[1] = overflow;
             S.misc[4] = overflow ? n_tiles : total_ne;
         }
+        // queue the tiles no triangle touches for the store waves
+        const int n_busy = overflow ? n_tiles : total_ne;
+        frame_publish(a, S, seq, fi.pixel_offset, W, H, ntx, n_busy, n_tiles, lane);
     }
-    __syncthreads();
+    frame_barrier(S, gen);
     const bool overflow = S.misc[1] != 0;
 
     // ---- phase 3: scatter triangle IDs into the tile bins ----
     const int n_surv = S.misc[3];
     if (!overflow && n_surv <= kFSurvMax) {
-        for (int k = tid; k < n_surv; k += kFT) {
+        for (int k = tid; k < n_surv; k += kFCT) {
             const unsigned e = S.u.surv[k];
             const int tx0 = e & 3, tx1 = (e >> 2) & 3, ty0 = (e >> 4) & 63, ty1 = (e >> 10) & 63;
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)(e >> 16);
         }
     } else if (!overflow) {  // too many survivors to remember: set them up again
-        for (int t = tid; t < n_tris; t += kFT) {
+        for (int t = tid; t < n_tris; t += kFCT) {
             const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, t);
             TriSetup T;
             if (!frame_setup(S, k, frame_tri(a, S, k, t), 0, 0, W - 1, H - 1, T)) continue;
@@ -734,38 +1083,21 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                     S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)t;
         }
     }
-    __syncthreads();
+    frame_barrier(S, gen);
 
-    // ---- phase 4: waves take tiles (those with bin entries first), rasterize, shade and
-    // write them.  A wave issues all loads of a tile before its stores, and tiles without
-    // entries are written with stores alone, so no load waits behind earlier stores of
-    // the same wave except at the start of a tile with entries.
+    // ---- phase 4: compute waves take the tiles with bin entries, rasterize, shade and
+    // write them, issuing all loads of a tile before its stores; the store waves write
+    // the rest meanwhile.
     const CamF cam = frame_camera(a, f);
     const int64_t HW = (int64_t)W * H, po = fi.pixel_offset;
     const int n_busy = S.misc[4];
-    const uintptr_t align = (uintptr_t)a.out_rgb | (uintptr_t)a.out_depth | (uintptr_t)a.out_normal |
-                            (uintptr_t)a.out_seg | (uintptr_t)a.out_tri;
-    const bool vec_frame = ((W | (int)(po & 3)) & 3) == 0 && (align & 15) == 0;
-    const int lj = lane / (kFTileW / 4), li0 = (lane % (kFTileW / 4)) * 4;  // the lane's 4-pixel row group
+    const bool vec_frame = frame_vec(a, W, po);
     unsigned long long *vis = S.u.vis[wave];
-    // The last kFStoreWaves waves first write the tiles without entries (stores only),
-    // the others first rasterize and shade the tiles with entries, so the background
-    // stores drain while the busy tiles compute; each wave then helps with the other kind.
-    const bool store_first = wave >= kFW - kFStoreWaves;
     while (true) {
-        int slot = -1;
-        if (lane == 0) {
-            const int n_empty = n_tiles - n_busy;
-            int q = atomicAdd(&S.misc[store_first ? 5 : 0], 1);
-            if (store_first ? q < n_empty : q < n_busy) {
-                slot = store_first ? n_busy + q : q;
-            } else {
-                q = atomicAdd(&S.misc[store_first ? 0 : 5], 1);
-                if (store_first ? q < n_busy : q < n_empty) slot = store_first ? q : n_busy + q;
-            }
-        }
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(&S.misc[0], 1);
         slot = __shfl(slot, 0);
-        if (slot < 0) break;
+        if (slot >= n_busy) break;
         const int t = S.order[slot];
         const int tyi = t / ntx, txi = t - tyi * ntx;
         const int x0 = txi * kFTileW, y0 = tyi * kFTileH;
@@ -773,10 +1105,6 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         const int j = y0 + lj, i0 = x0 + li0;
         const int n_in = j <= y1 ? max(0, min(4, x1 - i0 + 1)) : 0;
         const int64_t gpix = (int64_t)j * W + i0;
-        if (slot >= n_busy) {  // no triangle touches the tile
-            if (n_in > 0) store_background4(a, po, HW, gpix, vec_frame && n_in == 4, n_in);
-            continue;
-        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) vis[lane + 64 * q] = kEmptyKey;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -787,10 +1115,16 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             const int tri = overflow ? e : (int)S.bin[e];
             const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, tri);
             TriSetup T;
-            if (!frame_setup(S, k, frame_tri(a, S, k, tri), x0, y0, x1, y1, T)) continue;
-            const int flags = tri_flags(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc);
+            int flags;
+            float area;
+            if (overflow) {  // unbinned: the full culling set-up
+                if (!frame_setup(S, k, frame_tri(a, S, k, tri), x0, y0, x1, y1, T)) continue;
+                flags = tri_flags(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc);
+                area = (float)T.area;
+            } else if (!tile_setup(S, k, frame_tri(a, S, k, tri), x0, y0, x1, y1, T, flags, area)) {
+                continue;
+            }
             const float iwa = S.iw[T.va], iwb = S.iw[T.vb], iwc = S.iw[T.vc];
-            const float area = (float)T.area;
             if (!(flags & 8)) {  // small triangle: step the integer edge functions
                 const int b0 = (flags & 1) ? 0 : 1, b1 = (flags & 2) ? 0 : 1, b2 = (flags & 4) ? 0 : 1;
                 EdgeStep es = edge_start(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc, (T.i0 << 8) + 128, (T.j0 << 8) + 128);
@@ -844,16 +1178,18 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
 
         // shade the covered pixels, lane-compacted (lane takes list[lane + 64 r]); all
         // loads of the tile precede its stores
-        // two passes of (up to) two pixels per lane: loads and shading, then stores
+        // shade the covered pixels in passes of (up to) two per lane and put them, over
+        // the tile's background, into a staging slot that a store wave writes out
+        int stg = -1;
         for (int r0 = 0; r0 * kWave < n_cov; r0 += 2) {
             PixelOut o[2];
             unsigned long long kk[2];
-            int sg[2], pxl[2];
+            int sg[2], pl[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 kk[h] = kEmptyKey;
                 sg[h] = -1;
-                pxl[h] = 0;
+                pl[h] = 0;
                 const int c = (r0 + h) * kWave + lane;
                 if (c >= n_cov) continue;
                 const int p = list[c];
@@ -870,26 +1206,23 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                                    z, cam, S.light, S.light_type, fi.n_lights, S.o_mat[k]);
                 kk[h] = key;
                 sg[h] = S.o_seg[k];
-                pxl[h] = pj * W + pi;
+                pl[h] = p;
+                __builtin_amdgcn_sched_barrier(0);  // shade the two pixels one after the other
             }
+            if (stg < 0) stg = stage_begin(S, lane, lj, li0);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (kk[h] == kEmptyKey) continue;
-                store_pixel(a, po, HW, pxl[h], o[h], __uint_as_float((unsigned)(kk[h] >> 32)), sg[h],
-                            (int)(unsigned)(kk[h] & 0xffffffffu), kk[h]);
-            }
+            for (int h = 0; h < 2; ++h)
+                if (kk[h] != kEmptyKey) stage_pixel(S, stg, pl[h], o[h], sg[h], kk[h]);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (covq == 0) {
-            if (n_in > 0) store_background4(a, po, HW, gpix, vec_frame && n_in == 4, n_in);
-        } else {
-            const PixelOut bg = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (q < n_in && !((covq >> q) & 1)) store_pixel(a, po, HW, gpix + q, bg, 0.f, -1, -1, kEmptyKey);
-        }
+        if (stg < 0) stg = stage_begin(S, lane, lj, li0);
+        stage_end(S, stg, po, W, H, x0, y0, vec_frame, lane);
     }
+    frame_barrier(S, gen);  // the frame's LDS is reused by the next frame
+    }
+    if (wave == 0 && lane == 0) __hip_atomic_store(&S.all_published, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    // store waves from the start, compute waves after their last frame
+    frame_drain(a, S, wave, lane / (kFTileW / 4), (lane % (kFTileW / 4)) * 4, lane);
 }
 
 // ------------------------------------------------------------------------------------
@@ -945,9 +1278,12 @@ hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu) {
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_frame(const RenderArgs &a, hipStream_t stream) {
+// Persistent: one workgroup per CU (the frame LDS allows no more), each rendering
+// frames blockIdx.x, blockIdx.x + gridDim.x, ...
+hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu) {
     if (a.n_fitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_frame, dim3(a.n_fitems), dim3(kFT), 0, stream, a);
+    const int grid = a.n_fitems < n_cu ? a.n_fitems : n_cu;
+    hipLaunchKernelGGL(k_frame, dim3(grid), dim3(kFT), 0, stream, a);
     return hipGetLastError();
 }
 
