@@ -400,11 +400,12 @@ constexpr int kFTilesMax = 256;     // frames up to 256 x 256 (4 x 64 tiles)
 constexpr int kFBinMax = 8192;      // (tile, triangle) bin entries (hand scenes: < 7,000)
 constexpr int kFSurvMax = 6144;     // survivors remembered between set-up and scatter (< 5,200)
 constexpr int kFHint = 64;          // elements per object-lookup hint
-constexpr int kFCW = 14;            // compute waves: geometry, raster, shading
+constexpr int kFCW = 13;            // compute waves: geometry, raster, shading
 constexpr int kFCT = kFCW * kWave;  // compute threads
 constexpr int kFSlots = 4;          // frames whose background tiles may be pending at once
 constexpr int kFStage = 2;          // staged busy tiles (compute -> store waves)
-constexpr int kFPace = 32;          // store instructions in flight per store wave
+constexpr int kFPace = 60;          // store instructions in flight per store wave
+constexpr bool kFStageWave = true;  // the last wave writes only staged tiles
 constexpr bool kFHeavyFirst = false;  // order tiles with entries by entry count
 constexpr unsigned kFSpinCap = 1u << 16;  // bound on every wait loop (about 5 ms)
 constexpr int kInvalidX = (int)0x80000000;
@@ -823,6 +824,8 @@ ORRB_INLINE void store_pace() { asm volatile("s_waitcnt vmcnt(%0)" ::"n"(kFPace)
 // starting at the oldest frame that may still have tiles.
 ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj, int li0, int lane) {
     const bool store_wave = wave >= kFCW;
+    // a wave kept for staged tiles answers them without delay (no background tiles)
+    const bool staged_only = kFStageWave && wave == kFW - 1;
     int my = store_wave ? 0 : max(0, lds_load(&S.published) - kFSlots);
     while (true) {
         // 1: staged tile st claimed, 2: frame my is published, 0: nothing more will come
@@ -836,7 +839,7 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
                     }
                 if (action) break;
                 const int fin = lds_load(&S.all_published);
-                if (my < lds_load(&S.published)) {
+                if (!staged_only && my < lds_load(&S.published)) {
                     action = 2;
                     break;
                 }
@@ -853,7 +856,7 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
         if (!action) break;
         if (action == 1) {
             stage_write(a, S, __shfl(st, 0), lj, li0, lane);
-            if (store_wave) store_pace();
+            if (store_wave && !staged_only) store_pace();
             continue;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
@@ -889,7 +892,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         S.published = S.all_published = S.cbar = 0;
         for (int k = 0; k < kFSlots; ++k) S.bgf[k].n = S.bg_next[k] = S.bg_done[k] = 0;
         for (int k = 0; k < kFStage; ++k) S.stage_state[k] = 0;
-        for (int w = 0; w < kFW; ++w) S.cons_seq[w] = 0;
+        for (int w = 0; w < kFW; ++w) S.cons_seq[w] = kFStageWave && w == kFW - 1 ? 0x7fffffff : 0;
     }
     __syncthreads();  // the only barrier of all 16 waves; compute waves use frame_barrier
     if (wave < kFCW) {

@@ -86,6 +86,37 @@ def test_frame_path_bin_overflow(renderer):
     assert stats["covered"] > 50000
 
 
+def test_frame_path_survivor_overflow(renderer):
+    """A finely tessellated plane (6,498 front-facing triangles in the frame, 7,424 bin
+    entries): more survivors than the frame kernel remembers between set-up and
+    scatter, so it sets them up again while scattering; same result."""
+    mesh = S.plane_mesh(57, 57, 0.7, 0.7)
+    b = S.single_object_batch(mesh, S.make_pose(np.eye(3), (0.0, 0.0, -2.0), 1.0), res=(200, 200),
+                              lights=((0, (0.3, 0.4, 0.5), 1.5),), spec=0.4, rough=0.5)
+    gpu, job = _render(renderer, b)
+    assert job.layout.info.frame_path_frames == 1
+    stats = parity.compare(b, gpu, oracle.render(b))
+    print(stats)
+    assert stats["covered"] > 5000
+
+
+def test_frame_path_many_frames_per_workgroup(renderer):
+    """Far more frames than CUs (1,350 frames at 48x48): each persistent workgroup
+    renders five or more frames in a row, so the hand-over slots for background tiles
+    are reused; every frame matches the oracle, and rendering only the four benchmark
+    channels (16-byte stores, no tri_id/vis planes) gives the same bits."""
+    import torch
+    b = S.config2(2, 450, 48)
+    gpu, job = _render(renderer, b)
+    assert job.layout.info.frame_path_frames == b.n_frames == 1350
+    parity.compare(b, gpu, oracle.render(b))
+    out4 = renderer.render(job)
+    torch.cuda.synchronize()
+    assert set(out4) == {"rgb", "depth", "normal", "seg"}
+    for k in out4:
+        assert np.array_equal(out4[k].cpu().numpy(), gpu[k]), k
+
+
 def test_mixed_paths_uneven_batch(renderer):
     """An uneven batch (resolutions 64..256, 2k-50k triangles): scenes that fit LDS take
     the frame path, the others the tiled path, in one call."""
