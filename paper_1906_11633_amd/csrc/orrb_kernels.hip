@@ -406,6 +406,9 @@ constexpr int kFSlots = 4;          // frames whose background tiles may be pend
 constexpr int kFStage = 2;          // staged busy tiles (compute -> store waves)
 constexpr int kFPace = 60;          // store instructions in flight per store wave
 constexpr bool kFStageWave = true;  // the last wave writes only staged tiles
+constexpr int kFChunk = 1;          // background tiles a store wave takes at once
+constexpr int kFVN = 2;             // vertices per thread per pass
+constexpr int kFTN = 2;             // triangles per thread per pass
 constexpr bool kFHeavyFirst = false;  // order tiles with entries by entry count
 constexpr unsigned kFSpinCap = 1u << 16;  // bound on every wait loop (about 5 ms)
 constexpr int kInvalidX = (int)0x80000000;
@@ -515,8 +518,8 @@ ORRB_INLINE bool tile_setup(const FrameLds &S, int k, int4 tri, int x0, int y0, 
     return true;
 }
 
+// (Hidden objects need no test: their vertices are all marked invalid.)
 ORRB_INLINE bool frame_setup(const FrameLds &S, int k, int4 tri, int cx0, int cy0, int cx1, int cy1, TriSetup &T) {
-    if (!S.o_vis[k]) return false;
     const int vb = S.o_vbase[k];
     const int i0v = vb + tri.x, i1v = vb + tri.y, i2v = vb + tri.z;
     const int x0 = S.X[i0v], x1 = S.X[i1v], x2 = S.X[i2v];
@@ -529,7 +532,10 @@ ORRB_INLINE bool frame_setup(const FrameLds &S, int k, int4 tri, int cx0, int cy
     T.j0 = max(ceil256(ymin - 128), cy0);
     T.j1 = min(floor256(ymax - 128), cy1);
     if (T.i0 > T.i1 || T.j0 > T.j1) return false;
-    const long long A = (long long)(x1 - x0) * (y2 - y0) - (long long)(y1 - y0) * (x2 - x0);
+    // exact area: 24-bit products when the extent allows (|A| < 2^29), else 64-bit
+    const long long A = max(xmax - xmin, ymax - ymin) <= kSmallExtent
+                            ? (long long)(__mul24(x1 - x0, y2 - y0) - __mul24(y1 - y0, x2 - x0))
+                            : (long long)(x1 - x0) * (y2 - y0) - (long long)(y1 - y0) * (x2 - x0);
     if (A >= 0) return false;
     T.xa = x0; T.ya = y0; T.xb = x2; T.yb = y2; T.xc = x1; T.yc = y1;
     T.va = i0v; T.vb = i2v; T.vc = i1v;
@@ -560,7 +566,9 @@ ORRB_INLINE void frame_vertex(FrameLds &S, int v, int k, float4 p, double fx, do
 
 // Per-tile counts and the survivor entry of a set-up triangle.
 ORRB_INLINE unsigned frame_count(FrameLds &S, int t, const TriSetup &T, int ntx) {
-    const int tx0 = T.i0 / kFTileW, tx1 = T.i1 / kFTileW, ty0 = T.j0 / kFTileH, ty1 = T.j1 / kFTileH;
+    // pixel ranges are clipped to the frame, so non-negative: plain shifts
+    const int tx0 = (unsigned)T.i0 / kFTileW, tx1 = (unsigned)T.i1 / kFTileW;
+    const int ty0 = (unsigned)T.j0 / kFTileH, ty1 = (unsigned)T.j1 / kFTileH;
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&S.cnt[ty * ntx + tx], 1);
     return ((unsigned)t << 16) | (unsigned)(tx0 | (tx1 << 2) | (ty0 << 4) | (ty1 << 10));
@@ -860,27 +868,36 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
             continue;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        // take kFChunk background tiles at once: one claim, one done-count per chunk
         const int slot = my % kFSlots;
-        int i = 0;
-        if (lane == 0) i = atomicAdd(&S.bg_next[slot], 1);
-        i = __shfl(i, 0);
+        int i0 = 0;
+        if (lane == 0) i0 = atomicAdd(&S.bg_next[slot], kFChunk);
+        i0 = __shfl(i0, 0);
         const BgFrame b = S.bgf[slot];
-        if (i >= b.n) {  // the frame's tiles are all taken
+        if (i0 >= b.n) {  // the frame's tiles are all taken
             ++my;
             if (store_wave && lane == 0) lds_store(&S.cons_seq[wave], my);
             continue;
         }
-        const int t = S.bg_tile[slot][i];
-        const int tyi = t / b.ntx, txi = t - tyi * b.ntx;
-        const int x0 = txi * kFTileW, y0 = tyi * kFTileH;
-        const int x1 = min(x0 + kFTileW, b.W) - 1, y1 = min(y0 + kFTileH, b.H) - 1;
-        const int j = y0 + lj, i0 = x0 + li0;
-        const int n_in = j <= y1 ? max(0, min(4, x1 - i0 + 1)) : 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        const int n_take = min(kFChunk, b.n - i0);
+        int tl[kFChunk];
+#pragma unroll
+        for (int c = 0; c < kFChunk; ++c) tl[c] = c < n_take ? S.bg_tile[slot][i0 + c] : 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");  // slot read
         __builtin_amdgcn_wave_barrier();
-        if (lane == 0) atomicAdd(&S.bg_done[slot], 1);
-        if (n_in > 0)
-            store_background4(a, b.po, (int64_t)b.W * b.H, (int64_t)j * b.W + i0, b.vec && n_in == 4, n_in);
+        if (lane == 0) atomicAdd(&S.bg_done[slot], n_take);
+        const int64_t HW = (int64_t)b.W * b.H;
+#pragma unroll
+        for (int c = 0; c < kFChunk; ++c) {
+            if (c >= n_take) break;
+            const int t = tl[c];
+            const int tyi = t / b.ntx, txi = t - tyi * b.ntx;
+            const int x0 = txi * kFTileW, y0 = tyi * kFTileH;
+            const int x1 = min(x0 + kFTileW, b.W) - 1, y1 = min(y0 + kFTileH, b.H) - 1;
+            const int j = y0 + lj, i0p = x0 + li0;
+            const int n_in = j <= y1 ? max(0, min(4, x1 - i0p + 1)) : 0;
+            if (n_in > 0) store_background4(a, b.po, HW, (int64_t)j * b.W + i0p, b.vec && n_in == 4, n_in);
+        }
         if (store_wave) store_pace();
     }
 }
@@ -942,7 +959,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     for (int b = tid; b * kFHint < n_verts; b += kFCT) S.vtx_hint[b] = (unsigned char)find_slot(S.o_vbase, n_obj, b * kFHint);
     frame_barrier(S, gen);
 
-    // ---- phase 1: vertices, two per thread per pass; the next pass's positions are
+    // ---- phase 1: vertices, kFVN per thread per pass; the next pass's positions are
     // loaded before the current pass is transformed, hiding the load latency ----
     {
         const float *K = a.intr + 4 * (int64_t)f;
@@ -953,55 +970,71 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             k = slot_hint(S.o_vbase, n_obj, S.vtx_hint, u);
             return a.mesh_pos[S.o_mvb[k] + (u - S.o_vbase[k])];
         };
-        int kn0 = 0, kn1 = 0;
-        float4 pn0 = make_float4(0.f, 0.f, 0.f, 0.f), pn1 = pn0;
-        if (n_verts > 0) {
-            pn0 = vload(tid, kn0);
-            pn1 = vload(tid + kFCT, kn1);
+        int kn[kFVN];
+        float4 pn[kFVN];
+#pragma unroll
+        for (int r = 0; r < kFVN; ++r) {
+            kn[r] = 0;
+            pn[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (n_verts > 0) pn[r] = vload(tid + r * kFCT, kn[r]);
         }
-        for (int v0 = tid; v0 - tid < n_verts; v0 += 2 * kFCT) {
-            const int v1 = v0 + kFCT;
-            const float4 p0 = pn0, p1 = pn1;
-            const int k0 = kn0, k1 = kn1;
-            if (v0 - tid + 2 * kFCT < n_verts) {
-                pn0 = vload(v0 + 2 * kFCT, kn0);
-                pn1 = vload(v1 + 2 * kFCT, kn1);
+        for (int base = 0; base < n_verts; base += kFVN * kFCT) {
+            float4 p[kFVN];
+            int k[kFVN];
+#pragma unroll
+            for (int r = 0; r < kFVN; ++r) {
+                p[r] = pn[r];
+                k[r] = kn[r];
             }
-            if (v0 < n_verts) frame_vertex(S, v0, k0, p0, fx, fy, cx, cy, nearp);
-            if (v1 < n_verts) frame_vertex(S, v1, k1, p1, fx, fy, cx, cy, nearp);
+            if (base + kFVN * kFCT < n_verts) {
+#pragma unroll
+                for (int r = 0; r < kFVN; ++r) pn[r] = vload(base + (kFVN + r) * kFCT + tid, kn[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < kFVN; ++r) {
+                const int v = base + r * kFCT + tid;
+                if (v < n_verts) frame_vertex(S, v, k[r], p[r], fx, fy, cx, cy, nearp);
+            }
         }
     }
     frame_barrier(S, gen);
 
-    // ---- phase 2: set-up, per-tile counts, survivor list; two triangles per thread per
-    // pass, the next pass's mesh triangles loaded ahead ----
+    // ---- phase 2: set-up, per-tile counts, survivor list; kFTN triangles per thread
+    // per pass, the next pass's mesh triangles loaded ahead ----
     {
         auto tload = [&](int t, int &k) {
             const int u = min(t, n_tris - 1);  // out-of-range lanes load the last triangle
             k = slot_hint(S.o_tbase, n_obj, S.tri_hint, u);
             return frame_tri(a, S, k, u);
         };
-        int kn0 = 0, kn1 = 0;
-        int4 tn0 = make_int4(0, 0, 0, 0), tn1 = tn0;
-        if (n_tris > 0) {
-            tn0 = tload(tid, kn0);
-            tn1 = tload(tid + kFCT, kn1);
+        int kn[kFTN];
+        int4 tn[kFTN];
+#pragma unroll
+        for (int r = 0; r < kFTN; ++r) {
+            kn[r] = 0;
+            tn[r] = make_int4(0, 0, 0, 0);
+            if (n_tris > 0) tn[r] = tload(tid + r * kFCT, kn[r]);
         }
-        for (int base = 0; base < n_tris; base += 2 * kFCT) {
-            const int t0 = base + tid, t1 = t0 + kFCT;
-            const int4 tr0 = tn0, tr1 = tn1;
-            const int k0 = kn0, k1 = kn1;
-            if (base + 2 * kFCT < n_tris) {
-                tn0 = tload(t0 + 2 * kFCT, kn0);
-                tn1 = tload(t1 + 2 * kFCT, kn1);
+        for (int base = 0; base < n_tris; base += kFTN * kFCT) {
+            int4 tr[kFTN];
+            int k[kFTN];
+#pragma unroll
+            for (int r = 0; r < kFTN; ++r) {
+                tr[r] = tn[r];
+                k[r] = kn[r];
             }
-            TriSetup T0, T1;
-            const bool keep0 = t0 < n_tris && frame_setup(S, k0, tr0, 0, 0, W - 1, H - 1, T0);
-            const bool keep1 = t1 < n_tris && frame_setup(S, k1, tr1, 0, 0, W - 1, H - 1, T1);
-            const unsigned e0 = keep0 ? frame_count(S, t0, T0, ntx) : 0u;
-            const unsigned e1 = keep1 ? frame_count(S, t1, T1, ntx) : 0u;
-            frame_append(S, keep0, e0, lane);
-            frame_append(S, keep1, e1, lane);
+            if (base + kFTN * kFCT < n_tris) {
+#pragma unroll
+                for (int r = 0; r < kFTN; ++r) tn[r] = tload(base + (kFTN + r) * kFCT + tid, kn[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < kFTN; ++r) {
+                const int t = base + r * kFCT + tid;
+                TriSetup T;
+                const bool keep = t < n_tris && frame_setup(S, k[r], tr[r], 0, 0, W - 1, H - 1, T);
+                const unsigned e = keep ? frame_count(S, t, T, ntx) : 0u;
+                frame_append(S, keep, e, lane);
+            }
         }
     }
     frame_barrier(S, gen);
@@ -1081,8 +1114,8 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, t);
             TriSetup T;
             if (!frame_setup(S, k, frame_tri(a, S, k, t), 0, 0, W - 1, H - 1, T)) continue;
-            for (int ty = T.j0 / kFTileH; ty <= T.j1 / kFTileH; ++ty)
-                for (int tx = T.i0 / kFTileW; tx <= T.i1 / kFTileW; ++tx)
+            for (int ty = (unsigned)T.j0 / kFTileH; ty <= (int)((unsigned)T.j1 / kFTileH); ++ty)
+                for (int tx = (unsigned)T.i0 / kFTileW; tx <= (int)((unsigned)T.i1 / kFTileW); ++tx)
                     S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)t;
         }
     }
@@ -1196,7 +1229,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                 const int c = (r0 + h) * kWave + lane;
                 if (c >= n_cov) continue;
                 const int p = list[c];
-                const int pi = x0 + p % kFTileW, pj = y0 + p / kFTileW;
+                const int pi = x0 + (int)((unsigned)p % kFTileW), pj = y0 + (int)((unsigned)p / kFTileW);
                 const unsigned long long key = vis[p];
                 const int tri = (int)(unsigned)(key & 0xffffffffu);
                 const float z = __uint_as_float((unsigned)(key >> 32));
