@@ -118,7 +118,7 @@ typedef struct {
 } orrb_layout_desc;
 
 /* Launch choices.  They change speed only: the output bits are the same for every
- * valid tuning.  Frames whose scene fits in LDS (<= 7040 vertices, <= 64 objects,
+ * valid tuning.  Frames whose scene fits in LDS (<= 6976 vertices, <= 48 objects,
  * < 65536 triangles, <= 256x256 pixels) can be rendered whole by one workgroup
  * ("frame path"); the others go through the tiled path (a vertex kernel, then one
  * workgroup per screen tile). */

@@ -392,18 +392,18 @@ __global__ __launch_bounds__(kBlock) void k_raster_shade(RenderArgs a) {
 
 constexpr int kFT = 1024;           // threads of a frame workgroup
 constexpr int kFW = kFT / kWave;    // 16 waves
-constexpr int kFVMax = 7040;        // scene vertices held in LDS
-constexpr int kFOMax = 64;          // scene objects
+constexpr int kFVMax = 6976;        // scene vertices held in LDS
+constexpr int kFOMax = 48;          // scene objects
 constexpr int kFTileW = 64;         // wave tile: 64 x 4 pixels, so that a wave's store
 constexpr int kFTileH = 4;          // instruction writes 256-byte row segments
 constexpr int kFTilesMax = 256;     // frames up to 256 x 256 (4 x 64 tiles)
-constexpr int kFBinMax = 8192;      // (tile, triangle) bin entries (hand scenes: < 7,000)
+constexpr int kFBinMax = 7680;      // (tile, triangle) bin entries (hand scenes: < 7,000)
 constexpr int kFSurvMax = 6144;     // survivors remembered between set-up and scatter (< 5,200)
 constexpr int kFHint = 64;          // elements per object-lookup hint
-constexpr int kFCW = 13;            // compute waves: geometry, raster, shading
+constexpr int kFCW = 12;            // compute waves: geometry, raster, shading
 constexpr int kFCT = kFCW * kWave;  // compute threads
 constexpr int kFSlots = 4;          // frames whose background tiles may be pending at once
-constexpr int kFStage = 2;          // staged busy tiles (compute -> store waves)
+constexpr int kFStage = 3;          // staged busy tiles (compute -> store waves)
 constexpr int kFPace = 60;          // store instructions in flight per store wave
 constexpr bool kFStageWave = true;  // the last wave writes only staged tiles
 constexpr int kFChunk = 1;          // background tiles a store wave takes at once
