@@ -406,10 +406,8 @@ constexpr int kFSlots = 4;          // frames whose background tiles may be pend
 constexpr int kFStage = 3;          // staged busy tiles (compute -> store waves)
 constexpr int kFPace = 60;          // store instructions in flight per store wave
 constexpr bool kFStageWave = true;  // the last wave writes only staged tiles
-constexpr int kFChunk = 1;          // background tiles a store wave takes at once
 constexpr int kFVN = 2;             // vertices per thread per pass
 constexpr int kFTN = 2;             // triangles per thread per pass
-constexpr bool kFHeavyFirst = false;  // order tiles with entries by entry count
 constexpr unsigned kFSpinCap = 1u << 16;  // bound on every wait loop (about 5 ms)
 constexpr int kInvalidX = (int)0x80000000;
 
@@ -868,36 +866,27 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
             continue;
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-        // take kFChunk background tiles at once: one claim, one done-count per chunk
         const int slot = my % kFSlots;
-        int i0 = 0;
-        if (lane == 0) i0 = atomicAdd(&S.bg_next[slot], kFChunk);
-        i0 = __shfl(i0, 0);
+        int i = 0;
+        if (lane == 0) i = atomicAdd(&S.bg_next[slot], 1);
+        i = __shfl(i, 0);
         const BgFrame b = S.bgf[slot];
-        if (i0 >= b.n) {  // the frame's tiles are all taken
+        if (i >= b.n) {  // the frame's tiles are all taken
             ++my;
             if (store_wave && lane == 0) lds_store(&S.cons_seq[wave], my);
             continue;
         }
-        const int n_take = min(kFChunk, b.n - i0);
-        int tl[kFChunk];
-#pragma unroll
-        for (int c = 0; c < kFChunk; ++c) tl[c] = c < n_take ? S.bg_tile[slot][i0 + c] : 0;
+        const int t = S.bg_tile[slot][i];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");  // slot read
         __builtin_amdgcn_wave_barrier();
-        if (lane == 0) atomicAdd(&S.bg_done[slot], n_take);
-        const int64_t HW = (int64_t)b.W * b.H;
-#pragma unroll
-        for (int c = 0; c < kFChunk; ++c) {
-            if (c >= n_take) break;
-            const int t = tl[c];
-            const int tyi = t / b.ntx, txi = t - tyi * b.ntx;
-            const int x0 = txi * kFTileW, y0 = tyi * kFTileH;
-            const int x1 = min(x0 + kFTileW, b.W) - 1, y1 = min(y0 + kFTileH, b.H) - 1;
-            const int j = y0 + lj, i0p = x0 + li0;
-            const int n_in = j <= y1 ? max(0, min(4, x1 - i0p + 1)) : 0;
-            if (n_in > 0) store_background4(a, b.po, HW, (int64_t)j * b.W + i0p, b.vec && n_in == 4, n_in);
-        }
+        if (lane == 0) atomicAdd(&S.bg_done[slot], 1);
+        const int tyi = t / b.ntx, txi = t - tyi * b.ntx;
+        const int x0 = txi * kFTileW, y0 = tyi * kFTileH;
+        const int x1 = min(x0 + kFTileW, b.W) - 1, y1 = min(y0 + kFTileH, b.H) - 1;
+        const int j = y0 + lj, i0 = x0 + li0;
+        const int n_in = j <= y1 ? max(0, min(4, x1 - i0 + 1)) : 0;
+        if (n_in > 0)
+            store_background4(a, b.po, (int64_t)b.W * b.H, (int64_t)j * b.W + i0, b.vec && n_in == 4, n_in);
         if (store_wave) store_pace();
     }
 }
@@ -1065,27 +1054,12 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             if (t < n_tiles) {
                 S.off[t] = run;
                 S.cnt[t] = run;  // becomes the scatter cursor
-                // without bins every tile is rasterized, in plain order; tiles without
-                // entries go last
-                if (overflow || c[q] == 0 || !kFHeavyFirst)
-                    S.order[overflow ? t : (c[q] > 0 ? run_ne : total_ne + t - run_ne)] = (unsigned char)t;
+                // without bins every tile is rasterized, in plain order; otherwise tiles
+                // with entries first
+                S.order[overflow ? t : (c[q] > 0 ? run_ne : total_ne + t - run_ne)] = (unsigned char)t;
             }
             run += c[q];
             run_ne += c[q] > 0;
-        }
-        if (!overflow && kFHeavyFirst) {
-            // tiles with entries by decreasing power-of-two class of their entry count, so
-            // the longest tiles start first and the waves finish together
-            int at = 0;
-            for (int cls = 13; cls >= 0; --cls) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const bool in = c[q] > 0 && 31 - __clz(c[q]) == cls;
-                    const unsigned long long m = __ballot(in);
-                    if (in) S.order[at + lanes_below(m)] = (unsigned char)(lane * 4 + q);
-                    at += __popcll(m);
-                }
-            }
         }
         if (lane == kWave - 1) {
             S.off[n_tiles] = incl;
