@@ -4,14 +4,19 @@
 // every arithmetic primitive below (vertex snapping, edge functions, fragment depth,
 // shading), compiled with floating-point contraction off.
 //
-// Frame path (k_frame), for frames whose scene fits in LDS: one 1024-thread workgroup
-// renders a whole frame with no intermediate data in global memory:
+// Frame path (k_frame), for frames whose scene fits in LDS: a persistent kernel, one
+// 1024-thread workgroup per CU rendering frames one after another with no intermediate
+// data in global memory.  Twelve compute waves, per frame:
 //   1. transform and snap every vertex of the scene (FP64) into LDS;
 //   2. set up every triangle once (exact area, back-face and range cull) and count, per
 //      64x4 screen tile, the triangles whose pixel-centre range touches it;
-//   3. scan the counts and scatter 16-bit triangle IDs into per-tile LDS bins;
-//   4. each wave takes tiles from an LDS counter, rasterizes the tile's bin into its own
-//      256-key LDS visibility tile (ds_min_u64), then shades and writes the tile.
+//   3. scan the counts, hand the tiles no triangle touches to the store waves, and
+//      scatter 16-bit triangle IDs into per-tile LDS bins;
+//   4. take tiles with entries from an LDS counter, rasterize each bin into a 256-key
+//      LDS visibility tile (ds_min_u64), shade the covered pixels and put the finished
+//      tile into an LDS staging slot.
+// The other four waves issue every global store: the background of handed-over tiles
+// (while the compute waves go on with the next frame) and the staged tiles.
 //
 // Tiled path (k_vertex + k_raster_shade), for any scene size:
 //   k_vertex        one workgroup per (frame, object): FP64 transform and snap into a
