@@ -131,6 +131,19 @@ struct TileLds {
     int misc[16];  // [0] bin count, [1] next item, [4..8) scan, [8..12) wave counts
 };
 
+// Inclusive sum over the 64 lanes of a wave with DPP: shifts by 1, 2, 4 and 8 inside
+// each 16-lane row, then the last lane of row 0 into row 1 and of row 2 into row 3, then
+// lane 31 into rows 2 and 3 (lanes without a source add 0).
+ORRB_INLINE int wave_scan_add(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
 // Exclusive scan over n <= 4 * kBlock counts; writes pre[0..n].
 template <class F>
 ORRB_INLINE void block_scan(F cnt, int n, int *pre, int *wave_tot) {
@@ -140,12 +153,7 @@ ORRB_INLINE void block_scan(F cnt, int n, int *pre, int *wave_tot) {
     int local = 0;
     for (int k = 0; k < per; ++k)
         if (start + k < n) local += cnt(start + k);
-    int incl = local;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int y = __shfl_up(incl, off);
-        if (lane >= off) incl += y;
-    }
+    const int incl = wave_scan_add(local);
     if (lane == kWave - 1) wave_tot[wave] = incl;
     __syncthreads();
     int wbase = 0;
@@ -277,7 +285,7 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
             const unsigned long long m = __ballot(keep);
             int wb = 0;
             if (lane == 0 && m) wb = atomicAdd(&L.misc[0], __popcll(m));
-            wb = __shfl(wb, 0);
+            wb = __builtin_amdgcn_readlane(wb, 0);
             if (keep) {
                 const int slot = wb + lanes_below(m);
                 L.b_tri[slot] = tri_id;
@@ -581,7 +589,7 @@ ORRB_INLINE void frame_append(FrameLds &S, bool keep, unsigned entry, int lane) 
     const unsigned long long m = __ballot(keep);
     int wb = 0;
     if (lane == 0 && m) wb = atomicAdd(&S.misc[3], __popcll(m));
-    wb = __shfl(wb, 0);
+    wb = __builtin_amdgcn_readlane(wb, 0);
     if (keep) {
         const int slot = wb + lanes_below(m);
         if (slot < kFSurvMax) S.u.surv[slot] = entry;
@@ -728,7 +736,7 @@ ORRB_INLINE int stage_begin(FrameLds &S, int lane, int lj, int li0) {
             __builtin_amdgcn_s_sleep(1);
         }
     }
-    s = __shfl(s, 0);
+    s = __builtin_amdgcn_readlane(s, 0);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     const int p = lj * kFTileW + li0;
     uint4 z4;
@@ -863,10 +871,10 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
                 __builtin_amdgcn_s_sleep(2);
             }
         }
-        action = __shfl(action, 0);
+        action = __builtin_amdgcn_readlane(action, 0);
         if (!action) break;
         if (action == 1) {
-            stage_write(a, S, __shfl(st, 0), lj, li0, lane);
+            stage_write(a, S, __builtin_amdgcn_readlane(st, 0), lj, li0, lane);
             if (store_wave && !staged_only) store_pace();
             continue;
         }
@@ -874,7 +882,7 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
         const int slot = my % kFSlots;
         int i = 0;
         if (lane == 0) i = atomicAdd(&S.bg_next[slot], 1);
-        i = __shfl(i, 0);
+        i = __builtin_amdgcn_readlane(i, 0);
         const BgFrame b = S.bgf[slot];
         if (i >= b.n) {  // the frame's tiles are all taken
             ++my;
@@ -1041,17 +1049,9 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             local += c[q];
             ne += c[q] > 0;
         }
-        int incl = local, incl_ne = ne;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int y = __shfl_up(incl, o), yn = __shfl_up(incl_ne, o);
-            if (lane >= o) {
-                incl += y;
-                incl_ne += yn;
-            }
-        }
-        const int total_ne = __shfl(incl_ne, kWave - 1);
-        const bool overflow = __shfl(incl, kWave - 1) > kFBinMax;
+        const int incl = wave_scan_add(local), incl_ne = wave_scan_add(ne);
+        const int total_ne = __builtin_amdgcn_readlane(incl_ne, kWave - 1);
+        const bool overflow = __builtin_amdgcn_readlane(incl, kWave - 1) > kFBinMax;
         int run = incl - local, run_ne = incl_ne - ne;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1111,7 +1111,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     while (true) {
         int slot = 0;
         if (lane == 0) slot = atomicAdd(&S.misc[0], 1);
-        slot = __shfl(slot, 0);
+        slot = __builtin_amdgcn_readlane(slot, 0);
         if (slot >= n_busy) break;
         const int t = S.order[slot];
         const int tyi = t / ntx, txi = t - tyi * ntx;
