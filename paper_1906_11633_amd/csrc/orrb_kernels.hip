@@ -779,6 +779,31 @@ ORRB_INLINE void stage_end(FrameLds &S, int s, int64_t po, int W, int H, int x0,
     if (lane == 0) lds_store(&S.stage_state[s], 1);
 }
 
+// Touch the tables phase 0 of work item `item` reads (frame, objects, poses, materials,
+// view, intrinsics, lights), so that the next frame's set-up finds them in the caches
+// instead of waiting on memory behind the store traffic.  Called by the first compute
+// wave that runs out of tiles, while the others finish theirs.
+ORRB_INLINE void frame_warm(const RenderArgs &a, int item, int lane) {
+    if (item >= a.n_fitems) return;
+    const int f = a.fitems[item];
+    const FrameInfo fi = a.frames[f];
+    int acc = 0;
+    if (lane < fi.n_obj) {
+        const int o = fi.obj_begin + lane;
+        const float *pose = a.pose + 12 * (int64_t)o;
+        acc += a.objs[o].n_verts + a.seg[o] + a.visible[o] + __float_as_int(pose[0]) + __float_as_int(pose[11]) +
+               __float_as_int(a.roughness[o]) + __float_as_int(a.specular[o]) + __float_as_int(a.albedo[3 * o]);
+    }
+    if (lane < fi.n_lights) {
+        const int l = fi.light_begin + lane;
+        acc += a.light_type[l] + __float_as_int(a.light_vec[3 * l]) + __float_as_int(a.light_intensity[l]);
+    }
+    if (lane == 0)
+        acc += __float_as_int(a.view[12 * (int64_t)f]) + __float_as_int(a.view[12 * (int64_t)f + 11]) +
+               __float_as_int(a.intr[4 * (int64_t)f]) + __float_as_int(a.near_plane[f]) + __float_as_int(a.exposure[f]);
+    asm volatile("" ::"v"(acc));
+}
+
 // Store wave: write staged tile s (every output plane) and free the slot.
 ORRB_INLINE void stage_write(const RenderArgs &a, FrameLds &S, int s, int lj, int li0, int lane) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
@@ -1112,7 +1137,10 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         int slot = 0;
         if (lane == 0) slot = atomicAdd(&S.misc[0], 1);
         slot = __builtin_amdgcn_readlane(slot, 0);
-        if (slot >= n_busy) break;
+        if (slot >= n_busy) {
+            if (slot == n_busy) frame_warm(a, item + gridDim.x, lane);
+            break;
+        }
         const int t = S.order[slot];
         const int tyi = t / ntx, txi = t - tyi * ntx;
         const int x0 = txi * kFTileW, y0 = tyi * kFTileH;
@@ -1124,7 +1152,10 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         for (int q = 0; q < 4; ++q) vis[lane + 64 * q] = kEmptyKey;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        // without bins (overflow) the wave scans every triangle of the scene
+        // Keys in the LDS tile carry the triangle's object slot in bits 16..23 above its
+        // 16-bit ID: slots do not decrease with the ID, so the (depth, ID) order is
+        // unchanged, shading needs no object lookup, and the bits are cleared before the
+        // key leaves the tile.  Without bins (overflow) the wave scans every triangle.
         const int e0 = overflow ? 0 : S.off[t], e1 = overflow ? n_tris : S.off[t + 1];
         for (int e = e0 + lane; e < e1; e += kWave) {
             const int tri = overflow ? e : (int)S.bin[e];
@@ -1151,7 +1182,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                             ed.e0 = (float)e0;
                             ed.e1 = (float)e1;
                             ed.e2 = (float)e2;
-                            atomicMin(&vis[(jj - y0) * kFTileW + (ii - x0)], vis_key(fragment_depth(ed, iwa, iwb, iwc, area), tri));
+                            atomicMin(&vis[(jj - y0) * kFTileW + (ii - x0)], vis_key(fragment_depth(ed, iwa, iwb, iwc, area), tri | (k << 16)));
                         }
                         e0 += es.dx0;
                         e1 += es.dx1;
@@ -1166,7 +1197,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                     for (int ii = T.i0; ii <= T.i1; ++ii) {
                         const Edges ed = edge_eval(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc, (ii << 8) + 128, (jj << 8) + 128, flags);
                         if (!ed.covered) continue;
-                        atomicMin(&vis[(jj - y0) * kFTileW + (ii - x0)], vis_key(fragment_depth(ed, iwa, iwb, iwc, area), tri));
+                        atomicMin(&vis[(jj - y0) * kFTileW + (ii - x0)], vis_key(fragment_depth(ed, iwa, iwb, iwc, area), tri | (k << 16)));
                     }
                 }
             }
@@ -1210,16 +1241,15 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                 const int p = list[c];
                 const int pi = x0 + (int)((unsigned)p % kFTileW), pj = y0 + (int)((unsigned)p / kFTileW);
                 const unsigned long long key = vis[p];
-                const int tri = (int)(unsigned)(key & 0xffffffffu);
+                const int tri = (int)(unsigned)(key & 0xffffu), k = (int)(unsigned)((key >> 16) & 0xffu);
                 const float z = __uint_as_float((unsigned)(key >> 32));
-                const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, tri);
                 const int4 tv = frame_tri(a, S, k, tri);
                 const int vb = S.o_vbase[k], mvb = S.o_mvb[k];
                 const int va = vb + tv.x, vbb = vb + tv.z, vc = vb + tv.y;  // positive-area order
                 o[h] = shade_pixel(S.X[va], S.Y[va], S.X[vbb], S.Y[vbb], S.X[vc], S.Y[vc], S.iw[va], S.iw[vbb], S.iw[vc],
                                    a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], S.o_R[k], pi, pj,
                                    z, cam, S.light, S.light_type, fi.n_lights, S.o_mat[k]);
-                kk[h] = key;
+                kk[h] = key & ~0xffff0000ull;
                 sg[h] = S.o_seg[k];
                 pl[h] = p;
                 __builtin_amdgcn_sched_barrier(0);  // shade the two pixels one after the other
