@@ -420,7 +420,7 @@ constexpr int kFStage = 3;          // staged busy tiles (compute -> store waves
 constexpr int kFPace = 60;          // store instructions in flight per store wave
 constexpr bool kFStageWave = true;  // the last wave writes only staged tiles
 constexpr int kFVN = 2;             // vertices per thread per pass
-constexpr int kFTN = 2;             // triangles per thread per pass
+constexpr int kFTN = 3;             // triangles per thread per pass
 constexpr unsigned kFSpinCap = 1u << 16;  // bound on every wait loop (about 5 ms)
 constexpr int kInvalidX = (int)0x80000000;
 
@@ -483,8 +483,17 @@ bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height) {
 // 64-element block and step forward over the objects that begin at or before x.
 ORRB_INLINE int slot_hint(const int *base, int n, const unsigned char *hint, int x) {
     int k = hint[x / kFHint];
+    if (k & 0x80) return k & 0x7f;  // the whole block lies in one object
     while (k + 1 < n && base[k + 1] <= x) ++k;
     return k;
+}
+
+// Hint of block b: the object holding element b * kFHint, bit 7 set when no other
+// object starts inside the block.
+ORRB_INLINE unsigned char object_hint(const int *base, int n, int b) {
+    const int k = find_slot(base, n, b * kFHint);
+    const bool one = k + 1 >= n || base[k + 1] > b * kFHint + kFHint - 1;
+    return (unsigned char)(k | (one ? 0x80 : 0));
 }
 
 // Scene triangle t of object k and its mesh triangle (mesh-local vertex indices).
@@ -982,8 +991,8 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     const int n_verts = n_obj > 0 ? a.objs[fi.obj_begin + n_obj - 1].scene_vbase + a.objs[fi.obj_begin + n_obj - 1].n_verts : 0;
     frame_barrier(S, gen);
     const int n_tris = n_obj > 0 ? S.o_tbase[n_obj - 1] + S.o_nt[n_obj - 1] : 0;
-    for (int b = tid; b * kFHint < n_tris; b += kFCT) S.tri_hint[b] = (unsigned char)find_slot(S.o_tbase, n_obj, b * kFHint);
-    for (int b = tid; b * kFHint < n_verts; b += kFCT) S.vtx_hint[b] = (unsigned char)find_slot(S.o_vbase, n_obj, b * kFHint);
+    for (int b = tid; b * kFHint < n_tris; b += kFCT) S.tri_hint[b] = object_hint(S.o_tbase, n_obj, b);
+    for (int b = tid; b * kFHint < n_verts; b += kFCT) S.vtx_hint[b] = object_hint(S.o_vbase, n_obj, b);
     frame_barrier(S, gen);
 
     // ---- phase 1: vertices, kFVN per thread per pass; the next pass's positions are
