@@ -31,6 +31,9 @@
 // nearest fragment wins and exact depth ties go to the lower ID.  Being a 64-bit
 // minimum, the result does not depend on the order in which lanes, bins, tiles or
 // workgroups run: outputs are bit-identical for every tuning and batch composition.
+// (Inside k_frame's LDS tile the ID field also carries the object slot above the 16-bit
+// ID; slots never decrease with the ID, so the order is the same, and the slot bits are
+// cleared before a key is written out.)
 #include "orrb_primitives.h"
 
 namespace orrb {
