@@ -735,7 +735,7 @@ ORRB_INLINE void frame_publish(const RenderArgs &a, FrameLds &S, int seq, int64_
 // ---- staged busy tiles: a compute wave fills a slot, a store wave writes it out ----
 
 // Claim a free staging slot and fill it with the background for the whole tile (each
-// lane its 4-pixel group).  Waits while both slots are in use.
+// lane its 4-pixel group).  Waits while every slot is in use.
 ORRB_INLINE int stage_begin(FrameLds &S, int lane, int lj, int li0) {
     int s = 0;
     if (lane == 0) {
@@ -1236,10 +1236,9 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
 
-        // shade the covered pixels, lane-compacted (lane takes list[lane + 64 r]); all
-        // loads of the tile precede its stores
-        // shade the covered pixels in passes of (up to) two per lane and put them, over
-        // the tile's background, into a staging slot that a store wave writes out
+        // shade the covered pixels, lane-compacted (lane takes list[lane + 64 r]), in
+        // passes of (up to) two per lane and put them, over the tile's background, into a
+        // staging slot that a store wave writes out
         int stg = -1;
         for (int r0 = 0; r0 * kWave < n_cov; r0 += 2) {
             PixelOut o[2];
