@@ -424,9 +424,10 @@ constexpr int kFPace = 60;          // store instructions in flight per store wa
 constexpr bool kFStageWave = true;  // the last wave writes only staged tiles
 constexpr int kFVN = 2;             // vertices per thread per pass
 constexpr int kFTN = 3;             // triangles per thread per pass
-constexpr unsigned kFSpinCap = 1u << 16;  // bound on every wait loop (about 5 ms): reached
-                                          // only if a peer wave stalls; the kernel then ends
-                                          // with unspecified pixels rather than hanging
+constexpr unsigned kFSpinCap = 1u << 22;  // bound on every wait loop (about 0.3 s, far beyond
+                                          // the slowest legitimate tile): reached only if a
+                                          // peer wave stalls; the kernel then ends with
+                                          // unspecified pixels rather than hanging
 constexpr int kInvalidX = (int)0x80000000;
 
 struct BgFrame {
