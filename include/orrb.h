@@ -284,6 +284,15 @@ orrb_status orrb_profile_enable(orrb_context *ctx, int enable);
 /* Wait for the recorded events and return the totals since the last enable. */
 orrb_status orrb_profile_read(orrb_context *ctx, orrb_kernel_times *out);
 
+/* Number of waits inside the frame kernel (compute-wave barrier, staging slot,
+ * background publication, store-wave polling) that reached their bound on the
+ * context's device since the library was loaded.  Each wait is bounded (about 0.3 s)
+ * so that a stalled wave cannot hang the GPU; a non-zero count means some frames of
+ * the renders since then hold unspecified pixels.  Synchronizes with the device (reads
+ * a device counter, all streams); cumulative, never reset.  Errors:
+ * ORRB_ERR_INVALID_ARGUMENT for NULL arguments, ORRB_ERR_DEVICE if the read fails. */
+orrb_status orrb_wait_timeouts(orrb_context *ctx, uint64_t *count_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,7 @@ SIGNATURES = {
                                       C.POINTER(Grads), P, C.c_size_t, P]),
     "orrb_profile_enable": (C.c_int, [P, C.c_int]),
     "orrb_profile_read": (C.c_int, [P, C.POINTER(KernelTimes)]),
+    "orrb_wait_timeouts": (C.c_int, [P, C.POINTER(C.c_uint64)]),
 }
 
 _lock = threading.Lock()

@@ -107,6 +107,7 @@ void context_set_profiling(orrb_context *ctx, bool on);
 hipError_t launch_vertex(const RenderArgs &a, hipStream_t stream);
 hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu);
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu);
+hipError_t read_wait_timeouts(unsigned int *out);  // frame-kernel waits that hit their bound
 bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height);
 size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap);
 

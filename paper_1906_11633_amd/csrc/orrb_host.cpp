@@ -785,6 +785,16 @@ orrb_status orrb_profile_enable(orrb_context *ctx, int enable) {
     return ORRB_OK;
 }
 
+orrb_status orrb_wait_timeouts(orrb_context *ctx, uint64_t *count_out) {
+    g_last_error.clear();
+    if (!ctx || !count_out) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL argument");
+    ScopedDevice sd(ctx->device);
+    unsigned int n = 0;
+    HIP_TRY(read_wait_timeouts(&n));
+    *count_out = n;
+    return ORRB_OK;
+}
+
 orrb_status orrb_profile_read(orrb_context *ctx, orrb_kernel_times *out) {
     g_last_error.clear();
     if (!ctx || !out) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL argument");

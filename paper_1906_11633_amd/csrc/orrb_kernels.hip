@@ -678,6 +678,12 @@ ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, 
 // from per-slot counters and write them while the compute waves go on.  Every wait is
 // bounded by kFSpinCap polls.
 
+// Waits that reached kFSpinCap on this device since the library was loaded (their
+// frames' pixels are unspecified); read by orrb_wait_timeouts.
+__device__ unsigned int g_wait_timeouts;
+
+ORRB_INLINE void note_wait_timeout() { atomicAdd(&g_wait_timeouts, 1u); }
+
 ORRB_INLINE int lds_load(const int *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP); }
 ORRB_INLINE void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); }
 
@@ -686,7 +692,9 @@ ORRB_INLINE void frame_barrier(FrameLds &S, int &gen) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     if (lane_id() == 0) {
         atomicAdd(&S.cbar, 1);
-        for (unsigned spin = 0; lds_load(&S.cbar) < gen && spin < kFSpinCap; ++spin) __builtin_amdgcn_s_sleep(1);
+        unsigned spin = 0;
+        for (; lds_load(&S.cbar) < gen && spin < kFSpinCap; ++spin) __builtin_amdgcn_s_sleep(1);
+        if (spin == kFSpinCap) note_wait_timeout();
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
@@ -707,12 +715,14 @@ ORRB_INLINE void frame_publish(const RenderArgs &a, FrameLds &S, int seq, int64_
                                int n_tiles, int lane) {
     const int slot = seq % kFSlots, n_empty = n_tiles - n_busy;
     if (lane == 0 && seq >= kFSlots) {
-        for (unsigned spin = 0; spin < kFSpinCap; ++spin) {
+        unsigned spin = 0;
+        for (; spin < kFSpinCap; ++spin) {
             bool free = lds_load(&S.bg_done[slot]) >= S.bgf[slot].n;
             for (int w = kFCW; w < kFW; ++w) free = free && lds_load(&S.cons_seq[w]) > seq - kFSlots;
             if (free) break;
             __builtin_amdgcn_s_sleep(2);
         }
+        if (spin == kFSpinCap) note_wait_timeout();
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
@@ -740,7 +750,8 @@ ORRB_INLINE void frame_publish(const RenderArgs &a, FrameLds &S, int seq, int64_
 ORRB_INLINE int stage_begin(FrameLds &S, int lane, int lj, int li0) {
     int s = 0;
     if (lane == 0) {
-        for (unsigned spin = 0; spin < kFSpinCap; ++spin) {
+        unsigned spin = 0;
+        for (; spin < kFSpinCap; ++spin) {
             int k = 0;
             for (; k < kFStage; ++k)
                 if (lds_load(&S.stage_state[k]) == 0 && atomicCAS(&S.stage_state[k], 0, 2) == 0) break;
@@ -750,6 +761,7 @@ ORRB_INLINE int stage_begin(FrameLds &S, int lane, int lj, int li0) {
             }
             __builtin_amdgcn_s_sleep(1);
         }
+        if (spin == kFSpinCap) note_wait_timeout();
     }
     s = __builtin_amdgcn_readlane(s, 0);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
@@ -890,7 +902,8 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
         // 1: staged tile st claimed, 2: frame my is published, 0: nothing more will come
         int action = 0, st = 0;
         if (lane == 0) {
-            for (unsigned spin = 0; spin < kFSpinCap; ++spin) {
+            unsigned spin = 0;
+            for (; spin < kFSpinCap; ++spin) {
                 for (int k = 0; k < kFStage && !action; ++k)
                     if (lds_load(&S.stage_state[k]) == 1 && atomicCAS(&S.stage_state[k], 1, 3) == 1) {
                         action = 1;
@@ -910,6 +923,7 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
                 }
                 __builtin_amdgcn_s_sleep(2);
             }
+            if (spin == kFSpinCap) note_wait_timeout();
         }
         action = __builtin_amdgcn_readlane(action, 0);
         if (!action) break;
@@ -1287,6 +1301,10 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
 // ------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------
+
+hipError_t read_wait_timeouts(unsigned int *out) {
+    return hipMemcpyFromSymbol(out, HIP_SYMBOL(g_wait_timeouts), sizeof(unsigned int));
+}
 
 size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap) {
     const size_t vis = sizeof(unsigned long long) * (size_t)tile_w * tile_h;

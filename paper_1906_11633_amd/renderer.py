@@ -62,6 +62,13 @@ class Context:
         self._keep.append(mesh)
         return mid.value
 
+    def wait_timeouts(self) -> int:
+        """Frame-kernel waits that reached their bound on this device so far (0 unless
+        a wave stalled; non-zero means some rendered pixels are unspecified)."""
+        n = C.c_uint64()
+        L.check(self.lib.orrb_wait_timeouts(self.handle, C.byref(n)))
+        return int(n.value)
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.orrb_destroy(self.handle)

@@ -83,6 +83,7 @@ def test_null_arguments_rejected(lib):
     assert lib.orrb_add_mesh(None, None, None, 3, None, 1, C.byref(mid)) == 1
     assert lib.orrb_render_batch(None, None, None, None, None, None, None, 0, None) == 1
     assert lib.orrb_layout_info_get(None, None) == 1
+    assert lib.orrb_wait_timeouts(None, None) == 1
     lib.orrb_destroy(None)
     lib.orrb_layout_destroy(None)
 

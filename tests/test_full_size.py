@@ -59,6 +59,7 @@ def test_config2_full_size_sampled(renderer):
     torch.cuda.synchronize()
     st = _check(b, out, _sample(256, 4, 11))
     assert st["covered"] > 10000
+    assert renderer.ctx.wait_timeouts() == 0  # no frame-kernel wait reached its bound
 
 
 def test_uneven_full_size_sampled(renderer):
@@ -78,3 +79,4 @@ def test_uneven_full_size_sampled(renderer):
     scenes = sorted(set(_sample(1024, 3, 12)) | {int(tris.argmax())})
     st = _check(b, out, scenes)
     assert st["covered"] > 1000
+    assert renderer.ctx.wait_timeouts() == 0

@@ -79,11 +79,13 @@ def test_frame_path_bin_overflow(renderer):
     extra = [(mesh, S.make_pose(R, (0.02, -0.03, -2.2), 1.0)), (mesh, S.make_pose(R.T, (-0.01, 0.02, -2.4), 1.0))]
     b = S.single_object_batch(mesh, S.make_pose(np.eye(3), (0.0, 0.0, -2.0), 1.0), res=(256, 256), extra_objects=extra,
                               lights=((0, (0.3, 0.4, 0.5), 1.5),), spec=0.4, rough=0.5)
+    before = renderer.ctx.wait_timeouts()
     gpu, job = _render(renderer, b)
     assert job.layout.info.frame_path_frames == 1
     stats = parity.compare(b, gpu, oracle.render(b))
     print(stats)
     assert stats["covered"] > 50000
+    assert renderer.ctx.wait_timeouts() == before  # the slowest tiles stay far inside the bound
 
 
 def test_frame_path_survivor_overflow(renderer):
