@@ -246,7 +246,7 @@ typedef struct {                  /* device destinations, overwritten (not accum
     float *albedo;                /* [O,3] */
     float *roughness;             /* [O] */
     float *specular;              /* [O] */
-    float *light_pos;             /* [L,3] world-space position (0 for directional lights) */
+    float *light_vec;             /* [L,3] world-space position (0 for directional lights) */
     float *light_intensity;       /* [L] */
     float *exposure;              /* [F] */
 } orrb_grads;

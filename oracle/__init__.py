@@ -44,19 +44,24 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
+def open_library(path: str):
+    """Open a compiled oracle library and declare its entry points."""
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    inputs = [P] * 17 + [C.c_int32] + [P] * 8
+    lib.oracle_render.argtypes = inputs + [P] * 7 + [C.c_int32]
+    lib.oracle_render.restype = C.c_int
+    lib.oracle_shade_grad.argtypes = inputs + [C.c_int32, P, P, P, P, P, P, P, P, P, P, C.c_int32]
+    lib.oracle_shade_grad.restype = C.c_int
+    return lib
+
+
 def _load():
     global _lib
     with _lock:
         if _lib is None:
             build()
-            lib = C.CDLL(_LIB_PATH)
-            P = C.c_void_p
-            inputs = [P] * 17 + [C.c_int32] + [P] * 8
-            lib.oracle_render.argtypes = inputs + [P] * 7 + [C.c_int32]
-            lib.oracle_render.restype = C.c_int
-            lib.oracle_shade_grad.argtypes = inputs + [C.c_int32, P, P, P, P, P, P, P, P, P, P, C.c_int32]
-            lib.oracle_shade_grad.restype = C.c_int
-            _lib = lib
+            _lib = open_library(_LIB_PATH)
     return _lib
 
 
@@ -149,8 +154,9 @@ def shade_grad(batch, target_rgb=None, pixel_weight=None, threads: int = 0, dl_d
     With ``dl_drgb`` (planar like rgb, [3 * total_pixels]) the loss is the linear
     sum w_px dl_drgb . rgb instead and ``target_rgb`` is ignored.
 
-    Returns (loss, dict(albedo [O,3], roughness [O], specular [O], light_pos [L,3],
-    light_intensity [L], exposure [F]))."""
+    Returns (loss, dict(albedo [O,3], roughness [O], specular [O], light_vec [L,3]
+    (world-space gradient of each light's vector: position of a point light,
+    direction of a directional light), light_intensity [L], exposure [F]))."""
     pk = _pack(batch)
     P = pk.total_pixels
     if dl_drgb is not None:
@@ -171,11 +177,11 @@ def shade_grad(batch, target_rgb=None, pixel_weight=None, threads: int = 0, dl_d
     O = int(pk.object_mesh.shape[0])
     L = int(pk.light_type.shape[0])
     g = dict(albedo=np.zeros((O, 3)), roughness=np.zeros(O), specular=np.zeros(O),
-             light_pos=np.zeros((L, 3)), light_intensity=np.zeros(L), exposure=np.zeros(pk.n_frames))
+             light_vec=np.zeros((L, 3)), light_intensity=np.zeros(L), exposure=np.zeros(pk.n_frames))
     loss = np.zeros(1)
     rc = _load().oracle_shade_grad(*pk.args(), pk.n_scenes, _ptr(target), _ptr(wmask), _ptr(upstream),
                                    _ptr(loss), _ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]),
-                                   _ptr(g["light_pos"]), _ptr(g["light_intensity"]), _ptr(g["exposure"]),
+                                   _ptr(g["light_vec"]), _ptr(g["light_intensity"]), _ptr(g["exposure"]),
                                    int(threads))
     if rc != 0:
         raise MemoryError("oracle_shade_grad failed")

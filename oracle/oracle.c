@@ -273,6 +273,7 @@ static void fragment(const Inputs *in, int f, Vert **vt_of, const Pix *q, int i,
 typedef struct {
     int type;      /* 0 point, 1 directional */
     double q[3];   /* point: view-space position; directional: unit direction to the light */
+    double qn;     /* directional: |R_V u| before normalization (1 for point lights) */
     double I;
 } VLight;
 
@@ -286,10 +287,12 @@ static void view_lights(const Inputs *in, int f, VLight *L, int *nL) {
         const double *u = in->light_vec + 3 * (int64_t)l;
         x->type = in->light_type[l];
         x->I = in->light_intensity[l];
+        x->qn = 1.0;
         if (x->type == 0) {
             for (int r = 0; r < 3; r++) x->q[r] = V[r * 4 + 0] * u[0] + V[r * 4 + 1] * u[1] + V[r * 4 + 2] * u[2] + V[r * 4 + 3];
         } else {
             for (int r = 0; r < 3; r++) x->q[r] = -(V[r * 4 + 0] * u[0] + V[r * 4 + 1] * u[1] + V[r * 4 + 2] * u[2]);
+            x->qn = sqrt(dot3(x->q, x->q));
             normalize3(x->q);
         }
     }
@@ -469,15 +472,15 @@ int oracle_render(INPUT_ARGS, double *rgb, double *depth, double *normal, int32_
 
 /* Loss L = sum over frames, pixels and channels of w_px (rgb - target)^2, and its
  * analytic gradient over the fixed visibility with respect to per-object albedo (3),
- * roughness and specular, per-light position (world, 3) and intensity, and per-frame
- * exposure.  w_px is pixel_weight[px] (0/1, NULL = all 1).  Gradients are overwritten.
+ * roughness and specular, per-light vector (world, 3: the position of a point light,
+ * the direction of a directional light) and intensity, and per-frame exposure.  w_px is pixel_weight[px] (0/1, NULL = all 1).  Gradients are overwritten.
  * When dl_drgb is not NULL the loss is linear instead, L = sum w_px dl_drgb . rgb
  * (planar like rgb, target ignored): the adjoint is then that of a fixed upstream
  * gradient, which is what a backward pass receives from the layers above it.
  * Scenes are processed in parallel; within a scene, frames and pixels are summed in
  * order, so the result is deterministic. */
 int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const uint8_t *pixel_weight,
-                      const double *dl_drgb, double *loss_out, double *g_albedo, double *g_rough, double *g_spec, double *g_lightpos,
+                      const double *dl_drgb, double *loss_out, double *g_albedo, double *g_rough, double *g_spec, double *g_lightvec,
                       double *g_intensity, double *g_exposure, int32_t n_threads) {
     FILL_INPUTS(in);
     int err = 0;
@@ -487,7 +490,7 @@ int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const 
     memset(g_albedo, 0, sizeof(double) * 3 * (size_t)n_obj);
     memset(g_rough, 0, sizeof(double) * (size_t)n_obj);
     memset(g_spec, 0, sizeof(double) * (size_t)n_obj);
-    memset(g_lightpos, 0, sizeof(double) * 3 * (size_t)n_light);
+    memset(g_lightvec, 0, sizeof(double) * 3 * (size_t)n_light);
     memset(g_intensity, 0, sizeof(double) * (size_t)n_light);
     memset(g_exposure, 0, sizeof(double) * (size_t)n_frames);
     set_threads(n_threads);
@@ -556,7 +559,24 @@ int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const 
                         for (int c = 0; c < 3; c++) Gh += g[c] * (alb[c] + ks * x->s);
                         double dA_dI = L[l].type == 0 ? 1.0 / (x->D > LIGHT_EPS ? x->D : LIGHT_EPS) : 1.0;
                         g_intensity[lb + l] += e * Gh * x->ndl * dA_dI;
-                        if (L[l].type != 0) continue;
+                        if (L[l].type != 0) {
+                            /* directional light: l = a / |a| with a = -R_V u.  The shade
+                             * depends on l through n.l and through h = (l + v) / |l + v|:
+                             * dL/dl = e [Gh A n + G A ndl k_s m ndh^(m-1) (n - ndh h) / |l+v|],
+                             * then dL/da = (I - l l^T) dL/dl / |a| and dL/du = -R_V^T dL/da */
+                            if (x->ndl <= 0) continue;
+                            double gl[3];
+                            for (int c = 0; c < 3; c++) gl[c] = e * Gh * x->A * fr.n[c];
+                            if (x->has_h && x->ndh > 0 && mexp != 0) {
+                                double coef = e * G * x->A * x->ndl * ks * mexp * pow(x->ndh, mexp - 1.0) / x->hl;
+                                for (int c = 0; c < 3; c++) gl[c] += coef * (fr.n[c] - x->ndh * x->h[c]);
+                            }
+                            double lg = dot3(x->l, gl), ga[3];
+                            for (int c = 0; c < 3; c++) ga[c] = (gl[c] - lg * x->l[c]) / L[l].qn;
+                            for (int c = 0; c < 3; c++)
+                                g_lightvec[3 * (int64_t)(lb + l) + c] -= V[0 * 4 + c] * ga[0] + V[1 * 4 + c] * ga[1] + V[2 * 4 + c] * ga[2];
+                            continue;
+                        }
                         /* point-light position, view space, then rotated to world */
                         double gq[3] = {0, 0, 0};
                         if (x->D > LIGHT_EPS) {
@@ -576,7 +596,7 @@ int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const 
                             }
                         }
                         for (int c = 0; c < 3; c++)
-                            g_lightpos[3 * (int64_t)(lb + l) + c] += V[0 * 4 + c] * gq[0] + V[1 * 4 + c] * gq[1] + V[2 * 4 + c] * gq[2];
+                            g_lightvec[3 * (int64_t)(lb + l) + c] += V[0 * 4 + c] * gq[0] + V[1 * 4 + c] * gq[1] + V[2 * 4 + c] * gq[2];
                     }
                     for (int c = 0; c < 3; c++) g_albedo[3 * (int64_t)o + c] += e * g[c] * sum_And;
                     g_spec[o] += e * G * sum_Ands;

@@ -66,7 +66,7 @@ class Outputs(C.Structure):
 
 
 class Grads(C.Structure):
-    _fields_ = [("albedo", P), ("roughness", P), ("specular", P), ("light_pos", P), ("light_intensity", P),
+    _fields_ = [("albedo", P), ("roughness", P), ("specular", P), ("light_vec", P), ("light_intensity", P),
                 ("exposure", P)]
 
 

@@ -34,7 +34,7 @@ class ShadeFn(torch.autograd.Function):
     def backward(ctx, grad_rgb):
         g = shade_backward(ctx.renderer.ctx, ctx.job.layout, ctx.state, ctx.vis, grad_rgb.float(),
                            workspace=ctx.job.extra.get("grad_workspace"))
-        return (None, None, g["albedo"], g["roughness"], g["specular"], g["light_pos"], g["light_intensity"],
+        return (None, None, g["albedo"], g["roughness"], g["specular"], g["light_vec"], g["light_intensity"],
                 g["exposure"])
 
 

@@ -718,7 +718,7 @@ orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const o
     }
     if (L->n_frames > 0 && (!vis || !grad_rgb)) return fail(ORRB_ERR_INVALID_ARGUMENT, "vis or grad_rgb is NULL");
     if ((L->n_objects > 0 && (!gr->albedo || !gr->roughness || !gr->specular)) ||
-        (L->n_lights > 0 && (!gr->light_pos || !gr->light_intensity)) || (L->n_frames > 0 && !gr->exposure))
+        (L->n_lights > 0 && (!gr->light_vec || !gr->light_intensity)) || (L->n_frames > 0 && !gr->exposure))
         return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL gradient destination");
     if (L->max_scene_objects > grad_max_objects())
         return fail(ORRB_ERR_UNSUPPORTED, "a scene has %d objects; the adjoint supports %d", L->max_scene_objects,
@@ -760,7 +760,7 @@ orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const o
     g.g_albedo = gr->albedo;
     g.g_rough = gr->roughness;
     g.g_spec = gr->specular;
-    g.g_lpos = gr->light_pos;
+    g.g_lpos = gr->light_vec;
     g.g_lint = gr->light_intensity;
     g.g_expo = gr->exposure;
     g.n_objects = (int32_t)L->n_objects;

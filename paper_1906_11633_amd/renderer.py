@@ -260,7 +260,7 @@ class Graph:
 def shade_backward(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], vis: torch.Tensor,
                    grad_rgb: torch.Tensor, workspace: Optional[torch.Tensor] = None, stream=None) -> Dict[str, torch.Tensor]:
     """orrb_shade_backward: gradients of the loss with respect to albedo [O,3],
-    roughness [O], specular [O], light_pos [L,3] (world), light_intensity [L] and
+    roughness [O], specular [O], light_vec [L,3] (world), light_intensity [L] and
     exposure [F], given dL/d(rgb) and the forward visibility keys."""
     s = state
     dev = vis.device
@@ -271,14 +271,14 @@ def shade_backward(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor],
     g = dict(albedo=torch.empty((O, 3), dtype=torch.float32, device=dev),
              roughness=torch.empty(O, dtype=torch.float32, device=dev),
              specular=torch.empty(O, dtype=torch.float32, device=dev),
-             light_pos=torch.empty((Lc, 3), dtype=torch.float32, device=dev),
+             light_vec=torch.empty((Lc, 3), dtype=torch.float32, device=dev),
              light_intensity=torch.empty(Lc, dtype=torch.float32, device=dev),
              exposure=torch.empty(F, dtype=torch.float32, device=dev))
     sc = L.Scenes(_ptr(s["object_pose"]), _ptr(s["object_seg"]), _ptr(s["object_visible"]))
     cam = L.Cameras(_ptr(s["view"]), _ptr(s["intr"]), _ptr(s["near"]))
     par = L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
                    _ptr(s["light_intensity"]), _ptr(s["exposure"]))
-    gr = L.Grads(_ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]), _ptr(g["light_pos"]),
+    gr = L.Grads(_ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]), _ptr(g["light_vec"]),
                  _ptr(g["light_intensity"]), _ptr(g["exposure"]))
     grad_rgb = grad_rgb.contiguous()
     if grad_rgb.dtype != torch.float32 or grad_rgb.numel() != 3 * int(inf.total_pixels):

@@ -13,7 +13,7 @@ import numpy as np
 import oracle
 from tests import brute
 
-FIELD = dict(albedo="albedo", roughness="roughness", specular="specular", light_pos="light_vec",
+FIELD = dict(albedo="albedo", roughness="roughness", specular="specular", light_vec="light_vec",
              light_intensity="light_intensity", exposure="exposure")
 
 

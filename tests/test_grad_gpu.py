@@ -20,7 +20,7 @@ from tests import fd
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ("albedo", "roughness", "specular", "light_pos", "light_intensity", "exposure")
+KINDS = ("albedo", "roughness", "specular", "light_vec", "light_intensity", "exposure")
 
 
 @pytest.fixture(scope="module")
@@ -106,7 +106,7 @@ def test_adjoint_directional_lights(renderer):
     b = S.config1(materials=True)
     w = (~oracle.near_tie(oracle.render(b))).astype(np.uint8)
     gpu, ref = _linear_pair(renderer, b, w, 12)
-    assert np.all(gpu["light_pos"] == 0)
+    assert np.all(gpu["light_vec"] == 0)
     for k in ("albedo", "roughness", "specular", "light_intensity", "exposure"):
         a, r = gpu[k].reshape(-1), ref[k].reshape(-1)
         sel = np.abs(r) >= 1e-3 * np.abs(r).max()
@@ -146,8 +146,8 @@ def test_adjoint_vs_finite_differences_config4(renderer):
         if k in ("albedo", "roughness", "specular"):
             o = idx // 3 if k == "albedo" else idx
             s = int(np.searchsorted(base.scene_object_begin, o, side="right") - 1)
-        elif k in ("light_pos", "light_intensity"):
-            l = idx // 3 if k == "light_pos" else idx
+        elif k in ("light_vec", "light_intensity"):
+            l = idx // 3 if k == "light_vec" else idx
             s = int(np.searchsorted(base.scene_light_begin, l, side="right") - 1)
         else:
             s = int(base.frame_scene[idx])
@@ -161,7 +161,7 @@ def test_adjoint_vs_finite_differences_config4(renderer):
             sidx = idx - 3 * int(base.scene_object_begin[s])
         elif k in ("roughness", "specular"):
             sidx = idx - int(base.scene_object_begin[s])
-        elif k == "light_pos":
+        elif k == "light_vec":
             sidx = idx - 3 * int(base.scene_light_begin[s])
         elif k == "light_intensity":
             sidx = idx - int(base.scene_light_begin[s])
@@ -189,5 +189,5 @@ def test_shadefn_autograd(renderer):
     out = renderer.render(job, vis=True)
     g = shade_backward(renderer.ctx, job.layout, job.state, out["vis"], (2.0 * (out["rgb"] - tgt)).contiguous())
     torch.cuda.synchronize()
-    for p, k in zip(params, ("albedo", "roughness", "specular", "light_pos", "light_intensity", "exposure")):
+    for p, k in zip(params, ("albedo", "roughness", "specular", "light_vec", "light_intensity", "exposure")):
         assert torch.equal(p.grad, g[k]), k

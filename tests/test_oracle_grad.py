@@ -11,7 +11,7 @@ import oracle
 from paper_1906_11633_amd import scenes as S
 from tests import fd
 
-PARAMS = ("albedo", "roughness", "specular", "light_pos", "light_intensity", "exposure")
+PARAMS = ("albedo", "roughness", "specular", "light_vec", "light_intensity", "exposure")
 
 
 def _small_problem(res=40, n_scenes=2, seed=4):
@@ -43,14 +43,14 @@ def test_adjoint_matches_central_differences():
     assert checked >= 20
 
 
-def test_light_position_adjoint_converges_without_mask():
+def test_light_vecition_adjoint_converges_without_mask():
     """Over all pixels the light-position difference converges to the analytic
     gradient as h shrinks (the h = 1e-4 gap is the terminator kink, not the adjoint)."""
     b, tgt = _small_problem()
     _, g = oracle.shade_grad(b, tgt)
     for idx in range(3):
-        d = fd.central_difference(b, tgt, "light_pos", idx, 1e-6)
-        a = g["light_pos"].reshape(-1)[idx]
+        d = fd.central_difference(b, tgt, "light_vec", idx, 1e-6)
+        a = g["light_vec"].reshape(-1)[idx]
         assert abs(a - d) <= 1e-7 * abs(a), (idx, a, d)
 
 
