@@ -53,6 +53,16 @@ def load_traffic():
     return d.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(batch_fn, n_scenes_total: int, target_s: float, threads: int):
     """Time the FP64 oracle on the workload (its first scenes if the whole batch would
     take longer than target_s), repeating it until about target_s of work, and scale
@@ -77,7 +87,7 @@ def cpu_baseline(batch_fn, n_scenes_total: int, target_s: float, threads: int):
     what = "the whole workload" if n == n_scenes_total else f"the first {n} of {n_scenes_total} scenes"
     return dict(value=frames / dt, unit="frames/s", cores=threads, kind="oracle",
                 sample=f"{what} x 3 cameras ({b.n_frames} frames) rendered {reps}x by the FP64 oracle "
-                       f"(OpenMP over frames) in {dt:.1f} s")
+                       f"(OpenMP over frames, {threads} threads) in {dt:.1f} s")
 
 
 def _timed(fn, reps, torch):
@@ -87,6 +97,25 @@ def _timed(fn, reps, torch):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps
+
+
+def _event_times(fn, reps, torch, stream=None):
+    """Per-call device durations (ms) from HIP events recorded on `stream` (default:
+    torch's current stream, the one the library's calls are enqueued on)."""
+    st = stream if stream is not None else torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(st)
+        fn()
+        e1.record(st)
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in ev]
+
+
+def _pct(xs, q):
+    import numpy as np
+    return round(float(np.percentile(np.asarray(xs), q)), 4)
 
 
 def measure_extras(args, r, S):
@@ -109,8 +138,17 @@ def measure_extras(args, r, S):
     step = lambda: shade_backward(r.ctx, job.layout, job.state, out["vis"], grad_rgb, ws)
     step()
     dt = _timed(step, 10, torch)
+    ev = _event_times(step, 20, torch)
+    # algorithmic bytes: the visibility key (8 B) and dL/drgb (12 B) of every pixel
+    gbytes = 20 * base.total_pixels
+    gms = sorted(ev)[len(ev) // 2]
     ex["shading_grad"] = dict(frames=base.n_frames, ms_per_backward=round(dt * 1e3, 3),
-                              grad_frames_per_s=round(base.n_frames / dt, 1))
+                              grad_frames_per_s=round(base.n_frames / dt, 1),
+                              event_ms_median=_pct(ev, 50), event_ms_p90=_pct(ev, 90),
+                              roofline=dict(bound="hbm", kernel="backward (vertex + k_grad_tile + k_grad_reduce)",
+                                            bytes_per_call=gbytes, achieved=round(gbytes / (gms * 1e-3) / 1e9, 1),
+                                            peak=HBM_PEAK_GBS, unit="GB/s",
+                                            frac=round(gbytes / (gms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
     print(f"[bench] backward {dt * 1e3:.3f} ms for {base.n_frames} frames", file=sys.stderr, flush=True)
     del job, out, grad_rgb, ws
     # serving
@@ -118,10 +156,13 @@ def measure_extras(args, r, S):
     warm = Server(r.ctx, pool)
     warm.run(poisson_trace(pool, 2000.0, 0.3, seed=99))
     srv = Server(r.ctx, pool)
-    srv.layouts = warm.layouts
-    st = srv.run(poisson_trace(pool, 2000.0, args.serving_seconds, 0.5), warmup=0.5)
+    srv.layouts, srv.table_bytes = warm.layouts, warm.table_bytes
+    # config 5: Poisson arrivals at 2000 req/s, statistics over the requests arriving
+    # in the args.serving_seconds after a 1 s warm-up
+    st = srv.run(poisson_trace(pool, 2000.0, args.serving_seconds, 1.0), warmup=1.0)
+    assert st["wait_timeouts"] == 0, st
     ex["serving"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
-    ex["serving"].update(rate_req_per_s=2000.0, budget_gb=64)
+    ex["serving"].update(rate_req_per_s=2000.0, budget_gb=64, warmup_s=1.0, measured_s=args.serving_seconds)
     print(f"[bench] serving p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
     del srv, warm, pool
     # uneven batch: autotuned, one graph replay per step, vs one scene per launch
@@ -129,14 +170,20 @@ def measure_extras(args, r, S):
     job3 = r.prepare(b3)
     out3 = r.alloc_outputs(job3)
     tuning, _ = autotune(r.ctx, job3.layout, job3.state, out3, job3.workspace)
+    inf3 = job3.layout.info
+    # kernels one render of this layout launches: the frame kernel for frames on the
+    # frame path, the vertex and raster kernels for any on the tiled path
+    g_nodes = (1 if inf3.frame_path_frames > 0 else 0) + (2 if inf3.tile_items > 0 else 0)
     stream = torch.cuda.Stream()
     g = Graph(r.ctx, job3.layout, job3.state, out3, job3.workspace, stream)
     with torch.cuda.stream(stream):
         for _ in range(3):
             g.replay(stream)
         dt3 = _timed(lambda: g.replay(stream), 20, torch)
+        ev3 = _event_times(lambda: g.replay(stream), 20, torch, stream)
     g.close()
     bytes3 = BYTES_PER_PIXEL * b3.total_pixels
+    ms3 = sorted(ev3)[len(ev3) // 2]
     plain = []
     st3 = job3.state
     po = b3.pixel_offset
@@ -160,7 +207,11 @@ def measure_extras(args, r, S):
     ex["uneven_batch"] = dict(frames=b3.n_frames, pixels=b3.total_pixels, tuning=list(tuning),
                               ms_per_step=round(dt3 * 1e3, 3), frames_per_s=round(b3.n_frames / dt3, 1),
                               hbm_frac=round(bytes3 / dt3 / 1e9 / HBM_PEAK_GBS, 4),
-                              plain_frames_per_s=round(b3.n_frames / dtp, 1), batched_over_plain=round(dtp / dt3, 2))
+                              plain_frames_per_s=round(b3.n_frames / dtp, 1), batched_over_plain=round(dtp / dt3, 2),
+                              graph_kernel_nodes=g_nodes, event_ms_median=_pct(ev3, 50), event_ms_p90=_pct(ev3, 90),
+                              roofline=dict(bound="hbm", kernel="graph replay", bytes_per_call=bytes3,
+                                            achieved=round(bytes3 / (ms3 * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS,
+                                            unit="GB/s", frac=round(bytes3 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
     print(f"[bench] uneven batch {dt3 * 1e3:.3f} ms/step (graph), plain {dtp * 1e3:.3f} ms", file=sys.stderr, flush=True)
     return ex
 
@@ -177,7 +228,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient, serving and uneven-batch parts")
-    ap.add_argument("--serving-seconds", type=float, default=2.0)
+    ap.add_argument("--serving-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB 5 times (counter calibration)")
     args = ap.parse_args(argv)
@@ -220,12 +271,24 @@ def main(argv=None):
         r.render(job, out)
     torch.cuda.synchronize()
     _lib.check(lib.orrb_profile_enable(ctx, 1))
+    stats = torch.zeros(_lib.STATS_WORDS, dtype=torch.int32, device="cuda")
+    out["stats"] = stats
+    cur = torch.cuda.current_stream()
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for e0, e1 in step_ev:
+        e0.record(cur)
         r.render(job, out)
+        e1.record(cur)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    del out["stats"]
+    step_ms = [e0.elapsed_time(e1) for e0, e1 in step_ev]
+    from paper_1906_11633_amd.renderer import read_stats
+    counters = read_stats(stats)
+    if counters["wait_timeouts"]:
+        raise SystemExit(f"frame-kernel waits reached their bound: {counters}")
     kt = _lib.KernelTimes()
     _lib.check(lib.orrb_profile_read(ctx, C.byref(kt)))
     _lib.check(lib.orrb_profile_enable(ctx, 0))
@@ -250,8 +313,37 @@ def main(argv=None):
           ", ".join(f"{k} {v:.3f} ms" for k, v in kernel_ms.items() if v), file=sys.stderr, flush=True)
 
     extra = dict(kernel_ms={k: round(v, 4) for k, v in kernel_ms.items() if v},
+                 step_event_ms_median=_pct(step_ms, 50), step_event_ms_p90=_pct(step_ms, 90),
+                 counters=counters,
                  tuning=list(job.layout.info.tuning.as_tuple()),
                  whole_step_hbm_frac=round(bytes_per_launch / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+
+    # store-only ceiling: the same output buffers (same bytes, planar layout) filled by
+    # the runtime's fill kernels, no rendering
+    def fill_all():
+        for k in ("rgb", "depth", "normal", "seg"):
+            out[k].zero_()
+    fill_all()
+    fev = _event_times(fill_all, 20, torch)
+    fms = sorted(fev)[len(fev) // 2]
+    extra["store_ceiling_gbs"] = round(bytes_per_launch / (fms * 1e-3) / 1e9, 1)
+    extra["store_ceiling_frac"] = round(bytes_per_launch / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    for _ in range(2):
+        r.render(job, out)  # the outputs hold the render again
+
+    # with upload: the per-batch state (poses, materials, lights, cameras) copied from
+    # pinned host memory before each render, on the same stream
+    host = {k: v.cpu().pin_memory() for k, v in job.state.items()}
+    state_bytes = sum(v.numel() * v.element_size() for v in host.values())
+
+    def upload_and_render():
+        for k, v in host.items():
+            job.state[k].copy_(v, non_blocking=True)
+        r.render(job, out)
+    upload_and_render()
+    dtu = _timed(upload_and_render, max(5, args.steps // 4), torch)
+    extra["with_upload"] = dict(frames_per_s=round(F / dtu, 1), ms_per_step=round(dtu * 1e3, 4),
+                                state_bytes=state_bytes)
 
     if not args.no_plain:
         # the plain form: the same kernels, one scene (3 frames) per launch, no graph
@@ -298,6 +390,10 @@ def main(argv=None):
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         cpu = cpu_baseline(lambda n: S.config2(2, n, args.res), args.scenes, args.cpu_seconds, threads)
         cpu["value"] = round(cpu["value"], 3)
+        one = cpu_baseline(lambda n: S.config2(2, n, args.res), args.scenes, args.cpu_seconds / 3, 1)
+        extra["cpu_single_thread"] = dict(value=round(one["value"], 3), unit="frames/s", sample=one["sample"])
+        extra["cpu_model"] = cpu_model()
+        extra["cpu_threads_available"] = os.cpu_count()
 
     try:
         paper = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_throughput.json")))

@@ -139,6 +139,7 @@ typedef struct {
     size_t workspace_bytes;      /* workspace orrb_render_batch needs (current tuning) */
     size_t workspace_bytes_any;  /* workspace enough for every valid tuning */
     size_t grad_workspace_bytes; /* workspace orrb_shade_backward needs */
+    size_t table_bytes;          /* device memory the layout itself holds (its tables) */
     orrb_tuning tuning;
 } orrb_layout_info;
 
@@ -182,6 +183,25 @@ typedef struct {                  /* sampled randomization parameters */
     const float *exposure;        /* [F] linear post-processing gain */
 } orrb_params;
 
+/* Counters of one render call, written by its kernels into caller memory (the
+ * `stats` destination of orrb_outputs).  The kernels ADD to the words, so a caller
+ * zeroes the buffer before the call for per-call counts, or keeps adding across calls.
+ * They are ordinary device memory: read them with a copy on the call's stream (no
+ * device-wide synchronization).  Word meanings: */
+#define ORRB_STAT_WAIT_TIMEOUTS     0  /* frame-kernel waits that reached their bound; the
+                                          workgroup then stops, and the frames it had not
+                                          finished hold unspecified pixels (0 in every test) */
+#define ORRB_STAT_BIN_OVERFLOW      1  /* frame path: frames whose tile bins overflowed (each
+                                          busy tile then scans every triangle; same bits) */
+#define ORRB_STAT_SURVIVOR_RESETUP  2  /* frame path: frames whose survivor list overflowed
+                                          (triangles set up a second time; same bits) */
+#define ORRB_STAT_NEAR_VERTICES     3  /* vertex instances nearer than the near plane (their
+                                          triangles are discarded) */
+#define ORRB_STAT_GUARD_VERTICES    4  /* vertex instances beyond the +-65536 px guard band
+                                          (their triangles are discarded) */
+#define ORRB_STAT_TILED_EXTRA_FLUSH 5  /* tiled path: LDS bin flushes beyond one per tile */
+#define ORRB_STATS_WORDS 8             /* words 6 and 7 are reserved (written as 0 + 0) */
+
 typedef struct {                  /* destinations; rgb, depth, normal, seg may each be NULL */
     float *rgb;                   /* [3P] */
     float *depth;                 /* [P] */
@@ -190,6 +210,7 @@ typedef struct {                  /* destinations; rgb, depth, normal, seg may e
     int32_t *tri_id;              /* [P] or NULL: scene-local winning triangle, -1 background */
     uint64_t *vis;                /* [P] or NULL: visibility key (fp32 depth bits << 32 | tri_id),
                                      ~0 for background; input of orrb_shade_backward */
+    uint32_t *stats;              /* [ORRB_STATS_WORDS] or NULL: counters added to by the call */
 } orrb_outputs;
 
 /* Render every frame of the layout.  `scenes`, `cameras`, `params`, `out` are host
@@ -225,14 +246,19 @@ typedef struct orrb_graph orrb_graph;
 /* Capture one orrb_render_batch with these exact buffers into a HIP graph and
  * instantiate it.  Replays (orrb_graph_launch) render whatever the buffers hold at
  * replay time, so a caller updates scene state, cameras and parameters in place and
- * replays; the layout's tuning is frozen into the graph.  `stream` must not be the
- * null stream (it is used for capture only).  The layout, buffers and workspace must
- * outlive the graph. */
+ * replays.  The graph holds the layout's device tables and tuning as they were at
+ * capture: once orrb_layout_set_tuning or orrb_autotune has changed the layout, or
+ * orrb_add_mesh has grown the context's mesh pool (either may move device tables),
+ * orrb_graph_launch refuses the graph with ORRB_ERR_INVALID_ARGUMENT and launches
+ * nothing; capture a new graph then.  `stream` must not be the null stream (it is used
+ * for capture only).  The layout, buffers and workspace must outlive the graph. */
 orrb_status orrb_graph_create(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
                               const orrb_cameras *cameras, const orrb_params *params, const orrb_outputs *out,
                               void *workspace, size_t workspace_bytes, void *stream, orrb_graph **graph);
 
-/* Enqueue a replay of the captured render on `stream` (NULL: the null stream). */
+/* Enqueue a replay of the captured render on `stream` (NULL: the null stream).
+ * ORRB_ERR_INVALID_ARGUMENT, with nothing enqueued, if the layout or the mesh pool
+ * changed since capture (see orrb_graph_create). */
 orrb_status orrb_graph_launch(orrb_graph *graph, void *stream);
 
 /* Destroy a graph (the caller must have synchronized its replays).  NULL is ignored. */
@@ -246,7 +272,9 @@ typedef struct {                  /* device destinations, overwritten (not accum
     float *albedo;                /* [O,3] */
     float *roughness;             /* [O] */
     float *specular;              /* [O] */
-    float *light_vec;             /* [L,3] world-space position (0 for directional lights) */
+    float *light_vec;             /* [L,3] d/d light_vec: the world position of a point
+                                     light, the world direction vector u of a directional
+                                     light (l = -R_V u / |R_V u| toward the light) */
     float *light_intensity;       /* [L] */
     float *exposure;              /* [F] */
 } orrb_grads;
@@ -287,9 +315,11 @@ orrb_status orrb_profile_read(orrb_context *ctx, orrb_kernel_times *out);
 /* Number of waits inside the frame kernel (compute-wave barrier, staging slot,
  * background publication, store-wave polling) that reached their bound on the
  * context's device since the library was loaded.  Each wait is bounded (about 0.3 s)
- * so that a stalled wave cannot hang the GPU; a non-zero count means some frames of
- * the renders since then hold unspecified pixels.  Synchronizes with the device (reads
- * a device counter, all streams); cumulative, never reset.  Errors:
+ * so that a stalled wave cannot hang the GPU; the workgroup whose wait reached the
+ * bound stops at once and the frames it had not finished hold unspecified pixels.
+ * Synchronizes with the device (reads a device counter, all streams); cumulative,
+ * never reset.  Per-call counts without a device-wide synchronization: the stats
+ * destination of orrb_outputs (ORRB_STAT_WAIT_TIMEOUTS).  Errors:
  * ORRB_ERR_INVALID_ARGUMENT for NULL arguments, ORRB_ERR_DEVICE if the read fails. */
 orrb_status orrb_wait_timeouts(orrb_context *ctx, uint64_t *count_out);
 

@@ -18,6 +18,10 @@ ORRB_OK = 0
 STATUS_NAMES = {0: "ORRB_OK", 1: "ORRB_ERR_INVALID_ARGUMENT", 2: "ORRB_ERR_OUT_OF_MEMORY",
                 3: "ORRB_ERR_WORKSPACE_TOO_SMALL", 4: "ORRB_ERR_DEVICE", 5: "ORRB_ERR_UNSUPPORTED"}
 MAX_LIGHTS_PER_SCENE = 8
+# words of the per-call stats destination (orrb_outputs.stats)
+STATS_WORDS = 8
+STAT_NAMES = ("wait_timeouts", "bin_overflow_frames", "survivor_resetup_frames", "near_vertices", "guard_vertices",
+              "tiled_extra_flushes")
 
 
 class OrrbError(RuntimeError):
@@ -45,7 +49,8 @@ class LayoutInfo(C.Structure):
                 ("n_frames", C.c_int64), ("total_pixels", C.c_int64), ("vertex_instances", C.c_int64),
                 ("triangle_instances", C.c_int64), ("tile_items", C.c_int64), ("frame_path_frames", C.c_int64),
                 ("workspace_bytes", C.c_size_t),
-                ("workspace_bytes_any", C.c_size_t), ("grad_workspace_bytes", C.c_size_t), ("tuning", Tuning)]
+                ("workspace_bytes_any", C.c_size_t), ("grad_workspace_bytes", C.c_size_t),
+                ("table_bytes", C.c_size_t), ("tuning", Tuning)]
 
 
 class Scenes(C.Structure):
@@ -62,7 +67,7 @@ class Params(C.Structure):
 
 
 class Outputs(C.Structure):
-    _fields_ = [("rgb", P), ("depth", P), ("normal", P), ("seg", P), ("tri_id", P), ("vis", P)]
+    _fields_ = [("rgb", P), ("depth", P), ("normal", P), ("seg", P), ("tri_id", P), ("vis", P), ("stats", P)]
 
 
 class Grads(C.Structure):

@@ -1,7 +1,8 @@
 // Adjoint of the shading over a fixed visibility buffer (HIP, gfx950).
 //
 // Given the visibility keys of a forward render and dL/d(rgb), computes dL/d of the
-// per-object albedo (3), roughness and specular, the per-light world position (3) and
+// per-object albedo (3), roughness and specular, the per-light world vector (3: the
+// position of a point light, the direction vector of a directional light) and
 // intensity, and the per-frame exposure.  Visibility is fixed: none of these
 // parameters moves geometry.
 //
@@ -25,6 +26,7 @@ constexpr int kGMaxObj = 1024;              // objects per scene supported by th
 
 struct GradLds {
     double light_q[kMaxLights][3];
+    double light_qn[kMaxLights];  // directional: |R_V u| before normalization
     double light_I[kMaxLights];
     int light_type[kMaxLights];
     int pix_obj[kGPix];
@@ -86,11 +88,14 @@ __global__ __launch_bounds__(kBlock) void k_grad_tile(GradArgs g) {
             const double d = (double)V[r * 4 + 0] * u[0] + (double)V[r * 4 + 1] * u[1] + (double)V[r * 4 + 2] * u[2];
             q[r] = type == 0 ? d + (double)V[r * 4 + 3] : -d;
         }
+        double qn = 1.0;
         if (type != 0) {
-            const double inv = 1.0 / sqrt(dot3d(q, q));
+            qn = sqrt(dot3d(q, q));
+            const double inv = 1.0 / qn;
             for (int r = 0; r < 3; ++r) q[r] *= inv;
         }
         for (int r = 0; r < 3; ++r) S.light_q[tid][r] = q[r];
+        S.light_qn[tid] = qn;
         S.light_I[tid] = a.light_intensity[l];
         S.light_type[tid] = type;
     }
@@ -222,6 +227,18 @@ __global__ __launch_bounds__(kBlock) void k_grad_tile(GradArgs g) {
                             const double coef = e * G * A * ndl * ks * m * pow(ndh, m - 1.0) / (hl * dist);
                             for (int c = 0; c < 3; ++c) gq[c] += coef * (w[c] - lw * ld[c]);
                         }
+                    } else {
+                        // directional: l = a / |a| with a = -R_V u reaches the shade through
+                        // n.l and h = (l + v) / |l + v|; dL/dl, then dL/da = (I - l l^T)
+                        // dL/dl / |a|; gq holds dL/d(R_V u) = -dL/da (rotated to world below)
+                        double gl[3];
+                        for (int c = 0; c < 3; ++c) gl[c] = e * Gh * A * n[c];
+                        if (H2 >= 1e-12 && ndh > 0.0 && m != 0.0) {
+                            const double coef = e * G * A * ndl * ks * m * pow(ndh, m - 1.0) / hl;
+                            for (int c = 0; c < 3; ++c) gl[c] += coef * (n[c] - ndh * h[c]);
+                        }
+                        const double lg = dot3d(ld, gl);
+                        for (int c = 0; c < 3; ++c) gq[c] = -(gl[c] - lg * ld[c]) / S.light_qn[l];
                     }
                 }
             }
@@ -266,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_tile(GradArgs g) {
         block_sum5(v5, S);
         if (tid < 5) part[5 * k + tid] = v5[tid];
     }
-    // lights (view -> world for positions) and exposure: waves summed in order
+    // lights (view -> world: dL/dq_world = R_V^T dL/dq_view) and exposure: waves summed in order
     double *lp = part + 5 * n_obj;
     if (tid < nl) {
         const int l = tid;

@@ -69,7 +69,13 @@ struct RenderArgs {
     float4 *obj_rot;   // per (frame, object): rows of the fp32 view rotation (x, y, z, 0)
     int4 *obj_bbox;    // per (frame, object): covered pixel-centre range i0, j0, i1, j1
     unsigned int *queue;  // persistent work counter
+    unsigned int *stats;  // caller's ORRB_STATS_WORDS counters of the call, or null
 };
+
+// Add v to counter `word` of the call's stats (no-op without a stats buffer).
+__device__ __attribute__((always_inline)) inline void stat_add(const RenderArgs &a, int word, unsigned v) {
+    if (a.stats && v) atomicAdd(a.stats + word, v);
+}
 
 // Shading adjoint over a fixed visibility buffer (orrb_adjoint.hip).
 struct GradArgs {
@@ -101,6 +107,8 @@ namespace orrb {
 // host-runtime internals used by the autotuner and graph code (orrb_tune.cpp)
 orrb_status set_error(orrb_status st, const char *msg);
 uint64_t layout_signature(const orrb_layout *L);
+uint64_t layout_generation(const orrb_layout *L);    // bumped whenever its tables or tuning change
+uint64_t context_generation(const orrb_context *ctx); // bumped whenever the mesh pool grows
 int context_device(const orrb_context *ctx);
 bool context_profiling(const orrb_context *ctx);
 void context_set_profiling(orrb_context *ctx, bool on);

@@ -148,6 +148,7 @@ struct orrb_context {
     std::vector<int32_t> mesh_vbegin{0}, mesh_tbegin{0};
     DevBuf d_pos, d_nrm, d_tri;
     int n_layouts = 0;
+    uint64_t generation = 0;  // bumped whenever the mesh pool grows (its buffers may move)
 };
 
 struct orrb_layout {
@@ -174,6 +175,7 @@ struct orrb_layout {
     std::vector<int32_t> frame_item_begin, scene_frame_begin, scene_frames, obj_scene, obj_local, light_scene,
         light_local;
     uint64_t signature = 0;  // hash of the batch structure (autotuner cache key)
+    uint64_t generation = 0; // bumped whenever the tuning or the device tables change
     int64_t grad_partials = 0;
     int max_scene_objects = 0;
     bool grad_ready = false;  // tables uploaded on the first backward call
@@ -344,6 +346,8 @@ orrb_status set_error(orrb_status st, const char *msg) {
     return st;
 }
 uint64_t layout_signature(const orrb_layout *L) { return L->signature; }
+uint64_t layout_generation(const orrb_layout *L) { return L->generation; }
+uint64_t context_generation(const orrb_context *ctx) { return ctx->generation; }
 int context_device(const orrb_context *ctx) { return ctx->device; }
 bool context_profiling(const orrb_context *ctx) { return ctx->timer.enabled; }
 void context_set_profiling(orrb_context *ctx, bool on) { ctx->timer.enabled = on; }
@@ -457,6 +461,7 @@ orrb_status orrb_add_mesh(orrb_context *ctx, const float *pos, const float *nrm,
         return fail(e == hipErrorOutOfMemory ? ORRB_ERR_OUT_OF_MEMORY : ORRB_ERR_DEVICE, "mesh upload failed: %s",
                     hipGetErrorString(e));
     }
+    ctx->generation++;
     ctx->mesh_vbegin.push_back((int32_t)ctx->pos.size());
     ctx->mesh_tbegin.push_back((int32_t)ctx->tri.size());
     *mesh_id = (int32_t)ctx->mesh_vbegin.size() - 2;
@@ -623,6 +628,7 @@ orrb_status orrb_layout_info_get(const orrb_layout *L, orrb_layout_info *info) {
     info->workspace_bytes = ws_layout(L).total;
     info->workspace_bytes_any = ws_layout(L->all_vertex_instances, L->all_object_instances).total;
     info->grad_workspace_bytes = grad_workspace(L);
+    info->table_bytes = L->tab.dev.bytes + L->gtab.dev.bytes;
     info->tuning = L->tuning;
     return ORRB_OK;
 }
@@ -634,6 +640,7 @@ orrb_status orrb_layout_set_tuning(orrb_layout *L, const orrb_tuning *t) {
         return fail(ORRB_ERR_INVALID_ARGUMENT, "invalid tuning tile %dx%d cap %d persistent %d", t->tile_w, t->tile_h,
                     t->bin_cap, t->persistent);
     const bool rebuild = t->tile_w != L->tuning.tile_w || t->tile_h != L->tuning.tile_h || t->path != L->tuning.path;
+    if (memcmp(t, &L->tuning, sizeof(*t)) != 0) L->generation++;  // captured graphs are now stale
     L->tuning = *t;
     if (rebuild) {
         build_items(L);
@@ -642,10 +649,13 @@ orrb_status orrb_layout_set_tuning(orrb_layout *L, const orrb_tuning *t) {
     return ORRB_OK;
 }
 
-orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
-                              const orrb_params *par, const orrb_outputs *out, void *workspace, size_t workspace_bytes,
-                              void *stream) {
-    g_last_error.clear();
+}  // extern "C"
+
+// A render call: host checks, then the kernels on `stream`.  With `timing` false it
+// records no kernel-timing events (and so creates none).
+static orrb_status render_impl(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+                               const orrb_params *par, const orrb_outputs *out, void *workspace,
+                               size_t workspace_bytes, void *stream, bool timing) {
     if (!ctx || !L || !sc || !cam || !par || !out) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL handle or struct");
     if (L->ctx != ctx) return fail(ORRB_ERR_INVALID_ARGUMENT, "layout belongs to another context");
     if (L->n_frames == 0) return ORRB_OK;
@@ -677,6 +687,7 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
     a.out_seg = out->seg;
     a.out_tri = out->tri_id;
     a.out_vis = (unsigned long long *)out->vis;
+    a.stats = out->stats;
     char *ws = (char *)workspace;
     a.vtx_pos = (int4 *)(ws + w.vtx_pos);
     a.obj_rot = (float4 *)(ws + w.obj_rot);
@@ -690,19 +701,28 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
         if (k < 2 && a.n_titems == 0) continue;  // no frame on the tiled path
         if (k == 2 && a.n_fitems == 0) continue;
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (T.enabled) {
+        if (T.enabled && timing) {
             e0 = T.get();
             e1 = T.get();
             if (e0) e = hipEventRecord(e0, st);
         }
         if (e == hipSuccess) e = k == 0 ? launch_vertex(a, st) : k == 1 ? launch_raster(a, st, ctx->n_cu) : launch_frame(a, st, ctx->n_cu);
-        if (T.enabled && e0 && e1 && e == hipSuccess) {
+        if (T.enabled && timing && e0 && e1 && e == hipSuccess) {
             e = hipEventRecord(e1, st);
             T.pending[k].push_back({e0, e1});
         }
     }
     if (e != hipSuccess) return fail(ORRB_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return ORRB_OK;
+}
+
+extern "C" {
+
+orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+                              const orrb_params *par, const orrb_outputs *out, void *workspace, size_t workspace_bytes,
+                              void *stream) {
+    g_last_error.clear();
+    return render_impl(ctx, L, sc, cam, par, out, workspace, workspace_bytes, stream, true);
 }
 
 orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,

@@ -70,9 +70,12 @@ __global__ __launch_bounds__(kBlock) void k_vertex(RenderArgs a) {
     for (int k = 0; k < 12; ++k) Mr[k] = M[k];
     int xmin = 0x7fffffff, ymin = 0x7fffffff, xmax = -0x7fffffff, ymax = -0x7fffffff;
     const int64_t vb = fi.vbase + ob.scene_vbase;
+    unsigned n_near = 0, n_guard = 0;
     for (int v = threadIdx.x; v < ob.n_verts; v += kBlock) {
         const Snapped s = snap_vertex(Mr, a.mesh_pos[ob.mesh_vbegin + v], fx, fy, cx, cy, nearp);
         a.vtx_pos[vb + v] = make_int4(s.X, s.Y, __float_as_int(s.iw), s.valid);
+        n_near += s.cull == 1;
+        n_guard += s.cull == 2;
         if (s.valid) {
             xmin = min(xmin, s.X);
             xmax = max(xmax, s.X);
@@ -80,6 +83,8 @@ __global__ __launch_bounds__(kBlock) void k_vertex(RenderArgs a) {
             ymax = max(ymax, s.Y);
         }
     }
+    stat_add(a, ORRB_STAT_NEAR_VERTICES, n_near);  // rare: one atomic per thread that saw one
+    stat_add(a, ORRB_STAT_GUARD_VERTICES, n_guard);
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
         xmin = min(xmin, __shfl_xor(xmin, off));
@@ -218,7 +223,7 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
 
     // ---- visibility: object cull, triangle set-up into the LDS bin, raster ----
     const int64_t vbase = fi.vbase;
-    int n_ol = 0;
+    int n_ol = 0, n_flush = 0;
     for (int c0 = 0; c0 < fi.n_obj; c0 += kBlock) {
         const int s = c0 + tid;
         bool ov = false;
@@ -303,6 +308,7 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
             __syncthreads();
             const int nb = L.misc[0];
             if (nb > cap - kBlock) {
+                ++n_flush;
                 flush_bin(L, nb, tx0, ty0, TW);
                 if (tid == 0) L.misc[0] = 0;
                 __syncthreads();
@@ -311,7 +317,11 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
     }
     {
         const int nb = L.misc[0];
-        if (nb > 0) flush_bin(L, nb, tx0, ty0, TW);
+        if (nb > 0) {
+            ++n_flush;
+            flush_bin(L, nb, tx0, ty0, TW);
+        }
+        if (tid == 0 && n_flush > 1) stat_add(a, ORRB_STAT_TILED_EXTRA_FLUSH, (unsigned)(n_flush - 1));
     }
 
     // ---- deferred shading of the tile ----
@@ -471,6 +481,7 @@ struct FrameLds {
     int cons_seq[kFW];                       // frame each store wave takes tiles from
     int published, all_published;            // frames published; 1 once no more will be
     int cbar;                                // compute-wave barrier arrivals
+    int abort_flag;                          // 1 once a wait reached its bound: every wave stops
     // Busy tiles rendered by a compute wave and written out by a store wave: planes
     // r, g, b, nx, ny, nz, seg (as bits) and the visibility key per tile pixel.
     alignas(16) unsigned int stage_val[kFStage][7][kFTileW * kFTileH];
@@ -570,15 +581,17 @@ ORRB_INLINE bool frame_setup(const FrameLds &S, int k, int4 tri, int cx0, int cy
 }
 
 // Snap vertex v (object k, object-space position p) into the LDS vertex arrays.
-ORRB_INLINE void frame_vertex(FrameLds &S, int v, int k, float4 p, double fx, double fy, double cx, double cy,
-                              double nearp) {
-    int X = kInvalidX, Y = 0;
+// Returns the vertex's cull reason (Snapped::cull; 0 for hidden objects).
+ORRB_INLINE int frame_vertex(FrameLds &S, int v, int k, float4 p, double fx, double fy, double cx, double cy,
+                             double nearp) {
+    int X = kInvalidX, Y = 0, cull = 0;
     float iw = 0.f;
     if (S.o_vis[k]) {
         double M[12];
 #pragma unroll
         for (int q = 0; q < 12; ++q) M[q] = S.u.M[k][q];
         const Snapped s = snap_vertex(M, p, fx, fy, cx, cy, nearp);
+        cull = s.cull;
         if (s.valid) {
             X = s.X;
             Y = s.Y;
@@ -588,6 +601,7 @@ ORRB_INLINE void frame_vertex(FrameLds &S, int v, int k, float4 p, double fx, do
     S.X[v] = X;
     S.Y[v] = Y;
     S.iw[v] = iw;
+    return cull;
 }
 
 // Per-tile counts and the survivor entry of a set-up triangle.
@@ -676,28 +690,44 @@ ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, 
 // the hardware barrier cannot be used).  After each frame's tile scan, wave 0 publishes
 // the frame's background tiles into one of kFSlots slots; the store waves take them
 // from per-slot counters and write them while the compute waves go on.  Every wait is
-// bounded by kFSpinCap polls.
+// bounded by kFSpinCap polls.  A wait that reaches the bound means a peer wave stopped
+// making progress: the workgroup then stops (every wait ends at once and no wave starts
+// new work), so the kernel ends promptly with the unfinished frames' pixels
+// unspecified, and the event is counted for the call and for the device.
 
-// Waits that reached kFSpinCap on this device since the library was loaded (their
-// frames' pixels are unspecified); read by orrb_wait_timeouts.
+// Waits that reached kFSpinCap on this device since the library was loaded; read by
+// orrb_wait_timeouts.
 __device__ unsigned int g_wait_timeouts;
-
-ORRB_INLINE void note_wait_timeout() { atomicAdd(&g_wait_timeouts, 1u); }
 
 ORRB_INLINE int lds_load(const int *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP); }
 ORRB_INLINE void lds_store(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); }
 
-ORRB_INLINE void frame_barrier(FrameLds &S, int &gen) {
+ORRB_INLINE bool frame_aborted(FrameLds &S) { return lds_load(&S.abort_flag) != 0; }
+
+// A wait reached its bound: stop the workgroup (counted once per workgroup).
+ORRB_INLINE void wait_bound_reached(const RenderArgs &a, FrameLds &S) {
+    if (atomicExch(&S.abort_flag, 1) == 0) {
+        atomicAdd(&g_wait_timeouts, 1u);
+        stat_add(a, ORRB_STAT_WAIT_TIMEOUTS, 1u);
+    }
+}
+
+// Barrier of the compute waves; true if the workgroup has stopped.
+ORRB_INLINE bool frame_barrier(const RenderArgs &a, FrameLds &S, int &gen) {
     gen += kFCW;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    int stop = 0;
     if (lane_id() == 0) {
         atomicAdd(&S.cbar, 1);
         unsigned spin = 0;
-        for (; lds_load(&S.cbar) < gen && spin < kFSpinCap; ++spin) __builtin_amdgcn_s_sleep(1);
-        if (spin == kFSpinCap) note_wait_timeout();
+        for (; lds_load(&S.cbar) < gen && !frame_aborted(S) && spin < kFSpinCap; ++spin) __builtin_amdgcn_s_sleep(1);
+        if (spin == kFSpinCap) wait_bound_reached(a, S);
+        stop = frame_aborted(S);
     }
+    stop = __builtin_amdgcn_readlane(stop, 0);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    return stop != 0;
 }
 
 // 16-byte stores possible for the frame: width and offset multiples of 4 pixels and
@@ -714,16 +744,19 @@ ORRB_INLINE bool frame_vec(const RenderArgs &a, int W, int64_t po) {
 ORRB_INLINE void frame_publish(const RenderArgs &a, FrameLds &S, int seq, int64_t po, int W, int H, int ntx, int n_busy,
                                int n_tiles, int lane) {
     const int slot = seq % kFSlots, n_empty = n_tiles - n_busy;
+    int stop = 0;
     if (lane == 0 && seq >= kFSlots) {
         unsigned spin = 0;
-        for (; spin < kFSpinCap; ++spin) {
+        for (; spin < kFSpinCap && !frame_aborted(S); ++spin) {
             bool free = lds_load(&S.bg_done[slot]) >= S.bgf[slot].n;
             for (int w = kFCW; w < kFW; ++w) free = free && lds_load(&S.cons_seq[w]) > seq - kFSlots;
             if (free) break;
             __builtin_amdgcn_s_sleep(2);
         }
-        if (spin == kFSpinCap) note_wait_timeout();
+        if (spin == kFSpinCap) wait_bound_reached(a, S);
+        stop = frame_aborted(S);
     }
+    if (__builtin_amdgcn_readlane(stop, 0)) return;  // stopped: publish nothing
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     for (int i = lane; i < n_empty; i += kWave) S.bg_tile[slot][i] = S.order[n_busy + i];
@@ -746,12 +779,13 @@ ORRB_INLINE void frame_publish(const RenderArgs &a, FrameLds &S, int seq, int64_
 // ---- staged busy tiles: a compute wave fills a slot, a store wave writes it out ----
 
 // Claim a free staging slot and fill it with the background for the whole tile (each
-// lane its 4-pixel group).  Waits while every slot is in use.
-ORRB_INLINE int stage_begin(FrameLds &S, int lane, int lj, int li0) {
-    int s = 0;
+// lane its 4-pixel group).  Waits while every slot is in use; -1 if the workgroup has
+// stopped.
+ORRB_INLINE int stage_begin(const RenderArgs &a, FrameLds &S, int lane, int lj, int li0) {
+    int s = -1;
     if (lane == 0) {
         unsigned spin = 0;
-        for (; spin < kFSpinCap; ++spin) {
+        for (; spin < kFSpinCap && !frame_aborted(S); ++spin) {
             int k = 0;
             for (; k < kFStage; ++k)
                 if (lds_load(&S.stage_state[k]) == 0 && atomicCAS(&S.stage_state[k], 0, 2) == 0) break;
@@ -761,9 +795,10 @@ ORRB_INLINE int stage_begin(FrameLds &S, int lane, int lj, int li0) {
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        if (spin == kFSpinCap) note_wait_timeout();
+        if (spin == kFSpinCap) wait_bound_reached(a, S);
     }
     s = __builtin_amdgcn_readlane(s, 0);
+    if (s < 0) return -1;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     const int p = lj * kFTileW + li0;
     uint4 z4;
@@ -903,7 +938,7 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
         int action = 0, st = 0;
         if (lane == 0) {
             unsigned spin = 0;
-            for (; spin < kFSpinCap; ++spin) {
+            for (; spin < kFSpinCap && !frame_aborted(S); ++spin) {
                 for (int k = 0; k < kFStage && !action; ++k)
                     if (lds_load(&S.stage_state[k]) == 1 && atomicCAS(&S.stage_state[k], 1, 3) == 1) {
                         action = 1;
@@ -923,7 +958,8 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
                 }
                 __builtin_amdgcn_s_sleep(2);
             }
-            if (spin == kFSpinCap) note_wait_timeout();
+            if (spin == kFSpinCap) wait_bound_reached(a, S);
+            if (frame_aborted(S)) action = 0;
         }
         action = __builtin_amdgcn_readlane(action, 0);
         if (!action) break;
@@ -962,7 +998,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     __shared__ FrameLds S;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     if (tid == 0) {
-        S.published = S.all_published = S.cbar = 0;
+        S.published = S.all_published = S.cbar = S.abort_flag = 0;
         for (int k = 0; k < kFSlots; ++k) S.bgf[k].n = S.bg_next[k] = S.bg_done[k] = 0;
         for (int k = 0; k < kFStage; ++k) S.stage_state[k] = 0;
         for (int w = 0; w < kFW; ++w) S.cons_seq[w] = kFStageWave && w == kFW - 1 ? 0x7fffffff : 0;
@@ -1009,11 +1045,11 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     for (int t = tid; t <= n_tiles; t += kFCT) S.cnt[t] = 0;
     if (tid < 8) S.misc[tid] = 0;
     const int n_verts = n_obj > 0 ? a.objs[fi.obj_begin + n_obj - 1].scene_vbase + a.objs[fi.obj_begin + n_obj - 1].n_verts : 0;
-    frame_barrier(S, gen);
+    if (frame_barrier(a, S, gen)) break;
     const int n_tris = n_obj > 0 ? S.o_tbase[n_obj - 1] + S.o_nt[n_obj - 1] : 0;
     for (int b = tid; b * kFHint < n_tris; b += kFCT) S.tri_hint[b] = object_hint(S.o_tbase, n_obj, b);
     for (int b = tid; b * kFHint < n_verts; b += kFCT) S.vtx_hint[b] = object_hint(S.o_vbase, n_obj, b);
-    frame_barrier(S, gen);
+    if (frame_barrier(a, S, gen)) break;
 
     // ---- phase 1: vertices, kFVN per thread per pass; the next pass's positions are
     // loaded before the current pass is transformed, hiding the load latency ----
@@ -1028,6 +1064,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         };
         int kn[kFVN];
         float4 pn[kFVN];
+        unsigned n_near = 0, n_guard = 0;
 #pragma unroll
         for (int r = 0; r < kFVN; ++r) {
             kn[r] = 0;
@@ -1049,11 +1086,17 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
 #pragma unroll
             for (int r = 0; r < kFVN; ++r) {
                 const int v = base + r * kFCT + tid;
-                if (v < n_verts) frame_vertex(S, v, k[r], p[r], fx, fy, cx, cy, nearp);
+                if (v < n_verts) {
+                    const int cull = frame_vertex(S, v, k[r], p[r], fx, fy, cx, cy, nearp);
+                    n_near += cull == 1;
+                    n_guard += cull == 2;
+                }
             }
         }
+        stat_add(a, ORRB_STAT_NEAR_VERTICES, n_near);  // rare: one atomic per thread that saw one
+        stat_add(a, ORRB_STAT_GUARD_VERTICES, n_guard);
     }
-    frame_barrier(S, gen);
+    if (frame_barrier(a, S, gen)) break;
 
     // ---- phase 2: set-up, per-tile counts, survivor list; kFTN triangles per thread
     // per pass, the next pass's mesh triangles loaded ahead ----
@@ -1093,7 +1136,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             }
         }
     }
-    frame_barrier(S, gen);
+    if (frame_barrier(a, S, gen)) break;
     if (wave == 0) {  // exclusive scan of n_tiles <= 256 counts (4 per lane) and the tile order
         int c[4], local = 0, ne = 0;
 #pragma unroll
@@ -1125,12 +1168,13 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             S.misc[2] = incl;
             S.misc[1] = overflow;
             S.misc[4] = overflow ? n_tiles : total_ne;
+            stat_add(a, ORRB_STAT_BIN_OVERFLOW, overflow ? 1u : 0u);
         }
         // queue the tiles no triangle touches for the store waves
         const int n_busy = overflow ? n_tiles : total_ne;
         frame_publish(a, S, seq, fi.pixel_offset, W, H, ntx, n_busy, n_tiles, lane);
     }
-    frame_barrier(S, gen);
+    if (frame_barrier(a, S, gen)) break;
     const bool overflow = S.misc[1] != 0;
 
     // ---- phase 3: scatter triangle IDs into the tile bins ----
@@ -1143,6 +1187,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                 for (int tx = tx0; tx <= tx1; ++tx) S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)(e >> 16);
         }
     } else if (!overflow) {  // too many survivors to remember: set them up again
+        if (tid == 0) stat_add(a, ORRB_STAT_SURVIVOR_RESETUP, 1u);
         for (int t = tid; t < n_tris; t += kFCT) {
             const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, t);
             TriSetup T;
@@ -1152,7 +1197,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                     S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)t;
         }
     }
-    frame_barrier(S, gen);
+    if (frame_barrier(a, S, gen)) break;
 
     // ---- phase 4: compute waves take the tiles with bin entries, rasterize, shade and
     // write them, issuing all loads of a tile before its stores; the store waves write
@@ -1162,7 +1207,8 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     const int n_busy = S.misc[4];
     const bool vec_frame = frame_vec(a, W, po);
     unsigned long long *vis = S.u.vis[wave];
-    while (true) {
+    bool stopped = false;
+    while (!stopped) {
         int slot = 0;
         if (lane == 0) slot = atomicAdd(&S.misc[0], 1);
         slot = __builtin_amdgcn_readlane(slot, 0);
@@ -1282,15 +1328,20 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                 pl[h] = p;
                 __builtin_amdgcn_sched_barrier(0);  // shade the two pixels one after the other
             }
-            if (stg < 0) stg = stage_begin(S, lane, lj, li0);
+            if (stg < 0) stg = stage_begin(a, S, lane, lj, li0);
+            if (stg < 0) break;  // the workgroup has stopped
 #pragma unroll
             for (int h = 0; h < 2; ++h)
                 if (kk[h] != kEmptyKey) stage_pixel(S, stg, pl[h], o[h], sg[h], kk[h]);
         }
-        if (stg < 0) stg = stage_begin(S, lane, lj, li0);
+        if (stg < 0) stg = stage_begin(a, S, lane, lj, li0);
+        if (stg < 0) {
+            stopped = true;
+            break;
+        }
         stage_end(S, stg, po, W, H, x0, y0, vec_frame, lane);
     }
-    frame_barrier(S, gen);  // the frame's LDS is reused by the next frame
+    if (frame_barrier(a, S, gen)) break;  // the frame's LDS is reused by the next frame
     }
     if (wave == 0 && lane == 0) __hip_atomic_store(&S.all_published, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }

@@ -55,6 +55,7 @@ ORRB_INLINE double compose_entry(const float *V, const float *Wp, int e) {
 
 struct Snapped {
     int X, Y, valid;
+    int cull;  // invalid vertices: 1 nearer than the near plane, 2 beyond the guard band
     float iw;  // fp32 1 / w
 };
 
@@ -69,14 +70,17 @@ ORRB_INLINE Snapped snap_vertex(const double *M, float4 p, double fx, double fy,
     const double w = -e2;
     Snapped s;
     s.valid = 0;
+    s.cull = 1;
     s.X = s.Y = 0;
     s.iw = 0.f;
     if (w >= nearp) {
         const double qx = e0 / w, qy = e1 / w;  // IEEE division, round to nearest
         const double sx = fma(fx, qx, cx), sy = fma(-fy, qy, cy);
         const double Xd = rint(256.0 * sx), Yd = rint(256.0 * sy);  // half to even
+        s.cull = 2;
         if (fabs(Xd) <= (double)kGuard && fabs(Yd) <= (double)kGuard) {
             s.valid = 1;
+            s.cull = 0;
             s.X = (int)Xd;
             s.Y = (int)Yd;
             s.iw = 1.0f / (float)w;

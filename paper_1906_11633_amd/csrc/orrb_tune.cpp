@@ -148,6 +148,10 @@ struct orrb_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int device = 0;
+    // what the captured kernel arguments point into, and its state at capture
+    const orrb_layout *layout = nullptr;
+    const orrb_context *ctx = nullptr;
+    uint64_t layout_gen = 0, ctx_gen = 0;
 };
 
 orrb_status orrb_graph_create(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
@@ -185,12 +189,22 @@ orrb_status orrb_graph_create(orrb_context *ctx, const orrb_layout *layout, cons
     G->graph = g;
     G->exec = ex;
     G->device = context_device(ctx);
+    G->layout = layout;
+    G->ctx = ctx;
+    G->layout_gen = layout_generation(layout);
+    G->ctx_gen = context_generation(ctx);
     *graph = G;
     return ORRB_OK;
 }
 
 orrb_status orrb_graph_launch(orrb_graph *graph, void *stream) {
     if (!graph) return set_error(ORRB_ERR_INVALID_ARGUMENT, "NULL graph");
+    // the captured arguments hold the layout's table pointers, item counts and tuning
+    // and the mesh pool's pointers: refuse the replay once either may have moved
+    if (layout_generation(graph->layout) != graph->layout_gen)
+        return set_error(ORRB_ERR_INVALID_ARGUMENT, "the layout's tuning or tables changed since the graph was captured");
+    if (context_generation(graph->ctx) != graph->ctx_gen)
+        return set_error(ORRB_ERR_INVALID_ARGUMENT, "the mesh pool grew since the graph was captured");
     const hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
     if (e != hipSuccess) return set_error(ORRB_ERR_DEVICE, hipGetErrorString(e));
     return ORRB_OK;

@@ -167,7 +167,7 @@ class Renderer:
         ws = torch.empty(max(int(inf.workspace_bytes_any), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
         return Job(lay, st, int(inf.total_pixels), ws)
 
-    def alloc_outputs(self, job: Job, tri_id=False, vis=False) -> Dict[str, torch.Tensor]:
+    def alloc_outputs(self, job: Job, tri_id=False, vis=False, stats=False) -> Dict[str, torch.Tensor]:
         P = job.total_pixels
         dev = f"cuda:{self.device}"
         out = dict(rgb=torch.empty(3 * P, dtype=torch.float32, device=dev),
@@ -178,12 +178,14 @@ class Renderer:
             out["tri_id"] = torch.empty(P, dtype=torch.int32, device=dev)
         if vis:
             out["vis"] = torch.empty(P, dtype=torch.int64, device=dev)
+        if stats:
+            out["stats"] = torch.zeros(L.STATS_WORDS, dtype=torch.int32, device=dev)
         return out
 
     def render(self, job: Job, out: Optional[Dict[str, torch.Tensor]] = None, tri_id=False, vis=False,
-               stream=None) -> Dict[str, torch.Tensor]:
+               stream=None, stats=False) -> Dict[str, torch.Tensor]:
         if out is None:
-            out = self.alloc_outputs(job, tri_id, vis)
+            out = self.alloc_outputs(job, tri_id, vis, stats)
         render_batch(self.ctx, job.layout, job.state, out, job.workspace, stream)
         return out
 
@@ -197,7 +199,7 @@ def render_batch(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], o
     par = L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
                    _ptr(s["light_intensity"]), _ptr(s["exposure"]))
     o = L.Outputs(_ptr(out.get("rgb")), _ptr(out.get("depth")), _ptr(out.get("normal")), _ptr(out.get("seg")),
-                  _ptr(out.get("tri_id")), _ptr(out.get("vis")))
+                  _ptr(out.get("tri_id")), _ptr(out.get("vis")), _ptr(out.get("stats")))
     st = stream if stream is not None else torch.cuda.current_stream(ctx.device)
     L.check(ctx.lib.orrb_render_batch(ctx.handle, layout.handle, C.byref(sc), C.byref(cam), C.byref(par), C.byref(o),
                                       _ptr(workspace), int(workspace.numel()), C.c_void_p(st.cuda_stream)))
@@ -210,7 +212,7 @@ def _structs(state, out):
     par = L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
                    _ptr(s["light_intensity"]), _ptr(s["exposure"]))
     o = L.Outputs(_ptr(out.get("rgb")), _ptr(out.get("depth")), _ptr(out.get("normal")), _ptr(out.get("seg")),
-                  _ptr(out.get("tri_id")), _ptr(out.get("vis")))
+                  _ptr(out.get("tri_id")), _ptr(out.get("vis")), _ptr(out.get("stats")))
     return sc, cam, par, o
 
 
@@ -296,3 +298,9 @@ def frame_planes(arr: torch.Tensor, pixel_offset, f: int, width: int, height: in
     po = int(pixel_offset[f])
     n = width * height
     return arr[planes * po: planes * po + planes * n].view(planes, height, width)
+
+
+def read_stats(stats: torch.Tensor) -> Dict[str, int]:
+    """The named counters of a stats destination (copied on its stream's order)."""
+    v = stats.detach().to("cpu").numpy().astype(np.int64) & 0xffffffff
+    return {k: int(v[i]) for i, k in enumerate(L.STAT_NAMES)}

@@ -9,13 +9,16 @@ stalls (Sec. 4.4).  This server is the in-process equivalent on one MI355X:
   (Single Scene Multiple States, Sec. 3); a request names pool scenes and a
   resolution;
 * admission by memory: a request is admitted when the device-memory budget (and a
-  launch slot) has room for its outputs and gathered state; otherwise it waits, in
-  arrival order;
+  launch slot) has room for its outputs, its gathered state and the workspace of the
+  launch it joins (frames on the tiled path need 16 B per vertex instance); the
+  tables of the cached layouts count against the same budget for as long as they are
+  cached; otherwise it waits, in arrival order;
 * continuous batching: whenever a launch slot is free, every admitted request that
   is waiting is merged into one render launch (one layout, one kernel), while earlier
   launches are still running on other streams, so their work overlaps on the device;
 * per request, latency = completion (stream event observed) - arrival, reported as
-  p50 / p99 next to the frames/s served.
+  p50 / p99 next to the frames/s served; each launch's counters (wait timeouts and
+  the like) are read when it completes and summed into the statistics.
 
 The per-pixel arithmetic does not depend on batch composition, so a request's
 result is bit-identical alone and in any mix.
@@ -31,6 +34,7 @@ import numpy as np
 import torch
 
 from . import scenes as S
+from . import _lib
 from .renderer import Context, Layout, render_batch
 
 LIGHTS_PER_SCENE = 4   # lights padded with zero-intensity ones (they add exactly 0)
@@ -152,6 +156,7 @@ class _Launch:
     event: torch.cuda.Event
     stream: torch.cuda.Stream
     bytes: int
+    stats: Optional[torch.Tensor] = None
     keep: list = field(default_factory=list)
 
 
@@ -160,10 +165,15 @@ class Server:
 
     def __init__(self, ctx: Context, pool: ScenePool, budget_bytes: int = 64 << 30, n_streams: int = 4,
                  max_batch_frames: int = 1536, max_inflight: int = 8, keep_results: bool = False,
-                 layout_cache: int = 256):
+                 layout_cache: int = 256, tuning=None):
+        """`tuning` (tile_w, tile_h, bin_cap, persistent, path) is set on every layout
+        the server builds (None: the default, frame path where scenes fit)."""
         self.ctx, self.pool = ctx, pool
         self.budget = int(budget_bytes)
-        self.used = 0
+        self.used = 0          # outputs, state and workspace of launches in flight
+        self.table_bytes = 0   # device tables of the cached layouts
+        self.tuning = tuning
+        self.counters = {k: 0 for k in _lib.STAT_NAMES}
         self.streams = [torch.cuda.Stream(device=pool.device) for _ in range(n_streams)]
         self.next_stream = 0
         self.max_batch_frames = max_batch_frames
@@ -180,12 +190,25 @@ class Server:
         self.workspace = torch.empty(256, dtype=torch.uint8, device=pool.device)  # frame path: untouched
 
     # -- admission ------------------------------------------------------------------
-    def need_bytes(self, r: Request) -> int:
+    def data_bytes(self, r: Request) -> int:
+        """Outputs and gathered state of a request."""
         return r.out_bytes + len(r.scene_ids) * self.pool.state_bytes_per_scene
 
+    @staticmethod
+    def _workspace_bytes(lay: Layout) -> int:
+        n = int(lay.info.workspace_bytes)
+        return n if n > 256 else 0  # frame-path launches share the server's small buffer
+
+    def need_bytes(self, r: Request) -> int:
+        """Device bytes the request needs when launched alone: outputs, state and the
+        workspace of its layout (the layout's tables are counted while it is cached)."""
+        return self.data_bytes(r) + self._workspace_bytes(self._layout([r]))
+
     def submit(self, r: Request):
-        if self.need_bytes(r) > self.budget:
-            raise ValueError(f"request {r.rid} needs {self.need_bytes(r)} bytes, above the whole budget")
+        need = self.need_bytes(r)
+        if need + self.table_bytes > self.budget:
+            raise ValueError(f"request {r.rid} needs {need} bytes (outputs, state, workspace) besides "
+                             f"{self.table_bytes} bytes of layout tables: above the whole budget")
         self.queue.append(r)
 
     def _layout(self, reqs: List[Request]) -> Layout:
@@ -196,33 +219,63 @@ class Server:
             local = np.tile(self.pool.object_mesh, int(desc["n_scenes"]))
             lay = Layout(self.ctx, _LayoutDesc(desc, self.pool.meshes, local),
                          mesh_ids=self.pool.mesh_ids)
+            if self.tuning is not None:
+                lay.set_tuning(*self.tuning)
             self.layouts[key] = lay
+            self.table_bytes += int(lay.info.table_bytes)
             if len(self.layouts) > self.layout_cache:
                 _, old = self.layouts.popitem(last=False)
                 torch.cuda.synchronize()  # no launch may still use the evicted layout
+                self.table_bytes -= int(old.info.table_bytes)
                 old.close()
         else:
             self.layouts.move_to_end(key)
         return lay
 
+    def _evict_except(self, keep: Layout):
+        for key in [k for k, v in self.layouts.items() if v is not keep]:
+            old = self.layouts.pop(key)
+            self.table_bytes -= int(old.info.table_bytes)
+            old.close()
+
     def _dispatch(self, now: float):
         """Merge every waiting request that fits into one launch on the next stream."""
         if not self.queue or len(self.inflight) >= self.max_inflight:
             return
-        group, frames, need = [], 0, 0
+        group, frames, data = [], 0, 0
+        free = self.budget - self.used - self.table_bytes
         while self.queue:
             r = self.queue[0]
-            nb = self.need_bytes(r)
-            if self.used + need + nb > self.budget or (group and frames + r.n_frames > self.max_batch_frames):
+            nb = self.data_bytes(r)
+            if data + nb > free or (group and frames + r.n_frames > self.max_batch_frames):
                 break
             self.queue.popleft()
-            r.t_admit = now
             group.append(r)
             frames += r.n_frames
-            need += nb
+            data += nb
+        # the merged launch's workspace must fit as well: give back the latest requests
+        # until it does (a request that fits alone waits for launches to complete)
+        lay, need = None, 0
+        while group:
+            lay = self._layout(group)
+            need = data + self._workspace_bytes(lay)
+            if self.used + self.table_bytes + need <= self.budget:
+                break
+            if len(group) == 1 and not self.inflight:
+                # alone with nothing running: drop the other cached layouts' tables
+                self._evict_except(lay)
+                if self.table_bytes + need <= self.budget:
+                    break
+                raise RuntimeError(f"request {group[0].rid} needs {need} bytes and its layout "
+                                   f"{self.table_bytes}: it cannot run within the budget")
+            r = group.pop()
+            self.queue.appendleft(r)
+            frames -= r.n_frames
+            data -= self.data_bytes(r)
         if not group:
             return
-        lay = self._layout(group)
+        for r in group:
+            r.t_admit = now
         desc, oi, li, fi, intr = self.pool.batch_desc(group)
         stream = self.streams[self.next_stream]
         self.next_stream = (self.next_stream + 1) % len(self.streams)
@@ -247,6 +300,7 @@ class Server:
             # streams must not share it
             ws_need = int(lay.info.workspace_bytes)
             ws = self.workspace if ws_need <= 256 else torch.empty(ws_need, dtype=torch.uint8, device=dev)
+            out["stats"] = torch.zeros(_lib.STATS_WORDS, dtype=torch.int32, device=dev)
             render_batch(self.ctx, lay, st, out, ws, stream=stream)
             ev = torch.cuda.Event()
             ev.record(stream)
@@ -260,7 +314,7 @@ class Server:
                                 normal=out["normal"][3 * p0:3 * (p0 + n)], seg=out["seg"][p0:p0 + n])
             p0 += r.pixels
         self.used += need
-        self.inflight.append(_Launch(group, ev, stream, need, keep=[st, out, idx, ws]))
+        self.inflight.append(_Launch(group, ev, stream, need, stats=out["stats"], keep=[st, out, idx, ws]))
         self.launches += 1
         self.launch_frames += frames
         self.max_inflight_seen = max(self.max_inflight_seen, len(self.inflight))
@@ -274,6 +328,10 @@ class Server:
                     r.t_done = t
                     self.done.append(r)
                 self.used -= L.bytes
+                if L.stats is not None:  # complete: a plain copy, no device-wide wait
+                    v = L.stats.cpu().numpy().astype(np.int64) & 0xffffffff
+                    for i, k in enumerate(_lib.STAT_NAMES):
+                        self.counters[k] += int(v[i])
             else:
                 still.append(L)
         self.inflight = still
@@ -310,7 +368,7 @@ class Server:
                     mean_queue_wait_ms=float(wait.mean()) if wait.size else None,
                     launches=self.launches, mean_requests_per_launch=len(self.done) / max(self.launches, 1),
                     mean_frames_per_launch=self.launch_frames / max(self.launches, 1),
-                    max_inflight=self.max_inflight_seen)
+                    max_inflight=self.max_inflight_seen, wait_timeouts=self.counters["wait_timeouts"])
 
 
 def poisson_trace(pool: ScenePool, rate: float = 2000.0, duration: float = 10.0, warmup: float = 0.0, seed: int = 5,

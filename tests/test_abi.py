@@ -95,3 +95,17 @@ def test_paper_context_fixture():
     assert d["table2_gpu_scaling"] == {"1": 1342, "2": 2870, "3": 3395, "4": 3514}
     t3 = [d["table3_render_servers_on_8_gpus"][k] for k in sorted(d["table3_render_servers_on_8_gpus"], key=int)]
     assert t3 == sorted(t3) and t3[0] == 736 and t3[-1] == 3438
+
+
+def test_stat_words_match_header():
+    """The binding's names of the per-call counters follow the header's word indices."""
+    from paper_1906_11633_amd import _lib as L
+    text = open(HEADER).read()
+    words = {m.group(1).lower(): int(m.group(2)) for m in re.finditer(r"#define ORRB_STAT_([A-Z_]+)\s+(\d+)", text)}
+    assert int(re.search(r"#define ORRB_STATS_WORDS\s+(\d+)", text).group(1)) == L.STATS_WORDS
+    header_order = [k for k, _ in sorted(words.items(), key=lambda kv: kv[1])]
+    assert [v for _, v in sorted(words.items(), key=lambda kv: kv[1])] == list(range(len(words)))
+    expect = {"wait_timeouts": "wait_timeouts", "bin_overflow_frames": "bin_overflow",
+              "survivor_resetup_frames": "survivor_resetup", "near_vertices": "near_vertices",
+              "guard_vertices": "guard_vertices", "tiled_extra_flushes": "tiled_extra_flush"}
+    assert [expect[n] for n in L.STAT_NAMES] == header_order
