@@ -225,6 +225,24 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *layout, cons
                               const orrb_cameras *cameras, const orrb_params *params, const orrb_outputs *out,
                               void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same as orrb_render_batch
+ * (same kernels, same output bits) with the workspace taken from a fixed array in the
+ * library's device image: ORRB_NOALLOC_SCRATCH_BYTES per device, resolved once by
+ * orrb_create and held until the process ends.  The call allocates nothing (no
+ * hipMalloc, no hipFree, no allocating library routine).  Every call on one device
+ * shares that array and the kernels reuse it in place, so calls that overlap on one
+ * device (other streams, other threads, other contexts) race and must be serialized
+ * by the caller; consecutive calls on one stream are safe.  Errors: as
+ * orrb_render_batch, plus ORRB_ERR_UNSUPPORTED (with nothing enqueued) when the
+ * batch needs more workspace than the array holds (orrb_layout_info.workspace_bytes
+ * > ORRB_NOALLOC_SCRATCH_BYTES; the frame path needs a few hundred bytes, the tiled
+ * path 16 bytes per vertex instance plus 64 per object instance). */
+#define ORRB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+orrb_status orrb_render_batch_noalloc(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
+                                      const orrb_cameras *cameras, const orrb_params *params,
+                                      const orrb_outputs *out, void *stream);
+
 /* --------------------------------------------------------------------------------- */
 /* batched form: autotuning and graph replay                                          */
 /* --------------------------------------------------------------------------------- */

@@ -18,6 +18,7 @@ ORRB_OK = 0
 STATUS_NAMES = {0: "ORRB_OK", 1: "ORRB_ERR_INVALID_ARGUMENT", 2: "ORRB_ERR_OUT_OF_MEMORY",
                 3: "ORRB_ERR_WORKSPACE_TOO_SMALL", 4: "ORRB_ERR_DEVICE", 5: "ORRB_ERR_UNSUPPORTED"}
 MAX_LIGHTS_PER_SCENE = 8
+NOALLOC_SCRATCH_BYTES = 64 << 20  # ORRB_NOALLOC_SCRATCH_BYTES
 # words of the per-call stats destination (orrb_outputs.stats)
 STATS_WORDS = 8
 STAT_NAMES = ("wait_timeouts", "bin_overflow_frames", "survivor_resetup_frames", "near_vertices", "guard_vertices",
@@ -92,6 +93,8 @@ SIGNATURES = {
     "orrb_layout_set_tuning": (C.c_int, [P, C.POINTER(Tuning)]),
     "orrb_render_batch": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params),
                                     C.POINTER(Outputs), P, C.c_size_t, P]),
+    "orrb_render_batch_noalloc": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params),
+                                            C.POINTER(Outputs), P]),
     "orrb_autotune": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params), C.POINTER(Outputs),
                                 P, C.c_size_t, P, C.c_char_p, C.POINTER(Tuning), C.POINTER(C.c_double)]),
     "orrb_graph_create": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params),

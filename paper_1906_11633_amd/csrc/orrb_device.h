@@ -118,5 +118,11 @@ hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu);
 hipError_t read_wait_timeouts(unsigned int *out);  // frame-kernel waits that hit their bound
 bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height);
 size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap);
+// render call shared by orrb_render_batch and orrb_render_batch_noalloc (orrb_host.cpp)
+orrb_status render_impl(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+                        const orrb_params *par, const orrb_outputs *out, void *workspace, size_t workspace_bytes,
+                        void *stream, bool timing);
+size_t render_workspace_bytes(const orrb_layout *L);  // workspace of one render call (current tuning)
+hipError_t scratch_init(int device);  // resolve the device's copy of the fixed scratch (orrb_noalloc.cpp)
 
 }  // namespace orrb

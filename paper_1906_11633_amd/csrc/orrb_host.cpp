@@ -410,6 +410,14 @@ orrb_status orrb_create(int hip_device, orrb_context **out) {
     if (!c) return fail(ORRB_ERR_OUT_OF_MEMORY, "host allocation failed");
     c->device = hip_device;
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    {
+        // the device's copy of the fixed scratch array (orrb_render_batch_noalloc)
+        const hipError_t e = scratch_init(hip_device);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(ORRB_ERR_DEVICE, "scratch set-up on device %d failed: %s", hip_device, hipGetErrorString(e));
+        }
+    }
     *out = c;
     return ORRB_OK;
 }
@@ -651,9 +659,11 @@ orrb_status orrb_layout_set_tuning(orrb_layout *L, const orrb_tuning *t) {
 
 }  // extern "C"
 
+size_t orrb::render_workspace_bytes(const orrb_layout *L) { return ws_layout(L).total; }
+
 // A render call: host checks, then the kernels on `stream`.  With `timing` false it
 // records no kernel-timing events (and so creates none).
-static orrb_status render_impl(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
                                const orrb_params *par, const orrb_outputs *out, void *workspace,
                                size_t workspace_bytes, void *stream, bool timing) {
     if (!ctx || !L || !sc || !cam || !par || !out) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL handle or struct");

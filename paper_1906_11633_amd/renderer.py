@@ -205,6 +205,17 @@ def render_batch(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], o
                                       _ptr(workspace), int(workspace.numel()), C.c_void_p(st.cuda_stream)))
 
 
+def render_batch_noalloc(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], out: Dict[str, torch.Tensor],
+                         stream=None):
+    """orrb_render_batch_noalloc on `stream`: the workspace comes from the library's fixed
+    per-device array, so the call allocates nothing.  Calls that overlap on one device
+    race on that array."""
+    sc, cam, par, o = _structs(state, out)
+    st = stream if stream is not None else torch.cuda.current_stream(ctx.device)
+    L.check(ctx.lib.orrb_render_batch_noalloc(ctx.handle, layout.handle, C.byref(sc), C.byref(cam), C.byref(par),
+                                              C.byref(o), C.c_void_p(st.cuda_stream)))
+
+
 def _structs(state, out):
     s = state
     sc = L.Scenes(_ptr(s["object_pose"]), _ptr(s["object_seg"]), _ptr(s["object_visible"]))
