@@ -118,6 +118,41 @@ def _pct(xs, q):
     return round(float(np.percentile(np.asarray(xs), q)), 4)
 
 
+def measure_aux(args, r, S, batch, job, torch, frame_ms_plain):
+    """The same workload with the auxiliary outputs on: the transparency channel and
+    the Tracker records written by the frame kernel, and the post-processed 3 x 8-bit
+    RGB written by k_post from the fp32 rgb (colour grading and grain randomized per
+    frame).  k_post moves 15 B per pixel (12 read, 3 written)."""
+    import ctypes as C
+    from paper_1906_11633_amd import _lib
+    post, grain = S.postprocess_params(2, batch.n_frames, batch.frame_scene)
+    job.state["post"] = torch.from_numpy(post).cuda()
+    job.state["grain"] = torch.from_numpy(grain).cuda()
+    out = r.alloc_outputs(job, alpha=True, rgb8=True, track=True)
+    lib, ctx = r.ctx.lib, r.ctx.handle
+    for _ in range(3):
+        r.render(job, out)
+    torch.cuda.synchronize()
+    n = max(10, args.steps // 4)
+    _lib.check(lib.orrb_profile_enable(ctx, 1))
+    dt = _timed(lambda: r.render(job, out), n, torch)
+    kt = _lib.KernelTimes()
+    _lib.check(lib.orrb_profile_read(ctx, C.byref(kt)))
+    _lib.check(lib.orrb_profile_enable(ctx, 0))
+    del job.state["post"], job.state["grain"]
+    frame_ms = kt.frame_ms / max(kt.frame_launches, 1)
+    post_ms = kt.post_ms / max(kt.post_launches, 1)
+    P = batch.total_pixels
+    pbytes = 15 * P
+    return dict(ms_per_step=round(dt * 1e3, 4), frames_per_s=round(batch.n_frames / dt, 1),
+                k_frame_ms=round(frame_ms, 4), k_frame_ms_without=round(frame_ms_plain, 4),
+                k_frame_overhead=round(frame_ms / frame_ms_plain - 1, 4) if frame_ms_plain else None,
+                k_post=dict(ms=round(post_ms, 4), bytes_per_launch=pbytes,
+                            roofline=dict(bound="hbm", achieved=round(pbytes / (post_ms * 1e-3) / 1e9, 1),
+                                          peak=HBM_PEAK_GBS, unit="GB/s",
+                                          frac=round(pbytes / (post_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))))
+
+
 def measure_extras(args, r, S):
     """Shading-gradient throughput (64 scenes x 3 cameras at 200x200), the serving loop
     (Poisson 2000 req/s of 1-32 scenes at 64/128/200 px), and the uneven batch (1024
@@ -328,6 +363,9 @@ def main(argv=None):
     fms = sorted(fev)[len(fev) // 2]
     extra["store_ceiling_gbs"] = round(bytes_per_launch / (fms * 1e-3) / 1e9, 1)
     extra["store_ceiling_frac"] = round(bytes_per_launch / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    extra["aux_outputs"] = measure_aux(args, r, S, batch, job, torch, kernel_ms["k_frame"])
+    print(f"[bench] with alpha, tracker and rgb8: {extra['aux_outputs']['ms_per_step']:.3f} ms/step, "
+          f"k_post {extra['aux_outputs']['k_post']['ms']:.3f} ms", file=sys.stderr, flush=True)
     for _ in range(2):
         r.render(job, out)  # the outputs hold the render again
 

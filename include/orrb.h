@@ -181,7 +181,49 @@ typedef struct {                  /* sampled randomization parameters */
     const float *light_vec;       /* [L,3] world position (point) or direction (directional) */
     const float *light_intensity; /* [L] */
     const float *exposure;        /* [F] linear post-processing gain */
+    /* Post-processing of the 8-bit output (Sec. 4.3.1 PostprocessingRandomizer: colour
+     * grading and grain; used only when orrb_outputs.rgb8 is set).  `post` [F,
+     * ORRB_POST_WORDS] per frame, words ORRB_POST_*; NULL = identity grading, no grain.
+     * `grain` [3, grain_h, grain_w] noise texture with values in [0, 1) (NULL = no
+     * grain).  Per channel c of pixel (i, j), from the linear rgb:
+     *   1. white balance: c *= (1 + T/5, 1 - G/5, 1 - T/5)[c];
+     *   2. clamp to [0, 1] and encode with the sRGB transfer function (IEC 61966-2-1);
+     *   3. c = 1/2 + k (Y + s (c - Y) - 1/2), Y = Rec. 709 luma of the encoded pixel;
+     *   4. rotate (r, g, b) by the hue angle h about the grey axis;
+     *   5. grain: c += I ((1 - kappa) g0 + kappa g_c - 1/2), g at texel
+     *      ((i div S + ox) mod grain_w, (j div S + oy) mod grain_h);
+     *   6. code = floor(255 clamp(c, 0, 1) + 1/2), evaluated in fp32. */
+    const float *post;
+    const float *grain;
+    int32_t grain_w, grain_h;
 } orrb_params;
+
+#define ORRB_POST_WORDS 12
+#define ORRB_POST_TEMPERATURE 0  /* T, white balance warm (+) / cool (-) */
+#define ORRB_POST_TINT 1         /* G, magenta (+) / green (-) */
+#define ORRB_POST_HUE 2          /* h, radians */
+#define ORRB_POST_SATURATION 3   /* s, 1 = unchanged */
+#define ORRB_POST_CONTRAST 4     /* k, 1 = unchanged */
+#define ORRB_POST_GRAIN 5        /* I, grain intensity */
+#define ORRB_POST_GRAIN_COLOR 6  /* kappa in [0, 1]: 0 = the same noise on every channel */
+#define ORRB_POST_GRAIN_SIZE 7   /* S >= 1, pixels per grain texel (integer-valued) */
+#define ORRB_POST_GRAIN_X 8      /* ox, texel offset (integer-valued, >= 0) */
+#define ORRB_POST_GRAIN_Y 9      /* oy, texel offset (integer-valued, >= 0) */
+
+/* Tracker record (Sec. 4.3.2: screen-space coordinates and bounding boxes of the
+ * tracked objects), one per (frame, object of the frame's scene): frame f's records
+ * start at sum over earlier frames of their scene's object count, in scene order.
+ * count, the box and the sums cover the pixels whose nearest fragment belongs to the
+ * object (exact integers); the box is inclusive, (INT32_MAX, INT32_MAX, -1, -1) when
+ * count is 0; the centroid is sum / count + 1/2.  (x, y) is the object frame's origin
+ * projected with the frame's camera (pixels, y down) and w its eye depth along -z
+ * (computed in FP64; x = y = NaN when w <= 0), hidden objects included. */
+typedef struct {
+    int32_t count;
+    int32_t i_min, j_min, i_max, j_max;
+    float x, y, w;
+    uint64_t sum_i, sum_j;
+} orrb_track;
 
 /* Counters of one render call, written by its kernels into caller memory (the
  * `stats` destination of orrb_outputs).  The kernels ADD to the words, so a caller
@@ -211,6 +253,11 @@ typedef struct {                  /* destinations; rgb, depth, normal, seg may e
     uint64_t *vis;                /* [P] or NULL: visibility key (fp32 depth bits << 32 | tri_id),
                                      ~0 for background; input of orrb_shade_backward */
     uint32_t *stats;              /* [ORRB_STATS_WORDS] or NULL: counters added to by the call */
+    float *alpha;                 /* [P] or NULL: transparency channel (Sec. 4.4), 1 where a
+                                     triangle covers the pixel centre, 0 for background */
+    uint8_t *rgb8;                /* [3P] or NULL: post-processed 3 x 8-bit RGB, planar like
+                                     rgb (needs rgb: it is computed from the written rgb) */
+    orrb_track *track;            /* [sum over frames of the scene's objects] or NULL */
 } orrb_outputs;
 
 /* Render every frame of the layout.  `scenes`, `cameras`, `params`, `out` are host
@@ -320,6 +367,8 @@ typedef struct {
     double raster_ms;          /* summed device time of k_raster_shade launches (tiled path) */
     double frame_ms;           /* summed device time of k_frame launches (frame path) */
     int64_t vertex_launches, raster_launches, frame_launches;
+    double post_ms;            /* summed device time of k_post launches (rgb8 output) */
+    int64_t post_launches;
 } orrb_kernel_times;
 
 /* Enable (1) or disable (0) per-kernel timing and reset the totals.  While enabled,

@@ -49,7 +49,7 @@ def open_library(path: str):
     lib = C.CDLL(path)
     P = C.c_void_p
     inputs = [P] * 17 + [C.c_int32] + [P] * 8
-    lib.oracle_render.argtypes = inputs + [P] * 7 + [C.c_int32]
+    lib.oracle_render.argtypes = inputs + [P] * 8 + [C.c_int32]
     lib.oracle_render.restype = C.c_int
     lib.oracle_shade_grad.argtypes = inputs + [C.c_int32, P, P, P, P, P, P, P, P, P, P, C.c_int32]
     lib.oracle_shade_grad.restype = C.c_int
@@ -133,18 +133,22 @@ def render(batch, threads: int = 0) -> dict:
 
     Keys: rgb f64[3*P], depth f64[P], normal f64[3*P], seg i32[P], tri_id i32[P],
     depth2 f64[P] (second-nearest fragment depth, +inf if none), frag_count i32[P],
-    pixel_offset i64[F+1]; P = total pixels."""
+    obj_id i32[P] (global object of the nearest fragment, -1 background),
+    alpha f64[P] (1 covered, 0 background), pixel_offset i64[F+1]; P = total pixels."""
     pk = _pack(batch)
     P = pk.total_pixels
     out = dict(rgb=np.zeros(3 * P), depth=np.zeros(P), normal=np.zeros(3 * P),
                seg=np.zeros(P, np.int32), tri_id=np.zeros(P, np.int32), depth2=np.zeros(P),
-               frag_count=np.zeros(P, np.int32))
+               frag_count=np.zeros(P, np.int32), obj_id=np.zeros(P, np.int32))
     rc = _load().oracle_render(*pk.args(), _ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["normal"]),
                                _ptr(out["seg"]), _ptr(out["tri_id"]), _ptr(out["depth2"]),
-                               _ptr(out["frag_count"]), int(threads))
+                               _ptr(out["frag_count"]), _ptr(out["obj_id"]), int(threads))
     if rc != 0:
         raise MemoryError("oracle_render failed")
     out["pixel_offset"] = pk.pixel_offset
+    # Sec. 4.4: RGB "optionally with" a transparency channel.  No material is
+    # transparent here, so alpha is the coverage of the pixel centre.
+    out["alpha"] = (out["tri_id"] >= 0).astype(np.float64)
     return out
 
 
@@ -203,3 +207,125 @@ def frame_view(arr: np.ndarray, pixel_offset, f: int, width: int, height: int, p
     po = int(pixel_offset[f])
     n = width * height
     return arr[planes * po: planes * po + planes * n].reshape(planes, height, width)
+
+
+# ----------------------------------------------------------------------------------
+# Tracker (Sec. 4.3.2): auxiliary per-object outputs of a rendered frame
+# ----------------------------------------------------------------------------------
+
+TRACK_EMPTY_MIN = 2 ** 31 - 1  # i_min / j_min of an object with no visible pixel
+
+
+def track(batch, out) -> dict:
+    """Tracker outputs (Sec. 4.3.2: screen-space coordinates and bounding boxes of the
+    tracked objects) for every (frame, object of the frame's scene), frames in order and
+    a scene's objects in scene order.
+
+    From the rendered visibility (``out`` of :func:`render`): ``count`` = pixels whose
+    nearest fragment belongs to the object; ``bbox`` = (i_min, j_min, i_max, j_max), the
+    inclusive pixel range of those pixels ((2^31-1, 2^31-1, -1, -1) when count is 0);
+    ``sum_i`` / ``sum_j`` = sums of their column / row indices (the centroid is
+    sum / count + 1/2 in pixel coordinates).  ``origin`` = (x, y, w): the object frame's
+    origin projected with the frame's pinhole camera (origin at the image's top-left
+    corner, y down) and its eye depth w along -z, in FP64; x = y = NaN when w <= 0."""
+    b = batch
+    po = out["pixel_offset"]
+    obj_id = out["obj_id"]
+    rows = []
+    for f in range(b.n_frames):
+        s = int(b.frame_scene[f])
+        W, H = int(b.width[f]), int(b.height[f])
+        ids = obj_id[po[f]: po[f] + W * H].reshape(H, W)
+        V = np.asarray(b.view[f], np.float32).astype(np.float64)
+        fx, fy, cx, cy = np.asarray(b.intr[f], np.float32).astype(np.float64)
+        for o in range(int(b.scene_object_begin[s]), int(b.scene_object_begin[s + 1])):
+            jj, ii = np.nonzero(ids == o)
+            t = np.asarray(b.object_pose[o], np.float32).astype(np.float64)[:, 3]
+            e = V[:, :3] @ t + V[:, 3]
+            w = -e[2]
+            x, y = (fx * e[0] / w + cx, -fy * e[1] / w + cy) if w > 0 else (np.nan, np.nan)
+            n = ii.size
+            rows.append((n, ii.min() if n else TRACK_EMPTY_MIN, jj.min() if n else TRACK_EMPTY_MIN,
+                         ii.max() if n else -1, jj.max() if n else -1, int(ii.sum()), int(jj.sum()), x, y, w))
+    a = np.array(rows, dtype=object).reshape(-1, 10)
+    return dict(count=a[:, 0].astype(np.int64), bbox=a[:, 1:5].astype(np.int64), sum_i=a[:, 5].astype(np.int64),
+                sum_j=a[:, 6].astype(np.int64), origin=a[:, 7:10].astype(np.float64))
+
+
+# ----------------------------------------------------------------------------------
+# Post-processing and 3 x 8-bit encoding (Sec. 4.3.1 PostprocessingRandomizer:
+# colour grading hue, saturation, contrast, temperature, tint and grain; Sec. 5:
+# 200 x 200 images in 3 x 8-bit RGB).  The paper names the parameters, not the
+# formulas; the definitions below are this implementation's reading.
+# ----------------------------------------------------------------------------------
+
+POST_WORDS = 12  # per-frame parameter words (see postprocess)
+LUMA = np.array([0.2126, 0.7152, 0.0722])  # Rec. 709 luma weights
+
+
+def srgb_encode(x):
+    """sRGB transfer function (IEC 61966-2-1) of linear values in [0, 1]."""
+    x = np.asarray(x, np.float64)
+    return np.where(x <= 0.0031308, 12.92 * x, 1.055 * np.power(x, 1.0 / 2.4) - 0.055)
+
+
+def hue_rotation(h):
+    """Rotation by angle h (radians) about the grey axis (1, 1, 1)/sqrt(3) (Rodrigues)."""
+    u = np.ones(3) / np.sqrt(3.0)
+    K = np.array([[0, -u[2], u[1]], [u[2], 0, -u[0]], [-u[1], u[0], 0]])
+    return np.cos(h) * np.eye(3) + np.sin(h) * K + (1 - np.cos(h)) * np.outer(u, u)
+
+
+def postprocess(batch, rgb, post=None, grain=None):
+    """Colour grading, grain and 8-bit encoding of linear rgb (planar like the render's
+    rgb, exposure already applied), per frame and pixel, in FP64.
+
+    ``post`` f[F, 12] per frame: 0 temperature T, 1 tint G, 2 hue h (radians),
+    3 saturation s, 4 contrast k, 5 grain intensity I, 6 grain coloration kappa,
+    7 grain size S (pixels, integer >= 1), 8-9 grain texture offset (ox, oy) (integer
+    texels), 10-11 unused.  None = identity grading, no grain.  ``grain`` f[3, GH, GW]
+    in [0, 1) or None (no grain).  Steps, each channel c of pixel (i, j):
+
+    1. white balance: c *= (1 + T/5, 1 - G/5, 1 - T/5)[c]  (warm/cool, magenta/green);
+    2. clamp to [0, 1] and encode with the sRGB transfer function;
+    3. saturation about the Rec. 709 luma Y, then contrast about 1/2:
+       c = 1/2 + k (Y + s (c - Y) - 1/2);
+    4. hue: rotate (r, g, b) by h about the grey axis;
+    5. grain: c += I ((1 - kappa) g0 + kappa gc - 1/2), g sampled at texel
+       ((i div S + ox) mod GW, (j div S + oy) mod GH);
+    6. v = 255 clamp(c, 0, 1); code = floor(v + 1/2).
+
+    Returns (codes u8[3P], v f64[3P])."""
+    b = batch
+    rgb = np.asarray(rgb, np.float64).reshape(-1)
+    po = b.pixel_offset
+    codes = np.zeros(rgb.shape[0], np.uint8)
+    vals = np.zeros(rgb.shape[0], np.float64)
+    for f in range(b.n_frames):
+        W, H = int(b.width[f]), int(b.height[f])
+        P = W * H
+        p = np.zeros(POST_WORDS) if post is None else np.asarray(post[f], np.float32).astype(np.float64)
+        if post is None:
+            p[3] = p[4] = p[7] = 1.0
+        T, G, h, s, k, I, kap = p[:7]
+        S = max(1, int(np.floor(p[7])))
+        ox, oy = int(p[8]), int(p[9])
+        c = rgb[3 * po[f]: 3 * po[f] + 3 * P].reshape(3, P).T.copy()  # [P, 3]
+        c *= np.array([1 + T / 5, 1 - G / 5, 1 - T / 5])
+        e = srgb_encode(np.clip(c, 0.0, 1.0))
+        Y = e @ LUMA
+        q = 0.5 + k * (Y[:, None] + s * (e - Y[:, None]) - 0.5)
+        r = q @ hue_rotation(h).T
+        if grain is not None and I != 0:
+            g = np.asarray(grain, np.float32).astype(np.float64)
+            GH, GW = g.shape[1], g.shape[2]
+            jj, ii = np.divmod(np.arange(P), W)
+            tx = (ii // S + ox) % GW
+            ty = (jj // S + oy) % GH
+            g0 = g[0, ty, tx]
+            n = np.stack([(1 - kap) * g0 + kap * g[ch, ty, tx] - 0.5 for ch in range(3)], axis=1)
+            r = r + I * n
+        v = 255.0 * np.clip(r, 0.0, 1.0)
+        vals[3 * po[f]: 3 * po[f] + 3 * P] = v.T.reshape(-1)
+        codes[3 * po[f]: 3 * po[f] + 3 * P] = np.floor(v + 0.5).astype(np.uint8).T.reshape(-1)
+    return codes, vals

@@ -373,7 +373,7 @@ static void frame_end(FrameWork *fw) {
 }
 
 static void render_frame(const Inputs *in, int f, double *rgb, double *depth, double *normal, int32_t *seg,
-                         int32_t *tri_id, double *depth2, int32_t *frag_count, int *err) {
+                         int32_t *tri_id, double *depth2, int32_t *frag_count, int32_t *obj_id, int *err) {
     FrameWork fw;
     if (frame_begin(in, f, &fw)) {
         *err = 1;
@@ -391,6 +391,7 @@ static void render_frame(const Inputs *in, int f, double *rgb, double *depth, do
             const Pix *q = fw.pix + p;
             if (depth2) depth2[po + p] = q->tri >= 0 ? q->d2 : INFINITY;
             if (frag_count) frag_count[po + p] = q->count;
+            if (obj_id) obj_id[po + p] = q->tri >= 0 ? q->obj : -1;
             if (q->tri < 0) {
                 for (int c = 0; c < 3; c++) {
                     rgb[3 * po + c * HW + p] = 0;
@@ -455,16 +456,18 @@ static void set_threads(int n_threads) {
 
 /* Render all frames.  Outputs use the planar layout: rgb and normal planes of frame f
  * at 3*pixel_offset[f] + c*H*W, depth/seg/tri_id/depth2/frag_count at
- * pixel_offset[f].  tri_id, depth2 and frag_count may be NULL.  Returns 0 on success. */
+ * pixel_offset[f].  obj_id receives the (global) object index of each pixel's nearest
+ * fragment, -1 for background.  tri_id, depth2, frag_count and obj_id may be NULL.
+ * Returns 0 on success. */
 int oracle_render(INPUT_ARGS, double *rgb, double *depth, double *normal, int32_t *seg, int32_t *tri_id,
-                  double *depth2, int32_t *frag_count, int32_t n_threads) {
+                  double *depth2, int32_t *frag_count, int32_t *obj_id, int32_t n_threads) {
     FILL_INPUTS(in);
     int err = 0;
     set_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
     for (int f = 0; f < n_frames; f++) {
         int e = 0;
-        render_frame(&in, f, rgb, depth, normal, seg, tri_id, depth2, frag_count, &e);
+        render_frame(&in, f, rgb, depth, normal, seg, tri_id, depth2, frag_count, obj_id, &e);
         err |= e;
     }
     return err;

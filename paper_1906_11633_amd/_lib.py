@@ -64,11 +64,24 @@ class Cameras(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("albedo", P), ("roughness", P), ("specular", P), ("light_vec", P),
-                ("light_intensity", P), ("exposure", P)]
+                ("light_intensity", P), ("exposure", P), ("post", P), ("grain", P), ("grain_w", C.c_int32),
+                ("grain_h", C.c_int32)]
 
 
 class Outputs(C.Structure):
-    _fields_ = [("rgb", P), ("depth", P), ("normal", P), ("seg", P), ("tri_id", P), ("vis", P), ("stats", P)]
+    _fields_ = [("rgb", P), ("depth", P), ("normal", P), ("seg", P), ("tri_id", P), ("vis", P), ("stats", P),
+                ("alpha", P), ("rgb8", P), ("track", P)]
+
+
+class Track(C.Structure):
+    """orrb_track: one tracker record per (frame, object of the frame's scene)."""
+    _fields_ = [("count", C.c_int32), ("i_min", C.c_int32), ("j_min", C.c_int32), ("i_max", C.c_int32),
+                ("j_max", C.c_int32), ("x", C.c_float), ("y", C.c_float), ("w", C.c_float), ("sum_i", C.c_uint64),
+                ("sum_j", C.c_uint64)]
+
+
+TRACK_BYTES = 48
+POST_WORDS = 12  # ORRB_POST_WORDS
 
 
 class Grads(C.Structure):
@@ -78,7 +91,8 @@ class Grads(C.Structure):
 
 class KernelTimes(C.Structure):
     _fields_ = [("vertex_ms", C.c_double), ("raster_ms", C.c_double), ("frame_ms", C.c_double),
-                ("vertex_launches", C.c_int64), ("raster_launches", C.c_int64), ("frame_launches", C.c_int64)]
+                ("vertex_launches", C.c_int64), ("raster_launches", C.c_int64), ("frame_launches", C.c_int64),
+                ("post_ms", C.c_double), ("post_launches", C.c_int64)]
 
 
 # name -> (restype, argtypes)

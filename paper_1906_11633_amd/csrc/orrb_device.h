@@ -24,7 +24,7 @@ struct FrameInfo {
     int32_t obj_begin, n_obj;   // the scene's objects (global indices)
     int32_t oi_base;            // first (frame, object) instance
     int32_t light_begin, n_lights;
-    int32_t pad0;
+    int32_t track_base;         // first tracker record (frame, object) of the frame
 };
 
 // Per object, built on the host from the layout and the mesh pool.
@@ -64,6 +64,13 @@ struct RenderArgs {
     float *out_rgb, *out_depth, *out_normal;
     int32_t *out_seg, *out_tri;
     unsigned long long *out_vis;
+    float *out_alpha;
+    uint8_t *out_rgb8;
+    orrb_track *out_track;
+    // post-processing of rgb8
+    const float *post;   // [F, ORRB_POST_WORDS] or null
+    const float *grain;  // [3, grain_h, grain_w] or null
+    int32_t grain_w, grain_h;
     // workspace
     int4 *vtx_pos;     // per vertex instance: X, Y (1/256 px), bits of fp32 1/w, valid flag
     float4 *obj_rot;   // per (frame, object): rows of the fp32 view rotation (x, y, z, 0)
@@ -115,6 +122,7 @@ void context_set_profiling(orrb_context *ctx, bool on);
 hipError_t launch_vertex(const RenderArgs &a, hipStream_t stream);
 hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu);
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu);
+hipError_t launch_post(const RenderArgs &a, hipStream_t stream, int n_frames, int64_t max_frame_pixels);
 hipError_t read_wait_timeouts(unsigned int *out);  // frame-kernel waits that hit their bound
 bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height);
 size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap);

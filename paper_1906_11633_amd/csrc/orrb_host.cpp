@@ -102,9 +102,9 @@ struct ScopedDevice {
 struct KernelTimer {
     bool enabled = false;
     std::vector<hipEvent_t> pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];  // 0 vertex, 1 raster, 2 frame
-    double total_ms[3] = {0, 0, 0};
-    int64_t count[3] = {0, 0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[4];  // 0 vertex, 1 raster, 2 frame, 3 post
+    double total_ms[4] = {0, 0, 0, 0};
+    int64_t count[4] = {0, 0, 0, 0};
     hipEvent_t get() {
         hipEvent_t e = nullptr;
         if (!pool.empty()) {
@@ -116,7 +116,7 @@ struct KernelTimer {
         return e;
     }
     hipError_t drain() {
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             for (auto &pr : pending[k]) {
                 hipError_t e = hipEventSynchronize(pr.second);
                 if (e != hipSuccess) return e;
@@ -155,6 +155,7 @@ struct orrb_layout {
     orrb_context *ctx = nullptr;
     int64_t n_scenes = 0, n_objects = 0, n_lights = 0, n_frames = 0;
     int64_t total_pixels = 0, vertex_instances = 0, triangle_instances = 0;
+    int64_t max_frame_pixels = 0;
     // tiled-path sizes with the current tuning, and with every frame on the tiled path
     int64_t tiled_vertex_instances = 0, tiled_object_instances = 0;
     int64_t all_vertex_instances = 0, all_object_instances = 0;
@@ -562,10 +563,11 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
         fi.oi_base = 0;
         fi.light_begin = d->scene_light_begin[s];
         fi.n_lights = d->scene_light_begin[s + 1] - d->scene_light_begin[s];
-        fi.pad0 = 0;
+        fi.track_base = (int32_t)oi;
         L->fits[f] = frame_fits((int)std::min<int64_t>(L->scene_verts[s], 0x7fffffff), fi.n_obj,
                                 (int)std::min<int64_t>(L->scene_tris[s], 0x7fffffff), fi.width, fi.height);
         pix += (int64_t)fi.width * fi.height;
+        L->max_frame_pixels = std::max<int64_t>(L->max_frame_pixels, (int64_t)fi.width * fi.height);
         vi += L->scene_verts[s];
         ti += L->scene_tris[s];
         oi += fi.n_obj;
@@ -698,6 +700,16 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     a.out_tri = out->tri_id;
     a.out_vis = (unsigned long long *)out->vis;
     a.stats = out->stats;
+    a.out_alpha = out->alpha;
+    a.out_rgb8 = out->rgb8;
+    a.out_track = out->track;
+    a.post = par->post;
+    a.grain = par->grain;
+    a.grain_w = par->grain_w;
+    a.grain_h = par->grain_h;
+    if (out->rgb8 && !out->rgb) return fail(ORRB_ERR_INVALID_ARGUMENT, "rgb8 needs the rgb destination");
+    if (out->rgb8 && par->grain && (par->grain_w < 1 || par->grain_h < 1))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "grain texture size %d x %d", par->grain_w, par->grain_h);
     char *ws = (char *)workspace;
     a.vtx_pos = (int4 *)(ws + w.vtx_pos);
     a.obj_rot = (float4 *)(ws + w.obj_rot);
@@ -707,16 +719,21 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     hipStream_t st = (hipStream_t)stream;
     KernelTimer &T = ctx->timer;
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
         if (k < 2 && a.n_titems == 0) continue;  // no frame on the tiled path
         if (k == 2 && a.n_fitems == 0) continue;
+        if (k == 3 && !a.out_rgb8) continue;     // no post-processed 8-bit output
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (T.enabled && timing) {
             e0 = T.get();
             e1 = T.get();
             if (e0) e = hipEventRecord(e0, st);
         }
-        if (e == hipSuccess) e = k == 0 ? launch_vertex(a, st) : k == 1 ? launch_raster(a, st, ctx->n_cu) : launch_frame(a, st, ctx->n_cu);
+        if (e == hipSuccess)
+            e = k == 0   ? launch_vertex(a, st)
+                : k == 1 ? launch_raster(a, st, ctx->n_cu)
+                : k == 2 ? launch_frame(a, st, ctx->n_cu)
+                         : launch_post(a, st, (int)L->n_frames, L->max_frame_pixels);
         if (T.enabled && timing && e0 && e1 && e == hipSuccess) {
             e = hipEventRecord(e1, st);
             T.pending[k].push_back({e0, e1});
@@ -808,7 +825,7 @@ orrb_status orrb_profile_enable(orrb_context *ctx, int enable) {
     ScopedDevice sd(ctx->device);
     HIP_TRY(ctx->timer.drain());
     ctx->timer.enabled = enable != 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         ctx->timer.total_ms[k] = 0;
         ctx->timer.count[k] = 0;
     }
@@ -836,6 +853,8 @@ orrb_status orrb_profile_read(orrb_context *ctx, orrb_kernel_times *out) {
     out->vertex_launches = ctx->timer.count[0];
     out->raster_launches = ctx->timer.count[1];
     out->frame_launches = ctx->timer.count[2];
+    out->post_ms = ctx->timer.total_ms[3];
+    out->post_launches = ctx->timer.count[3];
     return ORRB_OK;
 }
 

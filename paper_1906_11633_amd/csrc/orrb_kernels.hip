@@ -52,19 +52,21 @@ __global__ __launch_bounds__(kBlock) void k_vertex(RenderArgs a) {
     const FrameInfo fi = a.frames[f];
     const int o = fi.obj_begin + it.y;
     const int oi = fi.oi_base + it.y;
+    if (threadIdx.x < 12) M[threadIdx.x] = compose_entry(a.view + 12 * (int64_t)f, a.pose + 12 * (int64_t)o, threadIdx.x);
+    __syncthreads();
+    const float *K = a.intr + 4 * (int64_t)f;
+    const double fx = K[0], fy = K[1], cx = K[2], cy = K[3], nearp = a.near_plane[f];
+    if (a.out_track && threadIdx.x == 0)  // hidden objects too: their origin is still reported
+        track_init(a.out_track + fi.track_base + it.y, M[3], M[7], M[11], fx, fy, cx, cy);
     if (!a.visible[o]) {
         if (threadIdx.x == 0) a.obj_bbox[oi] = make_int4(1, 1, 0, 0);
         return;
     }
     const ObjInfo ob = a.objs[o];
-    if (threadIdx.x < 12) M[threadIdx.x] = compose_entry(a.view + 12 * (int64_t)f, a.pose + 12 * (int64_t)o, threadIdx.x);
-    __syncthreads();
     if (threadIdx.x < 3) {
         const int r = threadIdx.x;
         a.obj_rot[3 * (int64_t)oi + r] = make_float4((float)M[4 * r + 0], (float)M[4 * r + 1], (float)M[4 * r + 2], 0.f);
     }
-    const float *K = a.intr + 4 * (int64_t)f;
-    const double fx = K[0], fy = K[1], cx = K[2], cy = K[3], nearp = a.near_plane[f];
     double Mr[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) Mr[k] = M[k];
@@ -385,6 +387,36 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
         }
         store_pixel(a, po, HW, pix, o, z, segv, triv, key);
     }
+
+    // ---- tracker: every lane of a wave takes part (the trip count is uniform) ----
+    if (a.out_track) {
+        for (int p0 = 0; p0 < tw * th; p0 += kBlock) {
+            const int p = p0 + tid;
+            int rec = -1, i = 0, j = 0;
+            if (p < tw * th) {
+                const int lj = (int)(((float)p + 0.5f) * inv_tw), li = p - lj * tw;
+                const unsigned long long key = L.vis[lj * TW + li];
+                if (key != kEmptyKey) {
+                    const int tri = (int)(unsigned)(key & 0xffffffffu);
+                    int local;
+                    if (lds_objs) {
+                        local = L.ol_obj[find_slot(L.ol_tbase, n_ol, tri)] - fi.obj_begin;
+                    } else {
+                        int lo = 0, hi = fi.n_obj;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (a.objs[fi.obj_begin + mid].scene_tbase <= tri) lo = mid; else hi = mid;
+                        }
+                        local = lo;
+                    }
+                    rec = fi.track_base + local;
+                    i = tx0 + li;
+                    j = ty0 + lj;
+                }
+            }
+            track_wave(a.out_track, rec, i, j);
+        }
+    }
 }
 
 // Work-item index of workgroup `bid` among `n`, grouping consecutive items on the same
@@ -654,6 +686,7 @@ ORRB_INLINE void store4i(int *p, const int *v, bool vec, int n) {
 
 // Background (no fragment) for four adjacent pixels: rgb, depth, normal 0, seg and
 // tri_id -1, vis the empty key.
+template <bool AUX>
 ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, int64_t pix, bool vec, int n) {
     // materialized at each use: hoisted out of the tile loops these constants get
     // spilled, and their reloads would wait for every earlier store of the wave
@@ -681,6 +714,7 @@ ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, 
         for (int q = 0; q < 4; ++q)
             if (q < n) a.out_vis[po + pix + q] = kEmptyKey;
     }
+    if (AUX && a.out_alpha) store4f(a.out_alpha + po + pix, zf, vec, n);
 }
 
 // ---- synchronization of the persistent frame workgroup ----
@@ -867,6 +901,7 @@ ORRB_INLINE void frame_warm(const RenderArgs &a, int item, int lane) {
 }
 
 // Store wave: write staged tile s (every output plane) and free the slot.
+template <bool AUX>
 ORRB_INLINE void stage_write(const RenderArgs &a, FrameLds &S, int s, int lj, int li0, int lane) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     const StageInfo in = S.stage_info[s];
@@ -919,6 +954,12 @@ ORRB_INLINE void stage_write(const RenderArgs &a, FrameLds &S, int s, int lj, in
         for (int q = 0; q < 4; ++q)
             if (q < n) a.out_vis[po + pix + q] = key[q];
     }
+    if (AUX && a.out_alpha) {
+        float al[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) al[q] = key[q] == kEmptyKey ? 0.f : 1.f;
+        store4f(a.out_alpha + po + pix, al, vec, n);
+    }
 }
 
 // Pace a store wave: at most kFPace store instructions in flight, so the CU's memory
@@ -928,6 +969,7 @@ ORRB_INLINE void store_pace() { asm volatile("s_waitcnt vmcnt(%0)" ::"n"(kFPace)
 // Write the background of published tiles until every frame is published and taken.
 // Store waves run this from the start; compute waves join after their last frame,
 // starting at the oldest frame that may still have tiles.
+template <bool AUX>
 ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj, int li0, int lane) {
     const bool store_wave = wave >= kFCW;
     // a wave kept for staged tiles answers them without delay (no background tiles)
@@ -964,7 +1006,7 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
         action = __builtin_amdgcn_readlane(action, 0);
         if (!action) break;
         if (action == 1) {
-            stage_write(a, S, __builtin_amdgcn_readlane(st, 0), lj, li0, lane);
+            stage_write<AUX>(a, S, __builtin_amdgcn_readlane(st, 0), lj, li0, lane);
             if (store_wave && !staged_only) store_pace();
             continue;
         }
@@ -989,11 +1031,14 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
         const int j = y0 + lj, i0 = x0 + li0;
         const int n_in = j <= y1 ? max(0, min(4, x1 - i0 + 1)) : 0;
         if (n_in > 0)
-            store_background4(a, b.po, (int64_t)b.W * b.H, (int64_t)j * b.W + i0, b.vec && n_in == 4, n_in);
+            store_background4<AUX>(a, b.po, (int64_t)b.W * b.H, (int64_t)j * b.W + i0, b.vec && n_in == 4, n_in);
         if (store_wave) store_pace();
     }
 }
 
+// AUX: the transparency channel and the Tracker records are written (a separate
+// instantiation, so the plain four-channel kernel carries none of that code).
+template <bool AUX>
 __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     __shared__ FrameLds S;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -1047,6 +1092,13 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     const int n_verts = n_obj > 0 ? a.objs[fi.obj_begin + n_obj - 1].scene_vbase + a.objs[fi.obj_begin + n_obj - 1].n_verts : 0;
     if (frame_barrier(a, S, gen)) break;
     const int n_tris = n_obj > 0 ? S.o_tbase[n_obj - 1] + S.o_nt[n_obj - 1] : 0;
+    if (AUX && a.out_track && tid < n_obj) {
+        const float *K = a.intr + 4 * (int64_t)f;
+        track_init(a.out_track + fi.track_base + tid, S.u.M[tid][3], S.u.M[tid][7], S.u.M[tid][11], K[0], K[1], K[2],
+                   K[3]);
+        // the record must be in memory before any wave adds to it (after the barriers)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
     for (int b = tid; b * kFHint < n_tris; b += kFCT) S.tri_hint[b] = object_hint(S.o_tbase, n_obj, b);
     for (int b = tid; b * kFHint < n_verts; b += kFCT) S.vtx_hint[b] = object_hint(S.o_vbase, n_obj, b);
     if (frame_barrier(a, S, gen)) break;
@@ -1296,6 +1348,19 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        if (AUX && a.out_track) {  // tracker: the object slot of each covered pixel's key
+            for (int c0 = 0; c0 < n_cov; c0 += kWave) {
+                const int c = c0 + lane;
+                int rec = -1, pi = 0, pj = 0;
+                if (c < n_cov) {
+                    const int p = list[c];
+                    rec = fi.track_base + (int)((vis[p] >> 16) & 0xffu);
+                    pi = x0 + (int)((unsigned)p % kFTileW);
+                    pj = y0 + (int)((unsigned)p / kFTileW);
+                }
+                track_wave(a.out_track, rec, pi, pj);
+            }
+        }
 
         // shade the covered pixels, lane-compacted (lane takes list[lane + 64 r]), in
         // passes of (up to) two per lane and put them, over the tile's background, into a
@@ -1346,7 +1411,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     if (wave == 0 && lane == 0) __hip_atomic_store(&S.all_published, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     // store waves from the start, compute waves after their last frame
-    frame_drain(a, S, wave, lane / (kFTileW / 4), (lane % (kFTileW / 4)) * 4, lane);
+    frame_drain<AUX>(a, S, wave, lane / (kFTileW / 4), (lane % (kFTileW / 4)) * 4, lane);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1411,7 +1476,10 @@ hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu) {
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu) {
     if (a.n_fitems <= 0) return hipSuccess;
     const int grid = a.n_fitems < n_cu ? a.n_fitems : n_cu;
-    hipLaunchKernelGGL(k_frame, dim3(grid), dim3(kFT), 0, stream, a);
+    if (a.out_alpha || a.out_track)
+        hipLaunchKernelGGL(k_frame<true>, dim3(grid), dim3(kFT), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_frame<false>, dim3(grid), dim3(kFT), 0, stream, a);
     return hipGetLastError();
 }
 

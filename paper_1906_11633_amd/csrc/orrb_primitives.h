@@ -315,6 +315,77 @@ ORRB_INLINE void store_pixel(const RenderArgs &a, int64_t po, int64_t HW, int64_
     if (a.out_seg) a.out_seg[po + pix] = seg;
     if (a.out_tri) a.out_tri[po + pix] = tri;
     if (a.out_vis) a.out_vis[po + pix] = key;
+    if (a.out_alpha) a.out_alpha[po + pix] = key != kEmptyKey ? 1.0f : 0.0f;
+}
+
+// ------------------------------------------------------------------------------------
+// tracker records (Sec. 4.3.2 Tracker)
+// ------------------------------------------------------------------------------------
+
+// Empty record of an object whose composed matrix M = V o W (FP64, row-major 3x4) puts
+// its origin at eye coordinates (M[3], M[7], M[11]); the origin projected with the
+// frame's pinhole camera, NaN when it is not in front of the camera.
+ORRB_INLINE void track_init(orrb_track *t, double e0, double e1, double e2, double fx, double fy, double cx,
+                            double cy) {
+    const double w = -e2;
+    float x = __builtin_nanf(""), y = __builtin_nanf("");
+    if (w > 0.0) {
+        x = (float)fma(fx, e0 / w, cx);
+        y = (float)fma(-fy, e1 / w, cy);
+    }
+    orrb_track r;
+    r.count = 0;
+    r.i_min = r.j_min = 0x7fffffff;
+    r.i_max = r.j_max = -1;
+    r.x = x;
+    r.y = y;
+    r.w = (float)w;
+    r.sum_i = r.sum_j = 0;
+    *t = r;
+}
+
+ORRB_INLINE int wave_min(int v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+ORRB_INLINE int wave_max(int v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+ORRB_INLINE unsigned wave_sum(unsigned v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += (unsigned)__shfl_xor((int)v, o);
+    return v;
+}
+
+// Add the wave's pixels to their tracker records: lane L holds pixel (i, j) of record
+// `rec` (-1: none).  Must be called with every lane of the wave active.  One group of
+// global atomics per distinct record in the wave; integer min / max / sums, so the
+// result does not depend on the order of waves or tiles.
+ORRB_INLINE void track_wave(orrb_track *base, int rec, int i, int j) {
+    unsigned long long pend = __ballot(rec >= 0);
+    while (pend) {
+        const int first = __builtin_ctzll(pend);
+        const int r0 = __builtin_amdgcn_readlane(rec, first);
+        const bool mine = rec == r0;
+        const unsigned long long m = __ballot(mine);
+        const int imin = wave_min(mine ? i : 0x7fffffff), jmin = wave_min(mine ? j : 0x7fffffff);
+        const int imax = wave_max(mine ? i : -1), jmax = wave_max(mine ? j : -1);
+        const unsigned si = wave_sum(mine ? (unsigned)i : 0u), sj = wave_sum(mine ? (unsigned)j : 0u);
+        if (lane_id() == first) {
+            orrb_track *t = base + r0;
+            atomicAdd(&t->count, (int)__popcll(m));
+            atomicMin(&t->i_min, imin);
+            atomicMin(&t->j_min, jmin);
+            atomicMax(&t->i_max, imax);
+            atomicMax(&t->j_max, jmax);
+            atomicAdd((unsigned long long *)&t->sum_i, (unsigned long long)si);
+            atomicAdd((unsigned long long *)&t->sum_j, (unsigned long long)sj);
+        }
+        pend &= ~m;
+    }
 }
 
 ORRB_INLINE CamF frame_camera(const RenderArgs &a, int f) {

@@ -104,6 +104,10 @@ class Layout:
         L.check(ctx.lib.orrb_layout_create(ctx.handle, C.byref(desc), C.byref(h)))
         self.handle = h
         self.pixel_offset = np.concatenate([[0], np.cumsum(a["w"].astype(np.int64) * a["h"].astype(np.int64))])
+        # tracker records: one per (frame, object of the frame's scene), frames in order
+        per_frame = np.diff(a["sob"].astype(np.int64))[a["fs"]] if a["fs"].size else np.zeros(0, np.int64)
+        self.track_base = np.concatenate([[0], np.cumsum(per_frame)]).astype(np.int64)
+        self.n_track_records = int(self.track_base[-1])
 
     @property
     def info(self) -> L.LayoutInfo:
@@ -128,7 +132,8 @@ class Layout:
 
 
 def device_state(batch, device="cuda") -> Dict[str, torch.Tensor]:
-    """Per-batch state of a generator Batch as contiguous device tensors."""
+    """Per-batch state of a generator Batch as contiguous device tensors (plus the
+    post-processing parameters and grain texture when the batch carries them)."""
     src = dict(object_pose=batch.object_pose, object_seg=batch.object_seg, object_visible=batch.object_visible,
                albedo=batch.albedo, roughness=batch.roughness, specular=batch.specular, light_vec=batch.light_vec,
                light_intensity=batch.light_intensity, view=batch.view, intr=batch.intr, near=batch.near,
@@ -139,6 +144,12 @@ def device_state(batch, device="cuda") -> Dict[str, torch.Tensor]:
         t = torch.from_numpy(arr.astype({torch.float32: np.float32, torch.int32: np.int32,
                                          torch.uint8: np.uint8}[dt], copy=False))
         out[k] = t.to(device, non_blocking=False).contiguous()
+    post = getattr(batch, "post", None)
+    if post is not None:
+        out["post"] = torch.from_numpy(np.ascontiguousarray(post, np.float32)).to(device)
+    grain = getattr(batch, "grain", None)
+    if grain is not None:
+        out["grain"] = torch.from_numpy(np.ascontiguousarray(grain, np.float32)).to(device)
     return out
 
 
@@ -167,7 +178,8 @@ class Renderer:
         ws = torch.empty(max(int(inf.workspace_bytes_any), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
         return Job(lay, st, int(inf.total_pixels), ws)
 
-    def alloc_outputs(self, job: Job, tri_id=False, vis=False, stats=False) -> Dict[str, torch.Tensor]:
+    def alloc_outputs(self, job: Job, tri_id=False, vis=False, stats=False, alpha=False, rgb8=False,
+                      track=False) -> Dict[str, torch.Tensor]:
         P = job.total_pixels
         dev = f"cuda:{self.device}"
         out = dict(rgb=torch.empty(3 * P, dtype=torch.float32, device=dev),
@@ -180,12 +192,19 @@ class Renderer:
             out["vis"] = torch.empty(P, dtype=torch.int64, device=dev)
         if stats:
             out["stats"] = torch.zeros(L.STATS_WORDS, dtype=torch.int32, device=dev)
+        if alpha:
+            out["alpha"] = torch.empty(P, dtype=torch.float32, device=dev)
+        if rgb8:
+            out["rgb8"] = torch.empty(3 * P, dtype=torch.uint8, device=dev)
+        if track:
+            n = int(job.layout.n_track_records)
+            out["track"] = torch.empty(n * L.TRACK_BYTES, dtype=torch.uint8, device=dev)
         return out
 
     def render(self, job: Job, out: Optional[Dict[str, torch.Tensor]] = None, tri_id=False, vis=False,
-               stream=None, stats=False) -> Dict[str, torch.Tensor]:
+               stream=None, stats=False, alpha=False, rgb8=False, track=False) -> Dict[str, torch.Tensor]:
         if out is None:
-            out = self.alloc_outputs(job, tri_id, vis, stats)
+            out = self.alloc_outputs(job, tri_id, vis, stats, alpha, rgb8, track)
         render_batch(self.ctx, job.layout, job.state, out, job.workspace, stream)
         return out
 
@@ -193,13 +212,7 @@ class Renderer:
 def render_batch(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], out: Dict[str, torch.Tensor],
                  workspace: torch.Tensor, stream=None):
     """orrb_render_batch on `stream` (default: torch's current stream)."""
-    s = state
-    sc = L.Scenes(_ptr(s["object_pose"]), _ptr(s["object_seg"]), _ptr(s["object_visible"]))
-    cam = L.Cameras(_ptr(s["view"]), _ptr(s["intr"]), _ptr(s["near"]))
-    par = L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
-                   _ptr(s["light_intensity"]), _ptr(s["exposure"]))
-    o = L.Outputs(_ptr(out.get("rgb")), _ptr(out.get("depth")), _ptr(out.get("normal")), _ptr(out.get("seg")),
-                  _ptr(out.get("tri_id")), _ptr(out.get("vis")), _ptr(out.get("stats")))
+    sc, cam, par, o = _structs(state, out)
     st = stream if stream is not None else torch.cuda.current_stream(ctx.device)
     L.check(ctx.lib.orrb_render_batch(ctx.handle, layout.handle, C.byref(sc), C.byref(cam), C.byref(par), C.byref(o),
                                       _ptr(workspace), int(workspace.numel()), C.c_void_p(st.cuda_stream)))
@@ -216,15 +229,33 @@ def render_batch_noalloc(ctx: Context, layout: Layout, state: Dict[str, torch.Te
                                               C.byref(o), C.c_void_p(st.cuda_stream)))
 
 
+def _params(state) -> L.Params:
+    s = state
+    grain = s.get("grain")
+    gh, gw = (int(grain.shape[-2]), int(grain.shape[-1])) if grain is not None else (0, 0)
+    return L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
+                    _ptr(s["light_intensity"]), _ptr(s["exposure"]), _ptr(s.get("post")), _ptr(grain), gw, gh)
+
+
 def _structs(state, out):
     s = state
     sc = L.Scenes(_ptr(s["object_pose"]), _ptr(s["object_seg"]), _ptr(s["object_visible"]))
     cam = L.Cameras(_ptr(s["view"]), _ptr(s["intr"]), _ptr(s["near"]))
-    par = L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
-                   _ptr(s["light_intensity"]), _ptr(s["exposure"]))
     o = L.Outputs(_ptr(out.get("rgb")), _ptr(out.get("depth")), _ptr(out.get("normal")), _ptr(out.get("seg")),
-                  _ptr(out.get("tri_id")), _ptr(out.get("vis")), _ptr(out.get("stats")))
-    return sc, cam, par, o
+                  _ptr(out.get("tri_id")), _ptr(out.get("vis")), _ptr(out.get("stats")), _ptr(out.get("alpha")),
+                  _ptr(out.get("rgb8")), _ptr(out.get("track")))
+    return sc, cam, _params(state), o
+
+
+def read_track(track: torch.Tensor) -> Dict[str, np.ndarray]:
+    """Tracker records (orrb_track, 48 bytes each) as numpy arrays: count, bbox
+    [n, 4] (i_min, j_min, i_max, j_max), sum_i, sum_j, origin [n, 3] (x, y, w)."""
+    raw = track.detach().to("cpu").numpy().view(np.uint8)
+    dt = np.dtype([("count", "<i4"), ("bbox", "<i4", 4), ("origin", "<f4", 3), ("sum_i", "<u8"), ("sum_j", "<u8")])
+    assert dt.itemsize == L.TRACK_BYTES
+    r = raw.view(dt)
+    return dict(count=r["count"].astype(np.int64), bbox=r["bbox"].astype(np.int64), sum_i=r["sum_i"].astype(np.int64),
+                sum_j=r["sum_j"].astype(np.int64), origin=r["origin"].astype(np.float64))
 
 
 def autotune(ctx: Context, layout: Layout, state, out, workspace, stream=None, cache_path=None):
@@ -289,8 +320,7 @@ def shade_backward(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor],
              exposure=torch.empty(F, dtype=torch.float32, device=dev))
     sc = L.Scenes(_ptr(s["object_pose"]), _ptr(s["object_seg"]), _ptr(s["object_visible"]))
     cam = L.Cameras(_ptr(s["view"]), _ptr(s["intr"]), _ptr(s["near"]))
-    par = L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
-                   _ptr(s["light_intensity"]), _ptr(s["exposure"]))
+    par = _params(s)
     gr = L.Grads(_ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]), _ptr(g["light_vec"]),
                  _ptr(g["light_intensity"]), _ptr(g["exposure"]))
     grad_rgb = grad_rgb.contiguous()

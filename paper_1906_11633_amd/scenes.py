@@ -286,6 +286,10 @@ class Batch:
     exposure: np.ndarray            # f32 [F]
     name: str = ""
     extra: dict = field(default_factory=dict)
+    # post-processing of the 8-bit output (optional): per-frame parameters and the
+    # grain noise texture (see with_postprocessing)
+    post: Optional[np.ndarray] = None   # f32 [F, 12]
+    grain: Optional[np.ndarray] = None  # f32 [3, GH, GW] in [0, 1)
 
     @property
     def n_scenes(self) -> int:
@@ -353,7 +357,8 @@ class Batch:
             roughness=self.roughness[objs], specular=self.specular[objs],
             light_vec=self.light_vec[lights], light_intensity=self.light_intensity[lights],
             view=self.view[frames], intr=self.intr[frames], near=self.near[frames],
-            exposure=self.exposure[frames], name=self.name + "[sub]")
+            exposure=self.exposure[frames], name=self.name + "[sub]",
+            post=None if self.post is None else self.post[frames], grain=self.grain)
 
     def replace(self, **kw) -> "Batch":
         d = dict(self.__dict__)
@@ -574,6 +579,49 @@ def config2(seed: int = 2, n_scenes: int = 256, res: int = 200, n_cams: int = 3,
     for s in ids:
         _hand_scene(b, np.random.default_rng([seed, int(s)]), res, n_cams)
     return b.build(f"config2[{n_scenes}x{n_cams}@{res}]")
+
+
+# ----------------------------------------------------------------------------------
+# post-processing randomizer (colour grading and grain of the 8-bit output)
+# ----------------------------------------------------------------------------------
+
+POST_WORDS = 12
+GRAIN_SIZE = (64, 64)  # grain noise texture, texels
+
+
+def postprocess_params(seed: int, n_frames: int, frame_scene=None, grain_size=GRAIN_SIZE):
+    """Per-frame colour-grading and grain parameters and one grain noise texture
+    (the PostprocessingRandomizer's draws): temperature and tint U[-0.3, 0.3], hue
+    U[-pi/12, pi/12], saturation U[0.7, 1.3], contrast U[0.8, 1.2], grain intensity
+    U[0, 0.06], coloration U[0, 1], size U{1, 2, 3} px, texel offsets uniform.  A frame's
+    draws come from default_rng([seed, 0x9057, scene, k]) with k its index among its
+    scene's frames, so they do not depend on the batch composition."""
+    fs = np.zeros(n_frames, np.int64) if frame_scene is None else np.asarray(frame_scene, np.int64)
+    GH, GW = grain_size
+    post = np.zeros((n_frames, POST_WORDS), np.float32)
+    seen = {}
+    for f in range(n_frames):
+        s = int(fs[f])
+        k = seen.get(s, 0)
+        seen[s] = k + 1
+        rng = np.random.default_rng([seed, 0x9057, s, k])
+        post[f, 0:2] = rng.uniform(-0.3, 0.3, 2)
+        post[f, 2] = rng.uniform(-math.pi / 12, math.pi / 12)
+        post[f, 3] = rng.uniform(0.7, 1.3)
+        post[f, 4] = rng.uniform(0.8, 1.2)
+        post[f, 5] = rng.uniform(0.0, 0.06)
+        post[f, 6] = rng.uniform(0.0, 1.0)
+        post[f, 7] = rng.integers(1, 4)
+        post[f, 8] = rng.integers(0, GW)
+        post[f, 9] = rng.integers(0, GH)
+    grain = np.random.default_rng([seed, 0x6A41]).uniform(0.0, 1.0, (3, GH, GW)).astype(np.float32)
+    return post, grain
+
+
+def with_postprocessing(batch: Batch, seed: int = 0) -> Batch:
+    """The batch with randomized post-processing parameters and grain texture."""
+    post, grain = postprocess_params(seed, batch.n_frames, batch.frame_scene)
+    return batch.replace(post=post, grain=grain)
 
 
 # ----------------------------------------------------------------------------------

@@ -43,7 +43,8 @@ def test_struct_sizes_match_header():
     import tempfile
     from paper_1906_11633_amd import _lib as L
     structs = {"orrb_layout_desc": L.LayoutDesc, "orrb_tuning": L.Tuning, "orrb_layout_info": L.LayoutInfo,
-               "orrb_scenes": L.Scenes, "orrb_cameras": L.Cameras, "orrb_params": L.Params, "orrb_outputs": L.Outputs}
+               "orrb_scenes": L.Scenes, "orrb_cameras": L.Cameras, "orrb_params": L.Params, "orrb_outputs": L.Outputs,
+               "orrb_track": L.Track, "orrb_kernel_times": L.KernelTimes}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -103,6 +104,8 @@ def test_stat_words_match_header():
     text = open(HEADER).read()
     words = {m.group(1).lower(): int(m.group(2)) for m in re.finditer(r"#define ORRB_STAT_([A-Z_]+)\s+(\d+)", text)}
     assert int(re.search(r"#define ORRB_STATS_WORDS\s+(\d+)", text).group(1)) == L.STATS_WORDS
+    assert int(re.search(r"#define ORRB_POST_WORDS\s+(\d+)", text).group(1)) == L.POST_WORDS
+    assert C.sizeof(L.Track) == L.TRACK_BYTES
     header_order = [k for k, _ in sorted(words.items(), key=lambda kv: kv[1])]
     assert [v for _, v in sorted(words.items(), key=lambda kv: kv[1])] == list(range(len(words)))
     expect = {"wait_timeouts": "wait_timeouts", "bin_overflow_frames": "bin_overflow",
