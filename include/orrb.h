@@ -118,15 +118,22 @@ typedef struct {
 } orrb_layout_desc;
 
 /* Launch choices.  They change speed only: the output bits are the same for every
- * valid tuning.  Frames whose scene fits in LDS (<= 6976 vertices, <= 48 objects,
- * < 65536 triangles, <= 256x256 pixels) can be rendered whole by one workgroup
- * ("frame path"); the others go through the tiled path (a vertex kernel, then one
+ * valid tuning.  The frame kernel (one persistent launch, a workgroup renders whole
+ * frames) takes frames of at most 256x256 pixels whose scene fits in LDS (<= 6976
+ * vertices, <= 48 objects, < 65536 triangles) and, with path 2, also larger scenes
+ * (<= 65536 vertices, <= 127 objects, < 65536 triangles) whose snapped vertices, bins
+ * and survivors then live in workspace scratch; every triangle is set up once per
+ * frame either way.  Other frames go through the tiled path (a vertex kernel, then one
  * workgroup per screen tile). */
 typedef struct {
     int32_t tile_w, tile_h;  /* tiled path: tile size, each in {16, 32, 64} */
-    int32_t bin_cap;         /* tiled path: triangles staged in LDS per flush, in {256, 512, 1024} */
+    int32_t bin_cap;         /* tiled path: triangles staged in LDS per flush, in {256, 512, 1024};
+                                path 2: the frame kernel's global bins hold bin_cap / 128 entries
+                                per triangle of the largest scratch-held scene (more: a frame falls
+                                back to scanning every triangle per tile, same bits) */
     int32_t persistent;      /* tiled path: 1 = persistent grid pulling tiles from a device queue */
-    int32_t path;            /* 0 = frame path where the scene fits, 1 = tiled path for every frame */
+    int32_t path;            /* 0 = frame kernel where the scene fits in LDS, 1 = tiled path for
+                                every frame, 2 = frame kernel for every frame it can take */
 } orrb_tuning;
 
 typedef struct {
@@ -135,7 +142,7 @@ typedef struct {
     int64_t vertex_instances;   /* sum over frames of the frame's scene vertex count */
     int64_t triangle_instances; /* sum over frames of the frame's scene triangle count */
     int64_t tile_items;         /* tiled-path work items with the current tuning */
-    int64_t frame_path_frames;  /* frames rendered by the frame path with the current tuning */
+    int64_t frame_path_frames;  /* frames rendered by the frame kernel with the current tuning */
     size_t workspace_bytes;      /* workspace orrb_render_batch needs (current tuning) */
     size_t workspace_bytes_any;  /* workspace enough for every valid tuning */
     size_t grad_workspace_bytes; /* workspace orrb_shade_backward needs */

@@ -25,6 +25,8 @@ struct FrameInfo {
     int32_t oi_base;            // first (frame, object) instance
     int32_t light_begin, n_lights;
     int32_t track_base;         // first tracker record (frame, object) of the frame
+    int32_t mode;               // frame kernel: 0 scene data in LDS, 1 in the global frame scratch
+    int32_t pad0;
 };
 
 // Per object, built on the host from the layout and the mesh pool.
@@ -44,6 +46,7 @@ struct RenderArgs {
     const int32_t *fitems;  // frames rendered by k_frame
     const int32_t *light_type;
     int32_t n_vitems, n_titems, n_fitems;
+    int32_t f_grid;         // frame kernel grid: workgroup b renders fitems[b + k f_grid] (-1: none)
     int32_t tile_w, tile_h, bin_cap;
     int32_t persistent;
     // resident meshes
@@ -76,6 +79,13 @@ struct RenderArgs {
     float4 *obj_rot;   // per (frame, object): rows of the fp32 view rotation (x, y, z, 0)
     int4 *obj_bbox;    // per (frame, object): covered pixel-centre range i0, j0, i1, j1
     unsigned int *queue;  // persistent work counter
+    // frame kernel, frames whose scene data live in global scratch (mode 1): one slice
+    // of fscratch_stride bytes per workgroup holding fs_verts snapped vertices (X, Y,
+    // 1/w), fs_surv survivor entries and fs_bins 16-bit bin entries; null if none
+    char *fscratch;
+    int64_t fscratch_stride;
+    int64_t fs_verts;
+    int32_t fs_surv, fs_bins;
     unsigned int *stats;  // caller's ORRB_STATS_WORDS counters of the call, or null
 };
 
@@ -125,6 +135,7 @@ hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu);
 hipError_t launch_post(const RenderArgs &a, hipStream_t stream, int n_frames, int64_t max_frame_pixels);
 hipError_t read_wait_timeouts(unsigned int *out);  // frame-kernel waits that hit their bound
 bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height);
+bool frame_fits_global(int64_t n_verts, int n_obj, int64_t n_tris, int width, int height);
 size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap);
 // render call shared by orrb_render_batch and orrb_render_batch_noalloc (orrb_host.cpp)
 orrb_status render_impl(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,

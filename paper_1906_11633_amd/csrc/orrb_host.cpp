@@ -162,9 +162,13 @@ struct orrb_layout {
     std::vector<FrameInfo> frames;
     std::vector<ObjInfo> objs;
     std::vector<int64_t> scene_verts, scene_tris;
-    std::vector<uint8_t> fits;  // per frame: the scene fits the frame path
+    std::vector<uint8_t> fits;  // per frame: 1 scene fits the frame kernel's LDS, 2 its global scratch, 0 neither
+    // frames on the frame kernel with scene data in global scratch (tuning path 2)
+    int64_t gframes = 0, gf_verts = 0, gf_tris = 0;
     std::vector<int2> vitems, titems;
-    std::vector<int32_t> fitems;
+    std::vector<int32_t> fitems;  // frame-kernel schedule (see schedule_frames); -1 = no frame
+    int64_t f_frames = 0;          // frames on the frame kernel
+    int32_t f_grid = 0;            // its persistent grid
     std::vector<int32_t> light_type;
     Packed tab;  // frames, objs, vitems, titems, fitems, light_type
     size_t o_frames = 0, o_objs = 0, o_vitems = 0, o_titems = 0, o_fitems = 0, o_light_type = 0;
@@ -193,10 +197,32 @@ struct orrb_layout {
 static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct WsLayout {
-    size_t vtx_pos, obj_rot, obj_bbox, queue, total;
+    size_t vtx_pos, obj_rot, obj_bbox, queue, fscratch, total;
+    size_t fs_stride;
+    int64_t fs_verts, fs_surv, fs_bins;
 };
 
-static WsLayout ws_layout(int64_t vertex_instances, int64_t object_instances) {
+// Global scratch of the frame kernel for frames whose scene data do not fit in LDS:
+// one slice per workgroup (grid = min(frames, CUs)) with the largest such scene's
+// snapped vertices (12 B each), a survivor entry per triangle (4 B) and
+// bin_cap / 128 16-bit bin entries per triangle (at least 4096).
+struct FrameScratch {
+    int64_t grid = 0, verts = 0, surv = 0, bins = 0;
+    size_t stride = 0;
+};
+static FrameScratch frame_scratch(int64_t gframes, int64_t frame_kernel_frames, int64_t verts, int64_t tris, int bin_cap,
+                                  int n_cu) {
+    FrameScratch f;
+    if (gframes <= 0) return f;
+    f.grid = std::min<int64_t>(frame_kernel_frames, n_cu);  // the frame kernel's grid: any workgroup may take such a frame
+    f.verts = verts;
+    f.surv = tris;
+    f.bins = std::max<int64_t>(4096, (bin_cap / 128) * tris);
+    f.stride = al256(12 * (size_t)verts) + al256(4 * (size_t)f.surv) + al256(2 * (size_t)f.bins);
+    return f;
+}
+
+static WsLayout ws_layout(int64_t vertex_instances, int64_t object_instances, const FrameScratch &fs = FrameScratch()) {
     WsLayout w;
     size_t off = 0;
     w.vtx_pos = off;
@@ -207,11 +233,15 @@ static WsLayout ws_layout(int64_t vertex_instances, int64_t object_instances) {
     off = al256(off + sizeof(int4) * (size_t)object_instances);
     w.queue = off;
     off = al256(off + 64);
+    w.fscratch = off;
+    w.fs_stride = fs.stride;
+    w.fs_verts = fs.verts;
+    w.fs_surv = fs.surv;
+    w.fs_bins = fs.bins;
+    off += fs.stride * (size_t)fs.grid;
     w.total = off;
     return w;
 }
-
-static WsLayout ws_layout(const orrb_layout *L) { return ws_layout(L->tiled_vertex_instances, L->tiled_object_instances); }
 
 static bool valid_tuning(const orrb_tuning &t) {
     auto ok_dim = [](int d) { return d == 16 || d == 32 || d == 64; };
@@ -219,24 +249,104 @@ static bool valid_tuning(const orrb_tuning &t) {
     if (t.tile_w * t.tile_h > 4096) return false;
     if (t.bin_cap != 256 && t.bin_cap != 512 && t.bin_cap != 1024) return false;
     if (t.persistent != 0 && t.persistent != 1) return false;
-    if (t.path != 0 && t.path != 1) return false;
+    if (t.path < 0 || t.path > 2) return false;
     return raster_lds_bytes(t.tile_w, t.tile_h, t.bin_cap) <= 160 * 1024;
 }
 
-// Split frames between the frame path and the tiled path and build the work items.
+// Static schedule of the frame kernel's persistent grid (min(frames, CUs) workgroups):
+// frames go, heaviest first, to the workgroup with the least estimated work (longest
+// processing time first), so an uneven batch finishes nearly together.  Workgroup b
+// renders fitems[b], fitems[b + grid], ...; -1 fills the slots of workgroups with fewer
+// frames.  Estimated work: triangles (half again when the scene data live in global
+// scratch) plus a quarter per pixel.  A uniform batch keeps the plain frame order.
+static void schedule_frames(orrb_layout *L) {
+    const int64_t n = (int64_t)L->fitems.size();
+    L->f_frames = n;
+    L->f_grid = (int32_t)std::min<int64_t>(n, L->ctx ? L->ctx->n_cu : 256);
+    if (n == 0) return;
+    std::vector<double> cost(n);
+    bool uniform = true;
+    for (int64_t k = 0; k < n; ++k) {
+        const FrameInfo &fi = L->frames[L->fitems[k]];
+        cost[k] = (double)L->scene_tris[fi.scene] * (fi.mode ? 1.5 : 1.0) + 0.25 * (double)fi.width * fi.height;
+        uniform = uniform && cost[k] == cost[0];
+    }
+    if (uniform) return;
+    const int G = L->f_grid;
+    std::vector<int64_t> order(n);
+    for (int64_t k = 0; k < n; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+    std::vector<double> load(G, 0.0);
+    std::vector<std::vector<int32_t>> lists(G);
+    for (int64_t k : order) {
+        int b = 0;
+        for (int g = 1; g < G; ++g)
+            if (load[g] < load[b]) b = g;
+        load[b] += cost[k];
+        lists[b].push_back(L->fitems[k]);
+    }
+    size_t len = 0;
+    for (auto &l : lists) len = std::max(len, l.size());
+    std::vector<int32_t> slots((size_t)G * len, -1);
+    for (int g = 0; g < G; ++g)
+        for (size_t r = 0; r < lists[g].size(); ++r) slots[(size_t)g + r * G] = lists[g][r];
+    L->fitems.swap(slots);
+}
+
+static WsLayout ws_layout(const orrb_layout *L) {
+    const FrameScratch fs =
+        frame_scratch(L->gframes, L->f_frames, L->gf_verts, L->gf_tris, L->tuning.bin_cap,
+                      L->ctx ? L->ctx->n_cu : 256);
+    return ws_layout(L->tiled_vertex_instances, L->tiled_object_instances, fs);
+}
+
+// Workspace enough for every valid tuning: every frame on the tiled path, plus the
+// frame scratch of path 2 at the largest bin capacity.
+static size_t ws_bytes_any(const orrb_layout *L) {
+    int64_t g = 0, v = 0, t = 0, nf = 0;
+    for (int64_t f = 0; f < L->n_frames; ++f) {
+        nf += L->fits[f] != 0;
+        if (L->fits[f] == 2) {
+            ++g;
+            v = std::max<int64_t>(v, L->scene_verts[L->frames[f].scene]);
+            t = std::max<int64_t>(t, L->scene_tris[L->frames[f].scene]);
+        }
+    }
+    const FrameScratch fs = frame_scratch(g, nf, v, t, 1024, L->ctx ? L->ctx->n_cu : 256);
+    return ws_layout(L->all_vertex_instances, L->all_object_instances).total + fs.stride * (size_t)fs.grid + 256;
+}
+
+// Split frames between the frame kernel and the tiled path and build the work items.
+// Path 0: the frame kernel takes frames whose scene fits in LDS; path 1: every frame
+// on the tiled path; path 2: the frame kernel also takes larger scenes (up to 65,536
+// vertices, 127 objects, 65,535 triangles, 256 x 256 pixels) with their data in global
+// scratch, so an uneven batch of such frames is one launch.
 static void build_items(orrb_layout *L) {
     L->titems.clear();
     L->vitems.clear();
     L->fitems.clear();
     const int TW = L->tuning.tile_w, TH = L->tuning.tile_h;
     int64_t vi = 0, oi = 0;
+    L->gframes = L->gf_verts = L->gf_tris = 0;
     for (int64_t f = 0; f < L->n_frames; ++f) {
         FrameInfo &fi = L->frames[f];
         fi.tiles_x = (fi.width + TW - 1) / TW;
-        if (L->tuning.path == 0 && L->fits[f]) {
+        fi.mode = 0;
+        const int path = L->tuning.path;
+        if ((path == 0 || path == 2) && L->fits[f] == 1) {
             L->fitems.push_back((int32_t)f);
             fi.vbase = 0;
             fi.oi_base = 0;
+            continue;
+        }
+        if (path == 2 && L->fits[f] == 2) {
+            L->fitems.push_back((int32_t)f);
+            fi.vbase = 0;
+            fi.oi_base = 0;
+            fi.mode = 1;
+            L->gframes++;
+            L->gf_verts = std::max<int64_t>(L->gf_verts, L->scene_verts[fi.scene]);
+            L->gf_tris = std::max<int64_t>(L->gf_tris, L->scene_tris[fi.scene]);
             continue;
         }
         fi.vbase = vi;
@@ -249,6 +359,7 @@ static void build_items(orrb_layout *L) {
     }
     L->tiled_vertex_instances = vi;
     L->tiled_object_instances = oi;
+    schedule_frames(L);
 }
 
 // Tables of the shading adjoint (independent of the tuning).
@@ -565,7 +676,12 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
         fi.n_lights = d->scene_light_begin[s + 1] - d->scene_light_begin[s];
         fi.track_base = (int32_t)oi;
         L->fits[f] = frame_fits((int)std::min<int64_t>(L->scene_verts[s], 0x7fffffff), fi.n_obj,
-                                (int)std::min<int64_t>(L->scene_tris[s], 0x7fffffff), fi.width, fi.height);
+                                (int)std::min<int64_t>(L->scene_tris[s], 0x7fffffff), fi.width, fi.height)
+                         ? 1
+                     : frame_fits_global(L->scene_verts[s], fi.n_obj, L->scene_tris[s], fi.width, fi.height) ? 2
+                                                                                                              : 0;
+        fi.mode = 0;
+        fi.pad0 = 0;
         pix += (int64_t)fi.width * fi.height;
         L->max_frame_pixels = std::max<int64_t>(L->max_frame_pixels, (int64_t)fi.width * fi.height);
         vi += L->scene_verts[s];
@@ -634,9 +750,9 @@ orrb_status orrb_layout_info_get(const orrb_layout *L, orrb_layout_info *info) {
     info->vertex_instances = L->vertex_instances;
     info->triangle_instances = L->triangle_instances;
     info->tile_items = (int64_t)L->titems.size();
-    info->frame_path_frames = (int64_t)L->fitems.size();
+    info->frame_path_frames = L->f_frames;
     info->workspace_bytes = ws_layout(L).total;
-    info->workspace_bytes_any = ws_layout(L->all_vertex_instances, L->all_object_instances).total;
+    info->workspace_bytes_any = ws_bytes_any(L);
     info->grad_workspace_bytes = grad_workspace(L);
     info->table_bytes = L->tab.dev.bytes + L->gtab.dev.bytes;
     info->tuning = L->tuning;
@@ -687,6 +803,7 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     a.titems = L->tab.at<int2>(L->o_titems);
     a.fitems = L->tab.at<int32_t>(L->o_fitems);
     a.n_fitems = (int32_t)L->fitems.size();
+    a.f_grid = L->f_grid;
     a.n_vitems = (int32_t)L->vitems.size();
     a.n_titems = (int32_t)L->titems.size();
     a.tile_w = L->tuning.tile_w;
@@ -715,6 +832,13 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     a.obj_rot = (float4 *)(ws + w.obj_rot);
     a.obj_bbox = (int4 *)(ws + w.obj_bbox);
     a.queue = (unsigned int *)(ws + w.queue);
+    if (L->gframes > 0) {
+        a.fscratch = ws + w.fscratch;
+        a.fscratch_stride = (int64_t)w.fs_stride;
+        a.fs_verts = w.fs_verts;
+        a.fs_surv = (int32_t)w.fs_surv;
+        a.fs_bins = (int32_t)std::min<int64_t>(w.fs_bins, 0x7fffffff);
+    }
     ScopedDevice sd(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     KernelTimer &T = ctx->timer;

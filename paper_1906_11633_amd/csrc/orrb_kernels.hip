@@ -452,6 +452,8 @@ constexpr int kFT = 1024;           // threads of a frame workgroup
 constexpr int kFW = kFT / kWave;    // 16 waves
 constexpr int kFVMax = 6976;        // scene vertices held in LDS
 constexpr int kFOMax = 48;          // scene objects
+constexpr int kFGOMax = 127;        // scene objects of a frame whose data live in global scratch
+constexpr int kFGVMax = 65536;      // scene vertices of such a frame
 constexpr int kFTileW = 64;         // wave tile: 64 x 4 pixels, so that a wave's store
 constexpr int kFTileH = 4;          // instruction writes 256-byte row segments
 constexpr int kFTilesMax = 256;     // frames up to 256 x 256 (4 x 64 tiles)
@@ -485,10 +487,21 @@ struct StageInfo {
 };
 
 struct FrameLds {
-    int X[kFVMax], Y[kFVMax];
-    float iw[kFVMax];
     union {
-        double M[kFOMax][12];                         // vertex phase
+        struct {  // scenes held in LDS: the snapped vertices
+            int X[kFVMax], Y[kFVMax];
+            float iw[kFVMax];
+        } v;
+        struct {  // larger scenes (vertices, bins, survivors in global scratch): object tables
+            int o_tbase[kFGOMax], o_vbase[kFGOMax], o_mtb[kFGOMax], o_mvb[kFGOMax], o_nt[kFGOMax], o_seg[kFGOMax],
+                o_vis[kFGOMax];
+            float o_R[kFGOMax][9];
+            Material o_mat[kFGOMax];
+            unsigned char vtx_hint[kFGVMax / kFHint];
+        } g;
+    } m;
+    union {
+        double M[kFGOMax][12];                        // vertex phase
         unsigned int surv[kFSurvMax];                 // set-up -> scatter: (tri << 16) | tile range
         unsigned long long vis[kFCW][kFTileW * kFTileH];  // tile phase
     } u;
@@ -528,6 +541,74 @@ bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height) {
     return n_verts <= kFVMax && n_obj <= kFOMax && n_tris < 65536 && width <= 4 * kFTileW && height <= 64 * kFTileH;
 }
 
+bool frame_fits_global(int64_t n_verts, int n_obj, int64_t n_tris, int width, int height) {
+    return n_verts <= kFGVMax && n_obj <= kFGOMax && n_tris < 65536 && width <= 4 * kFTileW && height <= 64 * kFTileH;
+}
+
+// Where one frame's scene data live.  G = false: the scene fits in LDS (vertices,
+// bins, survivors and object tables all in FrameLds).  G = true: a larger scene; its
+// snapped vertices, tile bins and survivor list are in the workgroup's slice of the
+// global frame scratch (a few hundred KB, mostly served by the L2) and its object
+// tables in the LDS the vertices would otherwise take.  Every triangle is still set
+// up once per frame.  Separate instantiations keep LDS accesses LDS instructions.
+template <bool G>
+struct FrameMem {
+    int *X, *Y;
+    float *iw;
+    unsigned short *bin;
+    unsigned *surv;
+    int bin_max, surv_max;
+    int *o_tbase, *o_vbase, *o_mtb, *o_mvb, *o_nt, *o_seg, *o_vis;
+    float (*o_R)[9];
+    Material *o_mat;
+    unsigned char *vtx_hint;
+};
+
+template <bool G>
+ORRB_INLINE FrameMem<G> frame_mem(const RenderArgs &a, FrameLds &S) {
+    FrameMem<G> F;
+    if constexpr (G) {
+        char *base = a.fscratch + (int64_t)blockIdx.x * a.fscratch_stride;
+        const int64_t nv = a.fs_verts;
+        F.X = reinterpret_cast<int *>(base);
+        F.Y = F.X + nv;
+        F.iw = reinterpret_cast<float *>(F.Y + nv);
+        F.surv = reinterpret_cast<unsigned *>(F.iw + nv);
+        F.bin = reinterpret_cast<unsigned short *>(F.surv + a.fs_surv);
+        F.bin_max = a.fs_bins;
+        F.surv_max = a.fs_surv;
+        F.o_tbase = S.m.g.o_tbase;
+        F.o_vbase = S.m.g.o_vbase;
+        F.o_mtb = S.m.g.o_mtb;
+        F.o_mvb = S.m.g.o_mvb;
+        F.o_nt = S.m.g.o_nt;
+        F.o_seg = S.m.g.o_seg;
+        F.o_vis = S.m.g.o_vis;
+        F.o_R = S.m.g.o_R;
+        F.o_mat = S.m.g.o_mat;
+        F.vtx_hint = S.m.g.vtx_hint;
+    } else {
+        F.X = S.m.v.X;
+        F.Y = S.m.v.Y;
+        F.iw = S.m.v.iw;
+        F.surv = S.u.surv;
+        F.bin = S.bin;
+        F.bin_max = kFBinMax;
+        F.surv_max = kFSurvMax;
+        F.o_tbase = S.o_tbase;
+        F.o_vbase = S.o_vbase;
+        F.o_mtb = S.o_mtb;
+        F.o_mvb = S.o_mvb;
+        F.o_nt = S.o_nt;
+        F.o_seg = S.o_seg;
+        F.o_vis = S.o_vis;
+        F.o_R = S.o_R;
+        F.o_mat = S.o_mat;
+        F.vtx_hint = S.vtx_hint;
+    }
+    return F;
+}
+
 // Object owning element x (a scene triangle or vertex): start from the hint of x's
 // 64-element block and step forward over the objects that begin at or before x.
 ORRB_INLINE int slot_hint(const int *base, int n, const unsigned char *hint, int x) {
@@ -546,8 +627,9 @@ ORRB_INLINE unsigned char object_hint(const int *base, int n, int b) {
 }
 
 // Scene triangle t of object k and its mesh triangle (mesh-local vertex indices).
-ORRB_INLINE int4 frame_tri(const RenderArgs &a, const FrameLds &S, int k, int t) {
-    return a.mesh_tri[S.o_mtb[k] + (t - S.o_tbase[k])];
+template <bool G>
+ORRB_INLINE int4 frame_tri(const RenderArgs &a, const FrameMem<G> &F, int k, int t) {
+    return a.mesh_tri[F.o_mtb[k] + (t - F.o_tbase[k])];
 }
 
 // Set-up of scene triangle t (object k, mesh triangle tri): front-facing, valid, with
@@ -563,12 +645,13 @@ struct TriSetup {
 // binned) clipped to the tile [x0, x1] x [y0, y1]: false if its pixel-centre range
 // misses the tile.  Also returns the edge flags and the area as a float, the area from
 // 24-bit products when the triangle is small (the same integer as the 64-bit form).
-ORRB_INLINE bool tile_setup(const FrameLds &S, int k, int4 tri, int x0, int y0, int x1, int y1, TriSetup &T, int &flags,
-                            float &area) {
-    const int vb = S.o_vbase[k];
+template <bool G>
+ORRB_INLINE bool tile_setup(const FrameMem<G> &F, int k, int4 tri, int x0, int y0, int x1, int y1, TriSetup &T,
+                            int &flags, float &area) {
+    const int vb = F.o_vbase[k];
     const int i0v = vb + tri.x, i1v = vb + tri.y, i2v = vb + tri.z;
-    const int xa = S.X[i0v], xb = S.X[i2v], xc = S.X[i1v];
-    const int ya = S.Y[i0v], yb = S.Y[i2v], yc = S.Y[i1v];
+    const int xa = F.X[i0v], xb = F.X[i2v], xc = F.X[i1v];
+    const int ya = F.Y[i0v], yb = F.Y[i2v], yc = F.Y[i1v];
     const int xmin = min(xa, min(xb, xc)), xmax = max(xa, max(xb, xc));
     const int ymin = min(ya, min(yb, yc)), ymax = max(ya, max(yb, yc));
     T.i0 = max(ceil256(xmin - 128), x0);
@@ -588,12 +671,13 @@ ORRB_INLINE bool tile_setup(const FrameLds &S, int k, int4 tri, int x0, int y0, 
 }
 
 // (Hidden objects need no test: their vertices are all marked invalid.)
-ORRB_INLINE bool frame_setup(const FrameLds &S, int k, int4 tri, int cx0, int cy0, int cx1, int cy1, TriSetup &T) {
-    const int vb = S.o_vbase[k];
+template <bool G>
+ORRB_INLINE bool frame_setup(const FrameMem<G> &F, int k, int4 tri, int cx0, int cy0, int cx1, int cy1, TriSetup &T) {
+    const int vb = F.o_vbase[k];
     const int i0v = vb + tri.x, i1v = vb + tri.y, i2v = vb + tri.z;
-    const int x0 = S.X[i0v], x1 = S.X[i1v], x2 = S.X[i2v];
+    const int x0 = F.X[i0v], x1 = F.X[i1v], x2 = F.X[i2v];
     if (x0 == kInvalidX || x1 == kInvalidX || x2 == kInvalidX) return false;
-    const int y0 = S.Y[i0v], y1 = S.Y[i1v], y2 = S.Y[i2v];
+    const int y0 = F.Y[i0v], y1 = F.Y[i1v], y2 = F.Y[i2v];
     const int xmin = min(x0, min(x1, x2)), xmax = max(x0, max(x1, x2));
     const int ymin = min(y0, min(y1, y2)), ymax = max(y0, max(y1, y2));
     T.i0 = max(ceil256(xmin - 128), cx0);
@@ -614,11 +698,12 @@ ORRB_INLINE bool frame_setup(const FrameLds &S, int k, int4 tri, int cx0, int cy
 
 // Snap vertex v (object k, object-space position p) into the LDS vertex arrays.
 // Returns the vertex's cull reason (Snapped::cull; 0 for hidden objects).
-ORRB_INLINE int frame_vertex(FrameLds &S, int v, int k, float4 p, double fx, double fy, double cx, double cy,
-                             double nearp) {
+template <bool G>
+ORRB_INLINE int frame_vertex(const FrameLds &S, const FrameMem<G> &F, int v, int k, float4 p, double fx, double fy,
+                             double cx, double cy, double nearp) {
     int X = kInvalidX, Y = 0, cull = 0;
     float iw = 0.f;
-    if (S.o_vis[k]) {
+    if (F.o_vis[k]) {
         double M[12];
 #pragma unroll
         for (int q = 0; q < 12; ++q) M[q] = S.u.M[k][q];
@@ -630,9 +715,9 @@ ORRB_INLINE int frame_vertex(FrameLds &S, int v, int k, float4 p, double fx, dou
             iw = s.iw;
         }
     }
-    S.X[v] = X;
-    S.Y[v] = Y;
-    S.iw[v] = iw;
+    F.X[v] = X;
+    F.Y[v] = Y;
+    F.iw[v] = iw;
     return cull;
 }
 
@@ -646,14 +731,15 @@ ORRB_INLINE unsigned frame_count(FrameLds &S, int t, const TriSetup &T, int ntx)
     return ((unsigned)t << 16) | (unsigned)(tx0 | (tx1 << 2) | (ty0 << 4) | (ty1 << 10));
 }
 
-ORRB_INLINE void frame_append(FrameLds &S, bool keep, unsigned entry, int lane) {
+template <bool G>
+ORRB_INLINE void frame_append(FrameLds &S, const FrameMem<G> &F, bool keep, unsigned entry, int lane) {
     const unsigned long long m = __ballot(keep);
     int wb = 0;
     if (lane == 0 && m) wb = atomicAdd(&S.misc[3], __popcll(m));
     wb = __builtin_amdgcn_readlane(wb, 0);
     if (keep) {
         const int slot = wb + lanes_below(m);
-        if (slot < kFSurvMax) S.u.surv[slot] = entry;
+        if (slot < F.surv_max) F.surv[slot] = entry;
     }
 }
 
@@ -746,10 +832,15 @@ ORRB_INLINE void wait_bound_reached(const RenderArgs &a, FrameLds &S) {
     }
 }
 
-// Barrier of the compute waves; true if the workgroup has stopped.
+// Barrier of the compute waves; true if the workgroup has stopped.  G: the frame also
+// keeps data in global scratch, so the fences cover global memory too.
+template <bool G = false>
 ORRB_INLINE bool frame_barrier(const RenderArgs &a, FrameLds &S, int &gen) {
     gen += kFCW;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    if constexpr (G)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    else
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     int stop = 0;
     if (lane_id() == 0) {
         atomicAdd(&S.cbar, 1);
@@ -760,7 +851,10 @@ ORRB_INLINE bool frame_barrier(const RenderArgs &a, FrameLds &S, int &gen) {
     }
     stop = __builtin_amdgcn_readlane(stop, 0);
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    if constexpr (G)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    else
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     return stop != 0;
 }
 
@@ -882,6 +976,7 @@ ORRB_INLINE void stage_end(FrameLds &S, int s, int64_t po, int W, int H, int x0,
 ORRB_INLINE void frame_warm(const RenderArgs &a, int item, int lane) {
     if (item >= a.n_fitems) return;
     const int f = a.fitems[item];
+    if (f < 0) return;
     const FrameInfo fi = a.frames[f];
     int acc = 0;
     if (lane < fi.n_obj) {
@@ -1036,22 +1131,11 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
     }
 }
 
-// AUX: the transparency channel and the Tracker records are written (a separate
-// instantiation, so the plain four-channel kernel carries none of that code).
-template <bool AUX>
-__global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
-    __shared__ FrameLds S;
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    if (tid == 0) {
-        S.published = S.all_published = S.cbar = S.abort_flag = 0;
-        for (int k = 0; k < kFSlots; ++k) S.bgf[k].n = S.bg_next[k] = S.bg_done[k] = 0;
-        for (int k = 0; k < kFStage; ++k) S.stage_state[k] = 0;
-        for (int w = 0; w < kFW; ++w) S.cons_seq[w] = kFStageWave && w == kFW - 1 ? 0x7fffffff : 0;
-    }
-    __syncthreads();  // the only barrier of all 16 waves; compute waves use frame_barrier
-    if (wave < kFCW) {
-    int gen = 0;  // compute-wave barrier generation
-    for (int item = blockIdx.x, seq = 0; item < a.n_fitems; item += gridDim.x, ++seq) {
+// One frame rendered by the compute waves (phases 0-4 below); true if the workgroup has
+// stopped.  G selects where the scene's data live (FrameMem).
+template <bool AUX, bool G>
+ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int seq, int &gen) {
+    const FrameMem<G> F = frame_mem<G>(a, S);
     // Thread indices made opaque per frame: address arithmetic derived from them is
     // recomputed inside the frame instead of being hoisted (and spilled) across frames.
     int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -1067,20 +1151,20 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     if (tid < n_obj) {
         const int o = fi.obj_begin + tid;
         const ObjInfo ob = a.objs[o];
-        S.o_tbase[tid] = ob.scene_tbase;
-        S.o_vbase[tid] = ob.scene_vbase;
-        S.o_mtb[tid] = ob.mesh_tbegin;
-        S.o_mvb[tid] = ob.mesh_vbegin;
-        S.o_nt[tid] = ob.n_tris;
-        S.o_seg[tid] = a.seg[o];
-        S.o_vis[tid] = a.visible[o];
-        S.o_mat[tid] = object_material(a, o);
+        F.o_tbase[tid] = ob.scene_tbase;
+        F.o_vbase[tid] = ob.scene_vbase;
+        F.o_mtb[tid] = ob.mesh_tbegin;
+        F.o_mvb[tid] = ob.mesh_vbegin;
+        F.o_nt[tid] = ob.n_tris;
+        F.o_seg[tid] = a.seg[o];
+        F.o_vis[tid] = a.visible[o];
+        F.o_mat[tid] = object_material(a, o);
     }
     for (int e = tid; e < 12 * n_obj; e += kFCT) {
         const int k = e / 12, q = e - 12 * k;
         const double m = compose_entry(a.view + 12 * (int64_t)f, a.pose + 12 * (int64_t)(fi.obj_begin + k), q);
         S.u.M[k][q] = m;
-        if ((q & 3) != 3) S.o_R[k][(q >> 2) * 3 + (q & 3)] = (float)m;
+        if ((q & 3) != 3) F.o_R[k][(q >> 2) * 3 + (q & 3)] = (float)m;
     }
     if (tid < fi.n_lights) {
         const int l = fi.light_begin + tid;
@@ -1090,8 +1174,8 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     for (int t = tid; t <= n_tiles; t += kFCT) S.cnt[t] = 0;
     if (tid < 8) S.misc[tid] = 0;
     const int n_verts = n_obj > 0 ? a.objs[fi.obj_begin + n_obj - 1].scene_vbase + a.objs[fi.obj_begin + n_obj - 1].n_verts : 0;
-    if (frame_barrier(a, S, gen)) break;
-    const int n_tris = n_obj > 0 ? S.o_tbase[n_obj - 1] + S.o_nt[n_obj - 1] : 0;
+    if (frame_barrier<G>(a, S, gen)) return true;
+    const int n_tris = n_obj > 0 ? F.o_tbase[n_obj - 1] + F.o_nt[n_obj - 1] : 0;
     if (AUX && a.out_track && tid < n_obj) {
         const float *K = a.intr + 4 * (int64_t)f;
         track_init(a.out_track + fi.track_base + tid, S.u.M[tid][3], S.u.M[tid][7], S.u.M[tid][11], K[0], K[1], K[2],
@@ -1099,9 +1183,9 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         // the record must be in memory before any wave adds to it (after the barriers)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
-    for (int b = tid; b * kFHint < n_tris; b += kFCT) S.tri_hint[b] = object_hint(S.o_tbase, n_obj, b);
-    for (int b = tid; b * kFHint < n_verts; b += kFCT) S.vtx_hint[b] = object_hint(S.o_vbase, n_obj, b);
-    if (frame_barrier(a, S, gen)) break;
+    for (int b = tid; b * kFHint < n_tris; b += kFCT) S.tri_hint[b] = object_hint(F.o_tbase, n_obj, b);
+    for (int b = tid; b * kFHint < n_verts; b += kFCT) F.vtx_hint[b] = object_hint(F.o_vbase, n_obj, b);
+    if (frame_barrier<G>(a, S, gen)) return true;
 
     // ---- phase 1: vertices, kFVN per thread per pass; the next pass's positions are
     // loaded before the current pass is transformed, hiding the load latency ----
@@ -1111,8 +1195,8 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         // vertex v (clamped to the last one) of object k: its mesh position
         auto vload = [&](int v, int &k) {
             const int u = min(v, n_verts - 1);
-            k = slot_hint(S.o_vbase, n_obj, S.vtx_hint, u);
-            return a.mesh_pos[S.o_mvb[k] + (u - S.o_vbase[k])];
+            k = slot_hint(F.o_vbase, n_obj, F.vtx_hint, u);
+            return a.mesh_pos[F.o_mvb[k] + (u - F.o_vbase[k])];
         };
         int kn[kFVN];
         float4 pn[kFVN];
@@ -1139,7 +1223,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             for (int r = 0; r < kFVN; ++r) {
                 const int v = base + r * kFCT + tid;
                 if (v < n_verts) {
-                    const int cull = frame_vertex(S, v, k[r], p[r], fx, fy, cx, cy, nearp);
+                    const int cull = frame_vertex(S, F, v, k[r], p[r], fx, fy, cx, cy, nearp);
                     n_near += cull == 1;
                     n_guard += cull == 2;
                 }
@@ -1148,15 +1232,15 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         stat_add(a, ORRB_STAT_NEAR_VERTICES, n_near);  // rare: one atomic per thread that saw one
         stat_add(a, ORRB_STAT_GUARD_VERTICES, n_guard);
     }
-    if (frame_barrier(a, S, gen)) break;
+    if (frame_barrier<G>(a, S, gen)) return true;
 
     // ---- phase 2: set-up, per-tile counts, survivor list; kFTN triangles per thread
     // per pass, the next pass's mesh triangles loaded ahead ----
     {
         auto tload = [&](int t, int &k) {
             const int u = min(t, n_tris - 1);  // out-of-range lanes load the last triangle
-            k = slot_hint(S.o_tbase, n_obj, S.tri_hint, u);
-            return frame_tri(a, S, k, u);
+            k = slot_hint(F.o_tbase, n_obj, S.tri_hint, u);
+            return frame_tri(a, F, k, u);
         };
         int kn[kFTN];
         int4 tn[kFTN];
@@ -1182,13 +1266,13 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
             for (int r = 0; r < kFTN; ++r) {
                 const int t = base + r * kFCT + tid;
                 TriSetup T;
-                const bool keep = t < n_tris && frame_setup(S, k[r], tr[r], 0, 0, W - 1, H - 1, T);
+                const bool keep = t < n_tris && frame_setup(F, k[r], tr[r], 0, 0, W - 1, H - 1, T);
                 const unsigned e = keep ? frame_count(S, t, T, ntx) : 0u;
-                frame_append(S, keep, e, lane);
+                frame_append(S, F, keep, e, lane);
             }
         }
     }
-    if (frame_barrier(a, S, gen)) break;
+    if (frame_barrier<G>(a, S, gen)) return true;
     if (wave == 0) {  // exclusive scan of n_tiles <= 256 counts (4 per lane) and the tile order
         int c[4], local = 0, ne = 0;
 #pragma unroll
@@ -1200,7 +1284,7 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         }
         const int incl = wave_scan_add(local), incl_ne = wave_scan_add(ne);
         const int total_ne = __builtin_amdgcn_readlane(incl_ne, kWave - 1);
-        const bool overflow = __builtin_amdgcn_readlane(incl, kWave - 1) > kFBinMax;
+        const bool overflow = __builtin_amdgcn_readlane(incl, kWave - 1) > F.bin_max;
         int run = incl - local, run_ne = incl_ne - ne;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1226,30 +1310,30 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         const int n_busy = overflow ? n_tiles : total_ne;
         frame_publish(a, S, seq, fi.pixel_offset, W, H, ntx, n_busy, n_tiles, lane);
     }
-    if (frame_barrier(a, S, gen)) break;
+    if (frame_barrier<G>(a, S, gen)) return true;
     const bool overflow = S.misc[1] != 0;
 
     // ---- phase 3: scatter triangle IDs into the tile bins ----
     const int n_surv = S.misc[3];
-    if (!overflow && n_surv <= kFSurvMax) {
+    if (!overflow && n_surv <= F.surv_max) {
         for (int k = tid; k < n_surv; k += kFCT) {
-            const unsigned e = S.u.surv[k];
+            const unsigned e = F.surv[k];
             const int tx0 = e & 3, tx1 = (e >> 2) & 3, ty0 = (e >> 4) & 63, ty1 = (e >> 10) & 63;
             for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)(e >> 16);
+                for (int tx = tx0; tx <= tx1; ++tx) F.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)(e >> 16);
         }
     } else if (!overflow) {  // too many survivors to remember: set them up again
         if (tid == 0) stat_add(a, ORRB_STAT_SURVIVOR_RESETUP, 1u);
         for (int t = tid; t < n_tris; t += kFCT) {
-            const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, t);
+            const int k = slot_hint(F.o_tbase, n_obj, S.tri_hint, t);
             TriSetup T;
-            if (!frame_setup(S, k, frame_tri(a, S, k, t), 0, 0, W - 1, H - 1, T)) continue;
+            if (!frame_setup(F, k, frame_tri(a, F, k, t), 0, 0, W - 1, H - 1, T)) continue;
             for (int ty = (unsigned)T.j0 / kFTileH; ty <= (int)((unsigned)T.j1 / kFTileH); ++ty)
                 for (int tx = (unsigned)T.i0 / kFTileW; tx <= (int)((unsigned)T.i1 / kFTileW); ++tx)
-                    S.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)t;
+                    F.bin[atomicAdd(&S.cnt[ty * ntx + tx], 1)] = (unsigned short)t;
         }
     }
-    if (frame_barrier(a, S, gen)) break;
+    if (frame_barrier<G>(a, S, gen)) return true;
 
     // ---- phase 4: compute waves take the tiles with bin entries, rasterize, shade and
     // write them, issuing all loads of a tile before its stores; the store waves write
@@ -1285,19 +1369,19 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         // key leaves the tile.  Without bins (overflow) the wave scans every triangle.
         const int e0 = overflow ? 0 : S.off[t], e1 = overflow ? n_tris : S.off[t + 1];
         for (int e = e0 + lane; e < e1; e += kWave) {
-            const int tri = overflow ? e : (int)S.bin[e];
-            const int k = slot_hint(S.o_tbase, n_obj, S.tri_hint, tri);
+            const int tri = overflow ? e : (int)F.bin[e];
+            const int k = slot_hint(F.o_tbase, n_obj, S.tri_hint, tri);
             TriSetup T;
             int flags;
             float area;
             if (overflow) {  // unbinned: the full culling set-up
-                if (!frame_setup(S, k, frame_tri(a, S, k, tri), x0, y0, x1, y1, T)) continue;
+                if (!frame_setup(F, k, frame_tri(a, F, k, tri), x0, y0, x1, y1, T)) continue;
                 flags = tri_flags(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc);
                 area = (float)T.area;
-            } else if (!tile_setup(S, k, frame_tri(a, S, k, tri), x0, y0, x1, y1, T, flags, area)) {
+            } else if (!tile_setup(F, k, frame_tri(a, F, k, tri), x0, y0, x1, y1, T, flags, area)) {
                 continue;
             }
-            const float iwa = S.iw[T.va], iwb = S.iw[T.vb], iwc = S.iw[T.vc];
+            const float iwa = F.iw[T.va], iwb = F.iw[T.vb], iwc = F.iw[T.vc];
             if (!(flags & 8)) {  // small triangle: step the integer edge functions
                 const int b0 = (flags & 1) ? 0 : 1, b1 = (flags & 2) ? 0 : 1, b2 = (flags & 4) ? 0 : 1;
                 EdgeStep es = edge_start(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc, (T.i0 << 8) + 128, (T.j0 << 8) + 128);
@@ -1382,14 +1466,14 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
                 const unsigned long long key = vis[p];
                 const int tri = (int)(unsigned)(key & 0xffffu), k = (int)(unsigned)((key >> 16) & 0xffu);
                 const float z = __uint_as_float((unsigned)(key >> 32));
-                const int4 tv = frame_tri(a, S, k, tri);
-                const int vb = S.o_vbase[k], mvb = S.o_mvb[k];
+                const int4 tv = frame_tri(a, F, k, tri);
+                const int vb = F.o_vbase[k], mvb = F.o_mvb[k];
                 const int va = vb + tv.x, vbb = vb + tv.z, vc = vb + tv.y;  // positive-area order
-                o[h] = shade_pixel(S.X[va], S.Y[va], S.X[vbb], S.Y[vbb], S.X[vc], S.Y[vc], S.iw[va], S.iw[vbb], S.iw[vc],
-                                   a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], S.o_R[k], pi, pj,
-                                   z, cam, S.light, S.light_type, fi.n_lights, S.o_mat[k]);
+                o[h] = shade_pixel(F.X[va], F.Y[va], F.X[vbb], F.Y[vbb], F.X[vc], F.Y[vc], F.iw[va], F.iw[vbb], F.iw[vc],
+                                   a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], F.o_R[k], pi, pj,
+                                   z, cam, S.light, S.light_type, fi.n_lights, F.o_mat[k]);
                 kk[h] = key & ~0xffff0000ull;
-                sg[h] = S.o_seg[k];
+                sg[h] = F.o_seg[k];
                 pl[h] = p;
                 __builtin_amdgcn_sched_barrier(0);  // shade the two pixels one after the other
             }
@@ -1406,9 +1490,34 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         }
         stage_end(S, stg, po, W, H, x0, y0, vec_frame, lane);
     }
-    if (frame_barrier(a, S, gen)) break;  // the frame's LDS is reused by the next frame
+    return frame_barrier<G>(a, S, gen);  // the frame's LDS is reused by the next frame
+}
+
+// AUX: the transparency channel and the Tracker records are written (a separate
+// instantiation, so the plain four-channel kernel carries none of that code).  MIXED:
+// some frames keep their scene data in global scratch (frame_mem).
+template <bool AUX, bool MIXED>
+__global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
+    __shared__ FrameLds S;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    if (tid == 0) {
+        S.published = S.all_published = S.cbar = S.abort_flag = 0;
+        for (int k = 0; k < kFSlots; ++k) S.bgf[k].n = S.bg_next[k] = S.bg_done[k] = 0;
+        for (int k = 0; k < kFStage; ++k) S.stage_state[k] = 0;
+        for (int w = 0; w < kFW; ++w) S.cons_seq[w] = kFStageWave && w == kFW - 1 ? 0x7fffffff : 0;
     }
-    if (wave == 0 && lane == 0) __hip_atomic_store(&S.all_published, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();  // the only barrier of all 16 waves; compute waves use frame_barrier
+    if (wave < kFCW) {
+        int gen = 0;  // compute-wave barrier generation
+        for (int item = blockIdx.x, seq = 0; item < a.n_fitems; item += gridDim.x) {
+            const int f = a.fitems[item];
+            if (f < 0) continue;  // this workgroup's schedule is shorter
+            const bool stop = MIXED && a.frames[f].mode != 0 ? frame_render<AUX, true>(a, S, item, seq, gen)
+                                                             : frame_render<AUX, false>(a, S, item, seq, gen);
+            if (stop) break;
+            ++seq;
+        }
+        if (wave == 0 && lane == 0) __hip_atomic_store(&S.all_published, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     // store waves from the start, compute waves after their last frame
     frame_drain<AUX>(a, S, wave, lane / (kFTileW / 4), (lane % (kFTileW / 4)) * 4, lane);
@@ -1474,12 +1583,17 @@ hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu) {
 // Persistent: one workgroup per CU (the frame LDS allows no more), each rendering
 // frames blockIdx.x, blockIdx.x + gridDim.x, ...
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu) {
-    if (a.n_fitems <= 0) return hipSuccess;
-    const int grid = a.n_fitems < n_cu ? a.n_fitems : n_cu;
-    if (a.out_alpha || a.out_track)
-        hipLaunchKernelGGL(k_frame<true>, dim3(grid), dim3(kFT), 0, stream, a);
+    if (a.n_fitems <= 0 || a.f_grid <= 0) return hipSuccess;
+    const int grid = a.f_grid;  // the schedule's grid (at most the CU count)
+    const bool aux = a.out_alpha || a.out_track, mixed = a.fscratch != nullptr;
+    if (aux && mixed)
+        hipLaunchKernelGGL((k_frame<true, true>), dim3(grid), dim3(kFT), 0, stream, a);
+    else if (aux)
+        hipLaunchKernelGGL((k_frame<true, false>), dim3(grid), dim3(kFT), 0, stream, a);
+    else if (mixed)
+        hipLaunchKernelGGL((k_frame<false, true>), dim3(grid), dim3(kFT), 0, stream, a);
     else
-        hipLaunchKernelGGL(k_frame<false>, dim3(grid), dim3(kFT), 0, stream, a);
+        hipLaunchKernelGGL((k_frame<false, false>), dim3(grid), dim3(kFT), 0, stream, a);
     return hipGetLastError();
 }
 

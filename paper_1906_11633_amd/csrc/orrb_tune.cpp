@@ -84,23 +84,34 @@ orrb_status orrb_autotune(orrb_context *ctx, orrb_layout *layout, const orrb_sce
         if (best_ms) *best_ms = bms;
         return ORRB_OK;
     }
-    // candidates: the frame path (tile choices matter only for frames that do not fit)
-    // and the tiled path over tile shapes, bin capacities and the persistent grid
+    // candidates: the frame kernel with scenes in LDS (tile choices matter only for the
+    // frames it leaves to the tiled path), the frame kernel for every frame it can take
+    // (path 2: its global bin capacity; tile choices again only for what remains), and
+    // the tiled path over tile shapes, bin capacities and the persistent grid
     std::vector<orrb_tuning> cand;
     const int shapes[][2] = {{16, 16}, {32, 16}, {32, 32}, {64, 32}};
     const int caps[] = {256, 512};
-    orrb_tuning probe{32, 32, 256, 0, 0};
-    st = orrb_layout_set_tuning(layout, &probe);
+    orrb_tuning probe{32, 32, 256, 0, 0}, probe2{32, 32, 256, 0, 2};
+    orrb_layout_info pi, pi2;
+    st = orrb_layout_set_tuning(layout, &probe2);
+    if (st == ORRB_OK) st = orrb_layout_info_get(layout, &pi2);
+    if (st == ORRB_OK) st = orrb_layout_set_tuning(layout, &probe);
+    if (st == ORRB_OK) st = orrb_layout_info_get(layout, &pi);
     if (st != ORRB_OK) return st;
-    orrb_layout_info pi;
-    orrb_layout_info_get(layout, &pi);
     const bool all_fit = pi.frame_path_frames == pi.n_frames;
-    for (int path = 0; path <= 1; ++path) {
+    for (int path = 0; path <= 2; ++path) {
         if (path == 0 && all_fit) {
             cand.push_back(probe);
             continue;
         }
         if (path == 0 && pi.frame_path_frames == 0) continue;  // same as the tiled path
+        if (path == 2) {
+            if (pi2.frame_path_frames == pi.frame_path_frames) continue;  // same as path 0
+            if (pi2.frame_path_frames == pi2.n_frames) {  // one launch: only the global bin capacity matters
+                for (int cap : {256, 512, 1024}) cand.push_back(orrb_tuning{32, 32, cap, 0, 2});
+                continue;
+            }
+        }
         for (auto &sh : shapes)
             for (int cap : caps)
                 for (int pers = 0; pers <= 1; ++pers) cand.push_back(orrb_tuning{sh[0], sh[1], cap, pers, path});

@@ -66,3 +66,80 @@ def test_every_tuning_bit_identical_uneven(renderer):
         torch.cuda.synchronize()
         for k in ("rgb", "depth", "normal", "seg", "tri_id"):
             assert torch.equal(o[k], ref[k]), (t, k)
+
+
+def _render_np(renderer, batch, tuning, **kw):
+    import torch
+    job = renderer.prepare(batch)
+    job.layout.set_tuning(*tuning)
+    print(f"[batched] {batch.name} frames={batch.n_frames} tuning={tuning}", flush=True)
+    out = renderer.render(job, tri_id=True, stats=True, **kw)
+    torch.cuda.synchronize()
+    return parity.to_numpy(out), job
+
+
+def test_single_launch_uneven_batch_matches_oracle(renderer):
+    """Path 2: every frame of an uneven batch (64..256 px, 2k-50k triangles) on the frame
+    kernel, one launch; scenes beyond LDS keep vertices, bins and survivors in global
+    scratch.  Parity with the oracle, bit-identical to the tiled path, no fallbacks."""
+    b = S.config3(3, 12)
+    gpu, job = _render_np(renderer, b, (32, 32, 512, 0, 2))
+    inf = job.layout.info
+    assert inf.frame_path_frames == b.n_frames and inf.tile_items == 0
+    nv = np.array([sum(b.meshes[m].pos.shape[0] for m in b.object_mesh[b.scene_object_begin[s]:b.scene_object_begin[s + 1]])
+                   for s in range(b.n_scenes)])
+    assert (nv > 6976).any() and (nv <= 6976).any()  # both storage modes in the launch
+    parity.compare(b, gpu, oracle.render(b))
+    assert int(gpu["stats"][0]) == 0 and int(gpu["stats"][1]) == 0
+    tiled, _ = _render_np(renderer, b, (32, 32, 256, 1, 1))
+    for k in ("rgb", "depth", "normal", "seg", "tri_id"):
+        assert np.array_equal(gpu[k], tiled[k]), k
+
+
+@pytest.mark.parametrize("bin_cap", [256, 1024])
+def test_single_launch_global_bin_overflow(renderer, bin_cap):
+    """A scene beyond LDS (two 60 x 60 planes, 7,442 vertices) plus 100 frame-filling
+    quads: (tile, triangle) pairs exceed the global bins at bin_cap / 128 entries per
+    triangle, the frame falls back to scanning every triangle per tile; same bits as the
+    tiled path, and the oracle agrees."""
+    fine = S.plane_mesh(60, 60, 2.6, 2.6)
+    quad = S.plane_mesh(1, 1, 3.0, 3.0)
+    extra = [(fine, S.make_pose(S.rot_axis("x", 0.15), (0.0, 0.0, -2.3), 1.0))]
+    extra += [(quad, S.make_pose(S.rot_axis("y", 0.01 * k), (0.0, 0.0, -2.5 - 0.01 * k), 1.0)) for k in range(100)]
+    b = S.single_object_batch(fine, S.make_pose(np.eye(3), (0.0, 0.0, -2.0), 1.0), res=(256, 256), extra_objects=extra,
+                              lights=((0, (0.3, 0.4, 0.5), 1.5),), spec=0.4, rough=0.5)
+    gpu, job = _render_np(renderer, b, (32, 32, bin_cap, 0, 2))
+    assert job.layout.info.frame_path_frames == 1
+    if bin_cap == 256:
+        assert int(gpu["stats"][1]) == 1  # the bins overflowed
+    parity.compare(b, gpu, oracle.render(b))
+    tiled, _ = _render_np(renderer, b, (32, 32, 256, 0, 1))
+    for k in ("rgb", "depth", "normal", "seg", "tri_id"):
+        assert np.array_equal(gpu[k], tiled[k]), k
+
+
+def test_single_launch_hidden_objects_and_aux_outputs(renderer):
+    """Scratch-held scenes with hidden objects, an empty frame, and the transparency
+    and Tracker outputs: identical to the tiled path."""
+    from paper_1906_11633_amd.renderer import read_track
+    import torch
+    b = S.config3(5, 6, min_tris=9000)
+    vis = b.object_visible.copy()
+    vis[::4] = 0
+    view = b.view.copy()
+    view[2, :, 3] += np.array([0.0, 0.0, 50.0], np.float32)
+    b = b.replace(object_visible=vis, view=view)
+    res = []
+    for t in ((32, 32, 512, 0, 2), (32, 32, 256, 0, 1)):
+        job = renderer.prepare(b)
+        job.layout.set_tuning(*t)
+        out = renderer.render(job, tri_id=True, alpha=True, track=True)
+        torch.cuda.synchronize()
+        res.append((parity.to_numpy({k: v for k, v in out.items() if k != "track"}), read_track(out["track"]),
+                    job.layout.info.frame_path_frames))
+    assert res[0][2] == b.n_frames and res[1][2] == 0
+    for k in ("rgb", "depth", "normal", "seg", "tri_id", "alpha"):
+        assert np.array_equal(res[0][0][k], res[1][0][k]), k
+    for k in ("count", "bbox", "sum_i", "sum_j", "origin"):
+        np.testing.assert_array_equal(res[0][1][k], res[1][1][k])
+    parity.compare(b, res[0][0], oracle.render(b))
