@@ -48,8 +48,8 @@ def open_library(path: str):
     """Open a compiled oracle library and declare its entry points."""
     lib = C.CDLL(path)
     P = C.c_void_p
-    inputs = [P] * 17 + [C.c_int32] + [P] * 8
-    lib.oracle_render.argtypes = inputs + [P] * 8 + [C.c_int32]
+    inputs = [P] * 17 + [C.c_int32] + [P] * 8 + [P] * 6 + [C.c_int32]
+    lib.oracle_render.argtypes = inputs + [P] * 9 + [C.c_int32]
     lib.oracle_render.restype = C.c_int
     lib.oracle_shade_grad.argtypes = inputs + [C.c_int32, P, P, P, P, P, P, P, P, P, P, C.c_int32]
     lib.oracle_shade_grad.restype = C.c_int
@@ -112,6 +112,20 @@ class _Packed:
         lights = np.diff(self.scene_light_begin)
         if lights.size and lights.max() > 64:
             raise ValueError("oracle supports at most 64 lights per scene")
+        # spot lights (type 2): axis, cone cosines, shadow camera; shadow maps are set
+        # by render() once the shadow frames are rendered
+        nl = int(self.light_type.shape[0])
+        self.has_spot = bool((self.light_type == 2).any())
+        opt = lambda name, shape: (p64(getattr(b, name)) if getattr(b, name, None) is not None
+                                   else np.zeros(shape, np.float64))
+        self.light_dir = opt("light_dir", (nl, 3))
+        self.light_cone = opt("light_cone", (nl, 2))
+        self.shadow_view = opt("shadow_view", (nl, 3, 4))
+        self.shadow_intr = opt("shadow_intr", (nl, 4))
+        self.shadow_res = int(getattr(b, "shadow_res", 0) or 0)
+        self.shadow_slot = np.full(nl, -1, np.int32)
+        self.shadow_slot[self.light_type == 2] = np.arange(int((self.light_type == 2).sum()), dtype=np.int32)
+        self.shadow_maps = np.zeros(max(1, int((self.light_type == 2).sum())) * max(1, self.shadow_res) ** 2)
 
     def args(self):
         return [_ptr(self.mesh_vbegin), _ptr(self.mesh_tbegin), _ptr(self.mesh_pos), _ptr(self.mesh_nrm),
@@ -121,15 +135,39 @@ class _Packed:
                 _ptr(self.scene_light_begin), _ptr(self.light_type), _ptr(self.light_vec),
                 _ptr(self.light_intensity), self.n_frames, _ptr(self.frame_scene), _ptr(self.view),
                 _ptr(self.intr), _ptr(self.near), _ptr(self.exposure), _ptr(self.width),
-                _ptr(self.height), _ptr(self.pixel_offset)]
+                _ptr(self.height), _ptr(self.pixel_offset), _ptr(self.light_dir), _ptr(self.light_cone),
+                _ptr(self.shadow_view), _ptr(self.shadow_intr), _ptr(self.shadow_maps), _ptr(self.shadow_slot),
+                self.shadow_res]
 
 
 def _pack(batch):
     return _Packed(batch)
 
 
+def shadow_batch(batch):
+    """The shadow frames of a batch's spot lights (type 2): one N x N frame per spot
+    light, of that light's scene, seen from its shadow camera (near 0.01 m).  Only their
+    depth is used; their lights are made point lights so that rendering them needs no
+    shadow map."""
+    lt = np.asarray(batch.light_type)
+    spots = np.nonzero(lt == 2)[0]
+    slb = np.asarray(batch.scene_light_begin)
+    scene_of = np.searchsorted(slb, spots, side="right") - 1
+    N = int(batch.shadow_res)
+    n = spots.size
+    return batch.replace(
+        light_type=np.where(lt == 2, 0, lt).astype(np.int32), frame_scene=scene_of.astype(np.int32),
+        width=np.full(n, N, np.int32), height=np.full(n, N, np.int32),
+        view=np.asarray(batch.shadow_view, np.float32)[spots], intr=np.asarray(batch.shadow_intr, np.float32)[spots],
+        near=np.full(n, 0.01, np.float32), exposure=np.ones(n, np.float32), post=None)
+
+
 def render(batch, threads: int = 0) -> dict:
     """FP64 render of every frame (planar layout, frames packed in order).
+
+    Spot lights (type 2) cast shadows (Sec. 5: spot lights with soft shadows): their
+    shadow maps are first rendered as depth frames from the lights' shadow cameras by
+    this same oracle, then shading filters them (3 x 3 percentage-closer filtering).
 
     Keys: rgb f64[3*P], depth f64[P], normal f64[3*P], seg i32[P], tri_id i32[P],
     depth2 f64[P] (second-nearest fragment depth, +inf if none), frag_count i32[P],
@@ -137,12 +175,20 @@ def render(batch, threads: int = 0) -> dict:
     alpha f64[P] (1 covered, 0 background), pixel_offset i64[F+1]; P = total pixels."""
     pk = _pack(batch)
     P = pk.total_pixels
+    shadow = None
+    if pk.has_spot:
+        if pk.shadow_res < 1:
+            raise ValueError("spot lights need shadow_res >= 1")
+        shadow = render(shadow_batch(batch), threads)
+        pk.shadow_maps = np.ascontiguousarray(shadow["depth"], np.float64)
     out = dict(rgb=np.zeros(3 * P), depth=np.zeros(P), normal=np.zeros(3 * P),
                seg=np.zeros(P, np.int32), tri_id=np.zeros(P, np.int32), depth2=np.zeros(P),
-               frag_count=np.zeros(P, np.int32), obj_id=np.zeros(P, np.int32))
+               frag_count=np.zeros(P, np.int32), obj_id=np.zeros(P, np.int32), shadow_amb=np.zeros(P, np.uint8))
     rc = _load().oracle_render(*pk.args(), _ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["normal"]),
                                _ptr(out["seg"]), _ptr(out["tri_id"]), _ptr(out["depth2"]),
-                               _ptr(out["frag_count"]), _ptr(out["obj_id"]), int(threads))
+                               _ptr(out["frag_count"]), _ptr(out["obj_id"]), _ptr(out["shadow_amb"]), int(threads))
+    if shadow is not None:
+        out["shadow_depth"] = shadow["depth"]
     if rc != 0:
         raise MemoryError("oracle_render failed")
     out["pixel_offset"] = pk.pixel_offset
@@ -183,6 +229,8 @@ def shade_grad(batch, target_rgb=None, pixel_weight=None, threads: int = 0, dl_d
     g = dict(albedo=np.zeros((O, 3)), roughness=np.zeros(O), specular=np.zeros(O),
              light_vec=np.zeros((L, 3)), light_intensity=np.zeros(L), exposure=np.zeros(pk.n_frames))
     loss = np.zeros(1)
+    if pk.has_spot:
+        raise ValueError("the oracle's adjoint does not cover spot lights")
     rc = _load().oracle_shade_grad(*pk.args(), pk.n_scenes, _ptr(target), _ptr(wmask), _ptr(upstream),
                                    _ptr(loss), _ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]),
                                    _ptr(g["light_vec"]), _ptr(g["light_intensity"]), _ptr(g["exposure"]),

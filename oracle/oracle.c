@@ -33,6 +33,9 @@
 
 #define GUARD_SUBPX 16777216LL /* 2^24 sub-pixel units = 65536 px */
 #define LIGHT_EPS 1e-4         /* clamp of the squared light distance, m^2 */
+#define SHADOW_BIAS 0.02       /* spot-light shadow test: lit if (1 - bias) w <= map depth */
+#define SHADOW_AMB_DEPTH 1e-4  /* relative band of a depth comparison reported as ambiguous */
+#define SHADOW_AMB_TEXEL 1e-3  /* texels: band of a texel-boundary decision reported as ambiguous */
 #define HALF_EPS 1e-12         /* |l+v|^2 below this: no specular term */
 
 /* ------------------------------------------------------------------------------ */
@@ -51,6 +54,11 @@ typedef struct {
     const int32_t *frame_scene, *width, *height;
     const double *view, *intr, *near_, *exposure;
     const int64_t *pixel_offset;
+    /* spot lights (type 2): axis, cone, shadow camera and shadow map (may be NULL when
+     * the batch has no spot light) */
+    const double *light_dir, *light_cone, *shadow_view, *shadow_intr, *shadow_maps;
+    const int32_t *shadow_slot;
+    int32_t shadow_res;
 } Inputs;
 
 /* per-vertex results of the vertex stage for one (frame, object) */
@@ -271,10 +279,15 @@ static void fragment(const Inputs *in, int f, Vert **vt_of, const Pix *q, int i,
 
 /* A light expressed in the frame's view space. */
 typedef struct {
-    int type;      /* 0 point, 1 directional */
-    double q[3];   /* point: view-space position; directional: unit direction to the light */
+    int type;      /* 0 point, 1 directional, 2 spot (with a shadow map) */
+    double q[3];   /* point, spot: view-space position; directional: unit direction to the light */
     double qn;     /* directional: |R_V u| before normalization (1 for point lights) */
     double I;
+    /* spot: unit view-space axis, cosines of the inner and outer half-angles, the map
+     * (N x N depths) and T = shadow view o V^-1 (view space -> shadow camera space) */
+    double axis[3], cos_in, cos_out;
+    const double *map;
+    double T[12], sK[4];
 } VLight;
 
 static void view_lights(const Inputs *in, int f, VLight *L, int *nL) {
@@ -288,9 +301,32 @@ static void view_lights(const Inputs *in, int f, VLight *L, int *nL) {
         x->type = in->light_type[l];
         x->I = in->light_intensity[l];
         x->qn = 1.0;
-        if (x->type == 0) {
+        if (x->type == 0 || x->type == 2) {
             for (int r = 0; r < 3; r++) x->q[r] = V[r * 4 + 0] * u[0] + V[r * 4 + 1] * u[1] + V[r * 4 + 2] * u[2] + V[r * 4 + 3];
-        } else {
+        }
+        if (x->type == 2) {
+            const double *d = in->light_dir + 3 * (int64_t)l;
+            for (int r = 0; r < 3; r++) x->axis[r] = V[r * 4 + 0] * d[0] + V[r * 4 + 1] * d[1] + V[r * 4 + 2] * d[2];
+            normalize3(x->axis);
+            x->cos_in = in->light_cone[2 * (int64_t)l];
+            x->cos_out = in->light_cone[2 * (int64_t)l + 1];
+            int slot = in->shadow_slot[l];
+            int64_t N = in->shadow_res;
+            x->map = in->shadow_maps + (int64_t)slot * N * N;
+            /* V^-1 of the rigid view [R | t] is [R^T | -R^T t]; T = S o V^-1 */
+            const double *Sv = in->shadow_view + 12 * (int64_t)l;
+            double Vi[12];
+            for (int r = 0; r < 3; r++) {
+                for (int c = 0; c < 3; c++) Vi[r * 4 + c] = V[c * 4 + r];
+                Vi[r * 4 + 3] = -(V[0 * 4 + r] * V[3] + V[1 * 4 + r] * V[7] + V[2 * 4 + r] * V[11]);
+            }
+            for (int r = 0; r < 3; r++) {
+                for (int c = 0; c < 4; c++)
+                    x->T[r * 4 + c] = Sv[r * 4 + 0] * Vi[0 * 4 + c] + Sv[r * 4 + 1] * Vi[1 * 4 + c] + Sv[r * 4 + 2] * Vi[2 * 4 + c];
+                x->T[r * 4 + 3] += Sv[r * 4 + 3];
+            }
+            for (int k = 0; k < 4; k++) x->sK[k] = in->shadow_intr[4 * (int64_t)l + k];
+        } else if (x->type == 1) {
             for (int r = 0; r < 3; r++) x->q[r] = -(V[r * 4 + 0] * u[0] + V[r * 4 + 1] * u[1] + V[r * 4 + 2] * u[2]);
             x->qn = sqrt(dot3(x->q, x->q));
             normalize3(x->q);
@@ -301,16 +337,68 @@ static void view_lights(const Inputs *in, int f, VLight *L, int *nL) {
 /* Per-light terms of the shading function at one fragment. */
 typedef struct {
     double l[3], dist, D, A, ndl, h[3], hl, ndh, s;
-    int has_h; /* |l+v|^2 >= HALF_EPS */
+    int has_h;     /* |l+v|^2 >= HALF_EPS */
+    double cone;   /* spot: smoothstep cone factor (1 otherwise) */
+    double vis;    /* spot: fraction of the 3 x 3 shadow-map texels that see the point (1 otherwise) */
+    int amb;       /* spot: a texel choice or depth comparison lies within the reporting band */
 } LTerm;
 
-static void light_term(const VLight *L, const Frag *fr, double m, LTerm *t) {
-    if (L->type == 0) {
+/* Spot-light shadow visibility by 3 x 3 percentage-closer filtering: the point p (view
+ * space) goes to the shadow camera (T), projects to continuous map coordinates (u, v)
+ * (pixel units, origin top-left, y down); the 3 x 3 texels around the texel holding
+ * (u, v) each count as lit when (1 - bias) w <= their depth (an empty texel, depth 0,
+ * and a texel outside the map count as lit).  A point not in front of the shadow
+ * camera is lit.  *amb reports decisions within the bands. */
+static double shadow_visibility(const VLight *L, int64_t N, const double *p, int *amb) {
+    double q[3];
+    for (int r = 0; r < 3; r++) q[r] = L->T[r * 4 + 0] * p[0] + L->T[r * 4 + 1] * p[1] + L->T[r * 4 + 2] * p[2] + L->T[r * 4 + 3];
+    double w = -q[2];
+    *amb = 0;
+    if (w <= 0) return 1.0;
+    double u = L->sK[0] * (q[0] / w) + L->sK[2], v = -L->sK[1] * (q[1] / w) + L->sK[3];
+    double fu = floor(u), fv = floor(v);
+    if (u - fu < SHADOW_AMB_TEXEL || fu + 1 - u < SHADOW_AMB_TEXEL || v - fv < SHADOW_AMB_TEXEL ||
+        fv + 1 - v < SHADOW_AMB_TEXEL)
+        *amb = 1;
+    double wb = (1.0 - SHADOW_BIAS) * w;
+    int lit = 0;
+    for (int dj = -1; dj <= 1; dj++) {
+        for (int di = -1; di <= 1; di++) {
+            double ti = fu + di, tj = fv + dj;
+            if (ti < 0 || tj < 0 || ti >= (double)N || tj >= (double)N) {
+                lit++;
+                continue;
+            }
+            double z = L->map[(int64_t)tj * N + (int64_t)ti];
+            if (z == 0 || wb <= z) lit++;
+            if (z != 0 && fabs(wb - z) < SHADOW_AMB_DEPTH * w) *amb = 1;
+        }
+    }
+    return lit / 9.0;
+}
+
+/* Spot cone: smoothstep of cos(angle to the axis) from the outer to the inner cosine. */
+static double spot_cone(const VLight *L, const double *l) {
+    double c = -dot3(l, L->axis);
+    double t = (c - L->cos_out) / (L->cos_in - L->cos_out);
+    t = t < 0 ? 0 : (t > 1 ? 1 : t);
+    return t * t * (3 - 2 * t);
+}
+
+static void light_term(const VLight *L, const Frag *fr, double m, LTerm *t, int64_t shadow_res) {
+    t->cone = t->vis = 1.0;
+    t->amb = 0;
+    if (L->type == 0 || L->type == 2) {
         double d[3] = {L->q[0] - fr->p[0], L->q[1] - fr->p[1], L->q[2] - fr->p[2]};
         t->D = dot3(d, d);
         t->dist = sqrt(t->D);
         for (int k = 0; k < 3; k++) t->l[k] = d[k] / t->dist;
         t->A = L->I / (t->D > LIGHT_EPS ? t->D : LIGHT_EPS);
+        if (L->type == 2) {
+            t->cone = spot_cone(L, t->l);
+            t->vis = shadow_visibility(L, shadow_res, fr->p, &t->amb);
+            t->A *= t->cone * t->vis;
+        }
     } else {
         for (int k = 0; k < 3; k++) t->l[k] = L->q[k];
         t->D = t->dist = 1.0;
@@ -373,7 +461,8 @@ static void frame_end(FrameWork *fw) {
 }
 
 static void render_frame(const Inputs *in, int f, double *rgb, double *depth, double *normal, int32_t *seg,
-                         int32_t *tri_id, double *depth2, int32_t *frag_count, int32_t *obj_id, int *err) {
+                         int32_t *tri_id, double *depth2, int32_t *frag_count, int32_t *obj_id, uint8_t *shadow_amb,
+                         int *err) {
     FrameWork fw;
     if (frame_begin(in, f, &fw)) {
         *err = 1;
@@ -392,6 +481,7 @@ static void render_frame(const Inputs *in, int f, double *rgb, double *depth, do
             if (depth2) depth2[po + p] = q->tri >= 0 ? q->d2 : INFINITY;
             if (frag_count) frag_count[po + p] = q->count;
             if (obj_id) obj_id[po + p] = q->tri >= 0 ? q->obj : -1;
+            if (shadow_amb) shadow_amb[po + p] = 0;
             if (q->tri < 0) {
                 for (int c = 0; c < 3; c++) {
                     rgb[3 * po + c * HW + p] = 0;
@@ -410,8 +500,9 @@ static void render_frame(const Inputs *in, int f, double *rgb, double *depth, do
             double U[3] = {0, 0, 0};
             for (int l = 0; l < nL; l++) {
                 LTerm t;
-                light_term(L + l, &fr, mexp, &t);
+                light_term(L + l, &fr, mexp, &t, in->shadow_res);
                 for (int c = 0; c < 3; c++) U[c] += t.A * t.ndl * (alb[c] + ks * t.s);
+                if (shadow_amb && t.amb && t.ndl > 0 && t.cone > 0) shadow_amb[po + p] = 1;
             }
             double e = in->exposure[f];
             for (int c = 0; c < 3; c++) {
@@ -438,13 +529,16 @@ static void render_frame(const Inputs *in, int f, double *rgb, double *depth, do
         const int32_t *scene_light_begin, const int32_t *light_type, const double *light_vec,                 \
         const double *light_intensity, int32_t n_frames, const int32_t *frame_scene, const double *view,      \
         const double *intr, const double *near_, const double *exposure, const int32_t *width,                \
-        const int32_t *height, const int64_t *pixel_offset
+        const int32_t *height, const int64_t *pixel_offset, const double *light_dir, const double *light_cone,      \
+        const double *shadow_view, const double *shadow_intr, const double *shadow_maps,                        \
+        const int32_t *shadow_slot, int32_t shadow_res
 
 #define FILL_INPUTS(in)                                                                                         \
     Inputs in = {mesh_vbegin, mesh_tbegin, mesh_pos, mesh_nrm, mesh_idx, scene_object_begin, object_mesh,      \
                  object_seg, object_pose, object_visible, albedo, roughness, specular, scene_light_begin,      \
                  light_type, light_vec, light_intensity, frame_scene, width, height, view, intr, near_,        \
-                 exposure, pixel_offset}
+                 exposure, pixel_offset, light_dir, light_cone, shadow_view, shadow_intr, shadow_maps,         \
+                 shadow_slot, shadow_res}
 
 static void set_threads(int n_threads) {
 #ifdef _OPENMP
@@ -460,14 +554,14 @@ static void set_threads(int n_threads) {
  * fragment, -1 for background.  tri_id, depth2, frag_count and obj_id may be NULL.
  * Returns 0 on success. */
 int oracle_render(INPUT_ARGS, double *rgb, double *depth, double *normal, int32_t *seg, int32_t *tri_id,
-                  double *depth2, int32_t *frag_count, int32_t *obj_id, int32_t n_threads) {
+                  double *depth2, int32_t *frag_count, int32_t *obj_id, uint8_t *shadow_amb, int32_t n_threads) {
     FILL_INPUTS(in);
     int err = 0;
     set_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
     for (int f = 0; f < n_frames; f++) {
         int e = 0;
-        render_frame(&in, f, rgb, depth, normal, seg, tri_id, depth2, frag_count, obj_id, &e);
+        render_frame(&in, f, rgb, depth, normal, seg, tri_id, depth2, frag_count, obj_id, shadow_amb, &e);
         err |= e;
     }
     return err;
@@ -486,6 +580,8 @@ int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const 
                       const double *dl_drgb, double *loss_out, double *g_albedo, double *g_rough, double *g_spec, double *g_lightvec,
                       double *g_intensity, double *g_exposure, int32_t n_threads) {
     FILL_INPUTS(in);
+    for (int64_t l = 0; l < scene_light_begin[n_scenes]; l++)
+        if (light_type[l] == 2) return 2; /* spot lights: no adjoint (shadow visibility is not differentiated) */
     int err = 0;
     double *scene_loss = (double *)calloc((size_t)n_scenes + 1, sizeof(double));
     if (!scene_loss) return 1;
@@ -533,7 +629,7 @@ int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const 
                     LTerm t[64];
                     double U[3] = {0, 0, 0};
                     for (int l = 0; l < nL; l++) {
-                        light_term(L + l, &fr, mexp, t + l);
+                        light_term(L + l, &fr, mexp, t + l, in.shadow_res);
                         for (int c = 0; c < 3; c++) U[c] += t[l].A * t[l].ndl * (alb[c] + ks * t[l].s);
                     }
                     double g[3], G = 0;

@@ -290,6 +290,13 @@ class Batch:
     # grain noise texture (see with_postprocessing)
     post: Optional[np.ndarray] = None   # f32 [F, 12]
     grain: Optional[np.ndarray] = None  # f32 [3, GH, GW] in [0, 1)
+    # spot lights (light_type 2), optional: axis, cone cosines (inner, outer), shadow
+    # camera (world -> light camera, intrinsics of an N x N map) and N
+    light_dir: Optional[np.ndarray] = None    # f32 [L, 3]
+    light_cone: Optional[np.ndarray] = None   # f32 [L, 2]
+    shadow_view: Optional[np.ndarray] = None  # f32 [L, 3, 4]
+    shadow_intr: Optional[np.ndarray] = None  # f32 [L, 4]
+    shadow_res: int = 0
 
     @property
     def n_scenes(self) -> int:
@@ -358,7 +365,11 @@ class Batch:
             light_vec=self.light_vec[lights], light_intensity=self.light_intensity[lights],
             view=self.view[frames], intr=self.intr[frames], near=self.near[frames],
             exposure=self.exposure[frames], name=self.name + "[sub]",
-            post=None if self.post is None else self.post[frames], grain=self.grain)
+            post=None if self.post is None else self.post[frames], grain=self.grain,
+            light_dir=None if self.light_dir is None else self.light_dir[lights],
+            light_cone=None if self.light_cone is None else self.light_cone[lights],
+            shadow_view=None if self.shadow_view is None else self.shadow_view[lights],
+            shadow_intr=None if self.shadow_intr is None else self.shadow_intr[lights], shadow_res=self.shadow_res)
 
     def replace(self, **kw) -> "Batch":
         d = dict(self.__dict__)
@@ -622,6 +633,61 @@ def with_postprocessing(batch: Batch, seed: int = 0) -> Batch:
     """The batch with randomized post-processing parameters and grain texture."""
     post, grain = postprocess_params(seed, batch.n_frames, batch.frame_scene)
     return batch.replace(post=post, grain=grain)
+
+
+# ----------------------------------------------------------------------------------
+# spot lights with shadow maps (the paper's benchmark scene: three spot lights with
+# soft shadows; LightRandomizer: intensities and spotlight angles; LightSetup:
+# distance from and height above a target)
+# ----------------------------------------------------------------------------------
+
+SPOT_SHADOW_RES = 128
+
+
+def spot_light(rng: np.random.Generator, target, res: int = SPOT_SHADOW_RES):
+    """One spot light placed like LightSetup (horizontal distance U[0.4, 0.8] m, height
+    U[0.3, 0.8] m, azimuth U[0, 2 pi) around the target), aimed at the target within
+    +-3 cm, outer half-angle U[20, 35] deg, inner = outer * U[0.5, 0.9], intensity
+    U[0.5, 2]; its shadow camera looks along the axis with a field of view of twice the
+    outer angle plus 2 deg over an N x N map.  Returns (pos, axis, (cos inner, cos
+    outer), intensity, view 3x4, intrinsics)."""
+    target = np.asarray(target, float)
+    az = rng.uniform(0, 2 * np.pi)
+    rho = rng.uniform(0.4, 0.8)
+    hgt = rng.uniform(0.3, 0.8)
+    pos = target + np.array([rho * math.cos(az), rho * math.sin(az), hgt])
+    aim = target + rng.uniform(-0.03, 0.03, 3)
+    axis = (aim - pos) / np.linalg.norm(aim - pos)
+    outer = math.radians(rng.uniform(20.0, 35.0))
+    inner = outer * rng.uniform(0.5, 0.9)
+    inten = rng.uniform(0.5, 2.0)
+    C = look_at_c2w(pos, pos + axis, (0, 0, 1))
+    view = view_from_c2w(C)
+    K = intrinsics(res, res, 2 * math.degrees(outer) + 2.0)
+    return pos, axis, (math.cos(inner), math.cos(outer)), inten, view, K
+
+
+def with_spot_lights(batch: Batch, seed: int = 0, n_lights: int = 3, res: int = SPOT_SHADOW_RES,
+                     target=None) -> Batch:
+    """The batch with every scene's lights replaced by n_lights shadow-casting spot
+    lights (type 2) aimed at `target` (default: the hand scenes' target).  Draws come
+    from default_rng([seed, 0x5907, scene])."""
+    tgt = HAND_TARGET if target is None else np.asarray(target, float)
+    S_ = batch.n_scenes
+    L = S_ * n_lights
+    vec = np.zeros((L, 3)); inten = np.zeros(L); dirs = np.zeros((L, 3)); cone = np.zeros((L, 2))
+    views = np.zeros((L, 3, 4)); intr = np.zeros((L, 4))
+    for sc in range(S_):
+        rng = np.random.default_rng([seed, 0x5907, sc])
+        for k in range(n_lights):
+            pos, axis, cs, I, V, K = spot_light(rng, tgt, res)
+            l = sc * n_lights + k
+            vec[l], dirs[l], cone[l], inten[l], views[l], intr[l] = pos, axis, cs, I, V, K
+    f32 = lambda x: np.asarray(x, np.float64).astype(np.float32)
+    return batch.replace(scene_light_begin=(np.arange(S_ + 1) * n_lights).astype(np.int32),
+                         light_type=np.full(L, 2, np.int32), light_vec=f32(vec), light_intensity=f32(inten),
+                         light_dir=f32(dirs), light_cone=f32(cone), shadow_view=f32(views), shadow_intr=f32(intr),
+                         shadow_res=int(res))
 
 
 # ----------------------------------------------------------------------------------
