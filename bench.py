@@ -153,6 +153,23 @@ def measure_aux(args, r, S, batch, job, torch, frame_ms_plain):
                                           frac=round(pbytes / (post_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))))
 
 
+def measure_shadows(args, r, S, torch):
+    """The workload lit like the paper's benchmark scene: three shadow-casting spot
+    lights per scene (LightSetup placement, randomized angles), 128 x 128 shadow maps
+    rendered by the same kernels (depth only) before the frames, 3 x 3 filtered."""
+    b = S.with_spot_lights(S.config2(2, args.scenes, args.res), seed=2)
+    job = r.prepare(b)
+    out = r.alloc_outputs(job)
+    for _ in range(3):
+        r.render(job, out)
+    n = max(10, args.steps // 4)
+    dt = _timed(lambda: r.render(job, out), n, torch)
+    ev = _event_times(lambda: r.render(job, out), n, torch)
+    return dict(frames=b.n_frames, shadow_maps=int((b.light_type == 2).sum()), shadow_res=int(b.shadow_res),
+                ms_per_step=round(dt * 1e3, 4), frames_per_s=round(b.n_frames / dt, 1),
+                event_ms_median=_pct(ev, 50), event_ms_p90=_pct(ev, 90))
+
+
 def measure_extras(args, r, S):
     """Shading-gradient throughput (64 scenes x 3 cameras at 200x200), the serving loop
     (Poisson 2000 req/s of 1-32 scenes at 64/128/200 px), and the uneven batch (1024
@@ -366,6 +383,9 @@ def main(argv=None):
     extra["aux_outputs"] = measure_aux(args, r, S, batch, job, torch, kernel_ms["k_frame"])
     print(f"[bench] with alpha, tracker and rgb8: {extra['aux_outputs']['ms_per_step']:.3f} ms/step, "
           f"k_post {extra['aux_outputs']['k_post']['ms']:.3f} ms", file=sys.stderr, flush=True)
+    extra["spot_shadows"] = measure_shadows(args, r, S, torch)
+    print(f"[bench] three shadow-casting spot lights: {extra['spot_shadows']['ms_per_step']:.3f} ms/step",
+          file=sys.stderr, flush=True)
     for _ in range(2):
         r.render(job, out)  # the outputs hold the render again
 

@@ -73,6 +73,7 @@ typedef struct orrb_layout orrb_layout;
 
 /* Documented limits. */
 #define ORRB_MAX_LIGHTS_PER_SCENE 8
+#define ORRB_MAX_SPOT_LIGHTS_PER_SCENE 4
 #define ORRB_MAX_DIM 8192           /* frame width and height */
 #define ORRB_MAX_SCENE_TRIANGLES 0x7fffff00  /* scene-local triangle IDs fit 31 bits */
 
@@ -110,11 +111,14 @@ typedef struct {
     const int32_t *scene_object_begin; /* [n_scenes+1], non-decreasing, starts at 0 */
     const int32_t *object_mesh;        /* [n_objects] mesh ids of this context */
     const int32_t *scene_light_begin;  /* [n_scenes+1], <= ORRB_MAX_LIGHTS_PER_SCENE each */
-    const int32_t *light_type;         /* [n_lights] 0 = point, 1 = directional */
+    const int32_t *light_type;         /* [n_lights] 0 = point, 1 = directional, 2 = spot light with a
+                                          shadow map (<= ORRB_MAX_SPOT_LIGHTS_PER_SCENE per scene) */
     int32_t n_frames;
     const int32_t *frame_scene;        /* [n_frames] scene of each frame (camera image) */
     const int32_t *width;              /* [n_frames] in [1, ORRB_MAX_DIM] */
     const int32_t *height;             /* [n_frames] in [1, ORRB_MAX_DIM] */
+    int32_t shadow_res;                /* shadow maps are shadow_res x shadow_res, in [8, 256]
+                                          (ignored without spot lights) */
 } orrb_layout_desc;
 
 /* Launch choices.  They change speed only: the output bits are the same for every
@@ -203,6 +207,22 @@ typedef struct {                  /* sampled randomization parameters */
     const float *post;
     const float *grain;
     int32_t grain_w, grain_h;
+    /* Spot lights (type 2; the paper's benchmark scene has spot lights with soft
+     * shadows, Sec. 5; the LightRandomizer draws spotlight angles, Sec. 4.3.1).  Needed
+     * when the layout has spot lights (NULL otherwise).  A spot light sits at light_vec
+     * and points along light_dir (world, any length); its light falls off like a point
+     * light's, times smoothstep((c - cos_outer) / (cos_inner - cos_outer)) of the cosine
+     * c between the axis and the direction from the light.  Each casts shadows through a
+     * shadow map: the depth (along -z) of the scene seen from shadow_view / shadow_intr (a
+     * camera at the light looking along its axis, over shadow_res x shadow_res pixels,
+     * near plane 0.01 m), rendered with the same rules as the frames before them.  A
+     * shaded point of eye depth w in the shadow camera sees the light by the fraction of
+     * the 3 x 3 map texels around its texel with (1 - 0.02) w <= their depth (empty and
+     * off-map texels count, a point not in front of the shadow camera is lit). */
+    const float *light_dir;       /* [L,3] */
+    const float *light_cone;      /* [L,2] cos(inner half-angle), cos(outer half-angle) */
+    const float *shadow_view;     /* [L,3,4] world -> shadow camera (rigid) */
+    const float *shadow_intr;     /* [L,4] fx, fy, cx, cy in shadow-map pixels */
 } orrb_params;
 
 #define ORRB_POST_WORDS 12
@@ -358,7 +378,7 @@ typedef struct {                  /* device destinations, overwritten (not accum
  * analytic derivative of the shading function in include/orrb.h's conventions,
  * evaluated per pixel in FP64 and reduced in a fixed order, so repeated calls are
  * bit-identical.  Sub-gradient 0 is taken where a max(0, .) is inactive.  Scenes with
- * more than 1024 objects return ORRB_ERR_UNSUPPORTED.  `workspace` needs
+ * more than 1024 objects, and layouts with spot lights, return ORRB_ERR_UNSUPPORTED.  `workspace` needs
  * orrb_layout_info.grad_workspace_bytes.  Asynchronous on `stream`. */
 orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
                                 const orrb_cameras *cameras, const orrb_params *params, const uint64_t *vis,

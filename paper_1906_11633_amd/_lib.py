@@ -18,6 +18,7 @@ ORRB_OK = 0
 STATUS_NAMES = {0: "ORRB_OK", 1: "ORRB_ERR_INVALID_ARGUMENT", 2: "ORRB_ERR_OUT_OF_MEMORY",
                 3: "ORRB_ERR_WORKSPACE_TOO_SMALL", 4: "ORRB_ERR_DEVICE", 5: "ORRB_ERR_UNSUPPORTED"}
 MAX_LIGHTS_PER_SCENE = 8
+MAX_SPOT_LIGHTS_PER_SCENE = 4
 NOALLOC_SCRATCH_BYTES = 64 << 20  # ORRB_NOALLOC_SCRATCH_BYTES
 # words of the per-call stats destination (orrb_outputs.stats)
 STATS_WORDS = 8
@@ -34,7 +35,7 @@ class OrrbError(RuntimeError):
 class LayoutDesc(C.Structure):
     _fields_ = [("n_scenes", C.c_int32), ("scene_object_begin", P), ("object_mesh", P),
                 ("scene_light_begin", P), ("light_type", P), ("n_frames", C.c_int32),
-                ("frame_scene", P), ("width", P), ("height", P)]
+                ("frame_scene", P), ("width", P), ("height", P), ("shadow_res", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -65,7 +66,7 @@ class Cameras(C.Structure):
 class Params(C.Structure):
     _fields_ = [("albedo", P), ("roughness", P), ("specular", P), ("light_vec", P),
                 ("light_intensity", P), ("exposure", P), ("post", P), ("grain", P), ("grain_w", C.c_int32),
-                ("grain_h", C.c_int32)]
+                ("grain_h", C.c_int32), ("light_dir", P), ("light_cone", P), ("shadow_view", P), ("shadow_intr", P)]
 
 
 class Outputs(C.Structure):

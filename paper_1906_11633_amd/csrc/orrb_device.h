@@ -12,6 +12,7 @@ namespace orrb {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads per raster / vertex workgroup
 constexpr int kMaxLights = 8;
+constexpr int kMaxSpots = 4;         // spot lights per scene
 constexpr int kGuard = 1 << 24;      // snapped coordinates beyond this are discarded
 constexpr int kSmallExtent = 1 << 14;// triangles up to 64 px wide use exact int32 edges
 constexpr unsigned long long kEmptyKey = ~0ull;
@@ -70,6 +71,12 @@ struct RenderArgs {
     float *out_alpha;
     uint8_t *out_rgb8;
     orrb_track *out_track;
+    // spot lights (type 2) and their shadow maps (null without spot lights)
+    const float *light_dir, *light_cone, *shadow_view, *shadow_intr;
+    const int32_t *spot_slot;  // per light: shadow-map slot
+    const float *shadow_maps;  // [slots, N, N] eye depths from the lights (0: empty)
+    int32_t shadow_res;        // N
+    int32_t shade_mode;        // frame kernel: 0 plain, 1 with spot lights, 2 depth only (no shading)
     // post-processing of rgb8
     const float *post;   // [F, ORRB_POST_WORDS] or null
     const float *grain;  // [3, grain_h, grain_w] or null
@@ -132,6 +139,8 @@ void context_set_profiling(orrb_context *ctx, bool on);
 hipError_t launch_vertex(const RenderArgs &a, hipStream_t stream);
 hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu);
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu);
+hipError_t launch_shadow_cams(const int32_t *spot_light, int n_spot, const float *shadow_view, const float *shadow_intr,
+                              float *view, float *intr, float *nearp, hipStream_t stream);
 hipError_t launch_post(const RenderArgs &a, hipStream_t stream, int n_frames, int64_t max_frame_pixels);
 hipError_t read_wait_timeouts(unsigned int *out);  // frame-kernel waits that hit their bound
 bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height);

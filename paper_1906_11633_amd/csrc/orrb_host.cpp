@@ -170,8 +170,17 @@ struct orrb_layout {
     int64_t f_frames = 0;          // frames on the frame kernel
     int32_t f_grid = 0;            // its persistent grid
     std::vector<int32_t> light_type;
-    Packed tab;  // frames, objs, vitems, titems, fitems, light_type
+    Packed tab;  // frames, objs, vitems, titems, fitems, light_type, spot tables
     size_t o_frames = 0, o_objs = 0, o_vitems = 0, o_titems = 0, o_fitems = 0, o_light_type = 0;
+    // spot lights (type 2) with shadow maps: one N x N depth frame per spot light, from
+    // its shadow camera, rendered by a sub-layout before the frames themselves
+    int64_t n_spot = 0;
+    int32_t shadow_res = 0;
+    std::vector<int32_t> spot_slot;   // per light: its shadow-map slot, -1 for other lights
+    std::vector<int32_t> spot_light;  // per slot: the light
+    std::vector<int32_t> spot_scene;  // per slot: the light's scene
+    size_t o_spot_slot = 0, o_spot_light = 0;
+    orrb_layout *shadow = nullptr;
     orrb_tuning tuning{32, 32, 256, 0, 0};
     // shading adjoint: every frame on the tiled-path vertex tables, gradient tiles
     std::vector<FrameInfo> frames_all;
@@ -316,6 +325,29 @@ static size_t ws_bytes_any(const orrb_layout *L) {
     return ws_layout(L->all_vertex_instances, L->all_object_instances).total + fs.stride * (size_t)fs.grid + 256;
 }
 
+// Workspace of one render call: the frames' own, then (with spot lights) the shadow
+// frames' (rendered first, on the same stream), the shadow maps (N x N fp32 per spot
+// light) and the gathered shadow cameras (view 12, intrinsics 4, near 1 floats each).
+struct CallWs {
+    WsLayout w;
+    size_t shadow_ws = 0, shadow_ws_bytes = 0, maps = 0, cams = 0, total = 0;
+};
+
+static CallWs call_ws(const orrb_layout *L, size_t shadow_ws_bytes) {
+    CallWs c;
+    c.w = ws_layout(L);
+    c.total = c.w.total;
+    if (L->shadow) {
+        c.shadow_ws = al256(c.total);
+        c.shadow_ws_bytes = shadow_ws_bytes;
+        c.maps = al256(c.shadow_ws + shadow_ws_bytes);
+        c.cams = al256(c.maps + sizeof(float) * (size_t)L->n_spot * L->shadow_res * L->shadow_res);
+        c.total = c.cams + sizeof(float) * 17 * (size_t)L->n_spot;
+    }
+    return c;
+}
+static CallWs call_ws(const orrb_layout *L) { return call_ws(L, L->shadow ? ws_layout(L->shadow).total : 0); }
+
 // Split frames between the frame kernel and the tiled path and build the work items.
 // Path 0: the frame kernel takes frames whose scene fits in LDS; path 1: every frame
 // on the tiled path; path 2: the frame kernel also takes larger scenes (up to 65,536
@@ -448,6 +480,10 @@ static orrb_status upload_layout(orrb_layout *L) {
     L->o_titems = P.add(L->titems);
     L->o_fitems = P.add(L->fitems);
     L->o_light_type = P.add(L->light_type);
+    if (L->n_spot > 0) {
+        L->o_spot_slot = P.add(L->spot_slot);
+        L->o_spot_light = P.add(L->spot_light);
+    }
     HIP_TRY(P.upload());
     return ORRB_OK;
 }
@@ -615,9 +651,24 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
     for (int64_t o = 0; o < O; ++o)
         if (d->object_mesh[o] < 0 || d->object_mesh[o] >= n_meshes)
             return fail(ORRB_ERR_INVALID_ARGUMENT, "object %lld uses unknown mesh %d", (long long)o, d->object_mesh[o]);
-    for (int64_t l = 0; l < NL; ++l)
-        if (d->light_type[l] != 0 && d->light_type[l] != 1)
-            return fail(ORRB_ERR_INVALID_ARGUMENT, "light %lld has type %d (0 point, 1 directional)", (long long)l, d->light_type[l]);
+    int64_t n_spot = 0;
+    for (int64_t l = 0; l < NL; ++l) {
+        if (d->light_type[l] < 0 || d->light_type[l] > 2)
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "light %lld has type %d (0 point, 1 directional, 2 spot)",
+                        (long long)l, d->light_type[l]);
+        n_spot += d->light_type[l] == 2;
+    }
+    if (n_spot > 0) {
+        if (d->shadow_res < 8 || d->shadow_res > 256)
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "shadow_res %d out of [8, 256] with spot lights", d->shadow_res);
+        for (int s = 0; s < S; ++s) {
+            int k = 0;
+            for (int l = d->scene_light_begin[s]; l < d->scene_light_begin[s + 1]; ++l) k += d->light_type[l] == 2;
+            if (k > ORRB_MAX_SPOT_LIGHTS_PER_SCENE)
+                return fail(ORRB_ERR_UNSUPPORTED, "scene %d has %d spot lights (max %d)", s, k,
+                            ORRB_MAX_SPOT_LIGHTS_PER_SCENE);
+        }
+    }
     for (int f = 0; f < d->n_frames; ++f) {
         if (d->frame_scene[f] < 0 || d->frame_scene[f] >= S)
             return fail(ORRB_ERR_INVALID_ARGUMENT, "frame %d refers to scene %d of %d", f, d->frame_scene[f], S);
@@ -657,6 +708,20 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
         L->scene_tris[s] = tb;
     }
     L->light_type.assign(d->light_type, d->light_type + NL);
+    if (n_spot > 0) {
+        L->n_spot = n_spot;
+        L->shadow_res = d->shadow_res;
+        L->spot_slot.assign(NL, -1);
+        std::vector<int32_t> frame_scene;
+        for (int s = 0; s < S; ++s)
+            for (int l = d->scene_light_begin[s]; l < d->scene_light_begin[s + 1]; ++l)
+                if (d->light_type[l] == 2) {
+                    L->spot_slot[l] = (int32_t)L->spot_light.size();
+                    L->spot_light.push_back(l);
+                    frame_scene.push_back(s);
+                }
+        L->spot_scene.swap(frame_scene);
+    }
     L->frames.resize(d->n_frames);
     L->fits.resize(d->n_frames);
     int64_t pix = 0, vi = 0, oi = 0, ti = 0;
@@ -727,6 +792,25 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
         delete L;
         return st;
     }
+    if (L->n_spot > 0) {  // the shadow frames: the same scenes, no lights, one N x N frame per spot light
+        std::vector<int32_t> no_lights(S + 1, 0), side(L->n_spot, d->shadow_res);
+        orrb_layout_desc sd{};
+        sd.n_scenes = S;
+        sd.scene_object_begin = d->scene_object_begin;
+        sd.object_mesh = d->object_mesh;
+        sd.scene_light_begin = no_lights.data();
+        sd.light_type = nullptr;
+        sd.n_frames = (int32_t)L->n_spot;
+        sd.frame_scene = L->spot_scene.data();
+        sd.width = side.data();
+        sd.height = side.data();
+        sd.shadow_res = 0;
+        st = orrb_layout_create(ctx, &sd, &L->shadow);
+        if (st != ORRB_OK) {
+            delete L;
+            return st;
+        }
+    }
     ctx->n_layouts++;
     *out = L;
     return ORRB_OK;
@@ -735,6 +819,7 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
 void orrb_layout_destroy(orrb_layout *L) {
     if (!L) return;
     ScopedDevice sd(L->ctx->device);
+    if (L->shadow) orrb_layout_destroy(L->shadow);
     L->ctx->n_layouts--;
     delete L;
 }
@@ -751,8 +836,9 @@ orrb_status orrb_layout_info_get(const orrb_layout *L, orrb_layout_info *info) {
     info->triangle_instances = L->triangle_instances;
     info->tile_items = (int64_t)L->titems.size();
     info->frame_path_frames = L->f_frames;
-    info->workspace_bytes = ws_layout(L).total;
+    info->workspace_bytes = call_ws(L).total;
     info->workspace_bytes_any = ws_bytes_any(L);
+    if (L->shadow) info->workspace_bytes_any += call_ws(L, ws_bytes_any(L->shadow)).total - ws_layout(L).total + 256;
     info->grad_workspace_bytes = grad_workspace(L);
     info->table_bytes = L->tab.dev.bytes + L->gtab.dev.bytes;
     info->tuning = L->tuning;
@@ -768,6 +854,10 @@ orrb_status orrb_layout_set_tuning(orrb_layout *L, const orrb_tuning *t) {
     const bool rebuild = t->tile_w != L->tuning.tile_w || t->tile_h != L->tuning.tile_h || t->path != L->tuning.path;
     if (memcmp(t, &L->tuning, sizeof(*t)) != 0) L->generation++;  // captured graphs are now stale
     L->tuning = *t;
+    if (L->shadow) {  // the shadow frames follow the same tuning
+        const orrb_status st = orrb_layout_set_tuning(L->shadow, t);
+        if (st != ORRB_OK) return st;
+    }
     if (rebuild) {
         build_items(L);
         return upload_layout(L);
@@ -777,7 +867,7 @@ orrb_status orrb_layout_set_tuning(orrb_layout *L, const orrb_tuning *t) {
 
 }  // extern "C"
 
-size_t orrb::render_workspace_bytes(const orrb_layout *L) { return ws_layout(L).total; }
+size_t orrb::render_workspace_bytes(const orrb_layout *L) { return call_ws(L).total; }
 
 // A render call: host checks, then the kernels on `stream`.  With `timing` false it
 // records no kernel-timing events (and so creates none).
@@ -791,11 +881,35 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
         const orrb_status st = check_inputs(L, sc, cam, par);
         if (st != ORRB_OK) return st;
     }
-    const WsLayout w = ws_layout(L);
+    const CallWs cw = call_ws(L);
+    const WsLayout &w = cw.w;
     if (!workspace) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace is NULL");
-    if (workspace_bytes < w.total)
-        return fail(ORRB_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", workspace_bytes, w.total);
+    if (workspace_bytes < cw.total)
+        return fail(ORRB_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", workspace_bytes, cw.total);
     if ((uintptr_t)workspace % 16 != 0) return fail(ORRB_ERR_INVALID_ARGUMENT, "workspace must be 16-byte aligned");
+    if (L->shadow && (!par->light_dir || !par->light_cone || !par->shadow_view || !par->shadow_intr))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "spot lights need light_dir, light_cone, shadow_view and shadow_intr");
+    if (L->shadow) {
+        // shadow frames first: gather each spot light's shadow camera, then render their
+        // depth (no shading) into the shadow maps
+        char *wsb = (char *)workspace;
+        float *cview = (float *)(wsb + cw.cams), *cintr = cview + 12 * L->n_spot, *cnear = cintr + 4 * L->n_spot;
+        ScopedDevice sd(ctx->device);
+        hipError_t e = launch_shadow_cams(L->tab.at<int32_t>(L->o_spot_light), (int)L->n_spot, par->shadow_view,
+                                          par->shadow_intr, cview, cintr, cnear, (hipStream_t)stream);
+        if (e != hipSuccess) return fail(ORRB_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+        const orrb_cameras cs{cview, cintr, cnear};
+        orrb_params ps = *par;
+        ps.exposure = cnear;  // never read: depth only (any n_spot floats)
+        ps.post = nullptr;
+        ps.grain = nullptr;
+        orrb_outputs os{};
+        os.depth = (float *)(wsb + cw.maps);
+        os.stats = out->stats;
+        const orrb_status st = render_impl(ctx, L->shadow, sc, &cs, &ps, &os, wsb + cw.shadow_ws, cw.shadow_ws_bytes,
+                                           stream, timing);
+        if (st != ORRB_OK) return st;
+    }
     RenderArgs a;
     fill_args(ctx, L, sc, cam, par, &a);
     a.frames = L->tab.at<FrameInfo>(L->o_frames);
@@ -824,6 +938,17 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     a.grain = par->grain;
     a.grain_w = par->grain_w;
     a.grain_h = par->grain_h;
+    // shading mode of the frame kernel: depth only when nothing shaded is written
+    a.shade_mode = (!out->rgb && !out->normal && !out->rgb8) ? 2 : L->shadow ? 1 : 0;
+    if (L->shadow) {
+        a.light_dir = par->light_dir;
+        a.light_cone = par->light_cone;
+        a.shadow_view = par->shadow_view;
+        a.shadow_intr = par->shadow_intr;
+        a.spot_slot = L->tab.at<int32_t>(L->o_spot_slot);
+        a.shadow_maps = (const float *)((char *)workspace + cw.maps);
+        a.shadow_res = L->shadow_res;
+    }
     if (out->rgb8 && !out->rgb) return fail(ORRB_ERR_INVALID_ARGUMENT, "rgb8 needs the rgb destination");
     if (out->rgb8 && par->grain && (par->grain_w < 1 || par->grain_h < 1))
         return fail(ORRB_ERR_INVALID_ARGUMENT, "grain texture size %d x %d", par->grain_w, par->grain_h);
@@ -891,6 +1016,7 @@ orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const o
     if ((L->n_objects > 0 && (!gr->albedo || !gr->roughness || !gr->specular)) ||
         (L->n_lights > 0 && (!gr->light_vec || !gr->light_intensity)) || (L->n_frames > 0 && !gr->exposure))
         return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL gradient destination");
+    if (L->n_spot > 0) return fail(ORRB_ERR_UNSUPPORTED, "the shading adjoint does not cover spot lights");
     if (L->max_scene_objects > grad_max_objects())
         return fail(ORRB_ERR_UNSUPPORTED, "a scene has %d objects; the adjoint supports %d", L->max_scene_objects,
                     grad_max_objects());

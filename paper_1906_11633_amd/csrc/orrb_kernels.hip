@@ -38,6 +38,25 @@
 
 namespace orrb {
 
+// Light k of frame f's scene (global light l = fi.light_begin + k) in view space, its
+// type word and, for a spot light, its record in spot[] (the index counts the scene's
+// spot lights before it).
+ORRB_INLINE void frame_light(const RenderArgs &a, int f, const FrameInfo &fi, int k, float4 *light, int *ltype,
+                             SpotLight *spot) {
+    const int l = fi.light_begin + k;
+    const float *V = a.view + 12 * (int64_t)f;
+    const int t = a.light_type[l];
+    light[k] = view_light(V, a.light_vec + 3 * (int64_t)l, t == 2 ? 0 : t, a.light_intensity[l]);
+    if (t == 2) {
+        int idx = 0;
+        for (int j = 0; j < k; ++j) idx += a.light_type[fi.light_begin + j] == 2;
+        spot[idx] = spot_setup(a, V, l);
+        ltype[k] = 2 | (idx << 4);
+    } else {
+        ltype[k] = t;
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // tiled path: k_vertex
 // ------------------------------------------------------------------------------------
@@ -138,6 +157,7 @@ struct TileLds {
     float ol_R[kBlock][9];
     float4 light[kMaxLights];
     int light_type[kMaxLights];
+    SpotLight spot[kMaxSpots];
     int misc[16];  // [0] bin count, [1] next item, [4..8) scan, [8..12) wave counts
 };
 
@@ -216,11 +236,7 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
 
     for (int p = tid; p < TW * TH; p += kBlock) L.vis[p] = kEmptyKey;
     if (tid == 0) L.misc[0] = 0;
-    if (tid < fi.n_lights) {
-        const int l = fi.light_begin + tid;
-        L.light[tid] = view_light(a.view + 12 * (int64_t)f, a.light_vec + 3 * (int64_t)l, a.light_type[l], a.light_intensity[l]);
-        L.light_type[tid] = a.light_type[l];
-    }
+    if (tid < fi.n_lights) frame_light(a, f, fi, tid, L.light, L.light_type, L.spot);
     __syncthreads();
 
     // ---- visibility: object cull, triangle set-up into the LDS bin, raster ----
@@ -379,9 +395,10 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
             const int4 tv = a.mesh_tri[mtb + (tri - tbase)];
             // the winning triangle is front-facing: same vertex order as in set-up
             const int4 pa = a.vtx_pos[vb + tv.x], pb = a.vtx_pos[vb + tv.z], pc = a.vtx_pos[vb + tv.y];
-            o = shade_pixel(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, __int_as_float(pa.z), __int_as_float(pb.z),
+            o = shade_pixel<true>(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, __int_as_float(pa.z), __int_as_float(pb.z),
                             __int_as_float(pc.z), a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], R,
-                            i, j, z, cam, L.light, L.light_type, fi.n_lights, object_material(a, obj));
+                            i, j, z, cam, L.light, L.light_type, fi.n_lights, object_material(a, obj), L.spot,
+                            a.shadow_maps, a.shadow_res);
             segv = a.seg[obj];
             triv = tri;
         }
@@ -516,6 +533,7 @@ struct FrameLds {
     Material o_mat[kFOMax];
     float4 light[kMaxLights];
     int light_type[kMaxLights];
+    SpotLight spot[kMaxSpots];
     int misc[8];  // [0] next tile with entries, [1] bin overflow, [2] total entries, [3] survivors,
                   // [4] tiles with entries
     // Background tiles (no triangle touches them) handed from the compute waves to the
@@ -1133,7 +1151,7 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
 
 // One frame rendered by the compute waves (phases 0-4 below); true if the workgroup has
 // stopped.  G selects where the scene's data live (FrameMem).
-template <bool AUX, bool G>
+template <bool AUX, bool G, int SHADE>
 ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int seq, int &gen) {
     const FrameMem<G> F = frame_mem<G>(a, S);
     // Thread indices made opaque per frame: address arithmetic derived from them is
@@ -1167,9 +1185,14 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
         if ((q & 3) != 3) F.o_R[k][(q >> 2) * 3 + (q & 3)] = (float)m;
     }
     if (tid < fi.n_lights) {
-        const int l = fi.light_begin + tid;
-        S.light[tid] = view_light(a.view + 12 * (int64_t)f, a.light_vec + 3 * (int64_t)l, a.light_type[l], a.light_intensity[l]);
-        S.light_type[tid] = a.light_type[l];
+        if constexpr (SHADE == 1) {
+            frame_light(a, f, fi, tid, S.light, S.light_type, S.spot);
+        } else if constexpr (SHADE == 0) {
+            const int l = fi.light_begin + tid;
+            S.light[tid] = view_light(a.view + 12 * (int64_t)f, a.light_vec + 3 * (int64_t)l, a.light_type[l],
+                                      a.light_intensity[l]);
+            S.light_type[tid] = a.light_type[l];
+        }
     }
     for (int t = tid; t <= n_tiles; t += kFCT) S.cnt[t] = 0;
     if (tid < 8) S.misc[tid] = 0;
@@ -1469,9 +1492,15 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
                 const int4 tv = frame_tri(a, F, k, tri);
                 const int vb = F.o_vbase[k], mvb = F.o_mvb[k];
                 const int va = vb + tv.x, vbb = vb + tv.z, vc = vb + tv.y;  // positive-area order
-                o[h] = shade_pixel(F.X[va], F.Y[va], F.X[vbb], F.Y[vbb], F.X[vc], F.Y[vc], F.iw[va], F.iw[vbb], F.iw[vc],
-                                   a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], F.o_R[k], pi, pj,
-                                   z, cam, S.light, S.light_type, fi.n_lights, F.o_mat[k]);
+                if constexpr (SHADE == 2) {  // depth only (shadow maps): no shading
+                    o[h] = PixelOut{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                } else {
+                    o[h] = shade_pixel<SHADE == 1>(F.X[va], F.Y[va], F.X[vbb], F.Y[vbb], F.X[vc], F.Y[vc], F.iw[va],
+                                                   F.iw[vbb], F.iw[vc], a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z],
+                                                   a.mesh_nrm[mvb + tv.y], F.o_R[k], pi, pj, z, cam, S.light,
+                                                   S.light_type, fi.n_lights, F.o_mat[k], S.spot, a.shadow_maps,
+                                                   a.shadow_res);
+                }
                 kk[h] = key & ~0xffff0000ull;
                 sg[h] = F.o_seg[k];
                 pl[h] = p;
@@ -1496,7 +1525,7 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
 // AUX: the transparency channel and the Tracker records are written (a separate
 // instantiation, so the plain four-channel kernel carries none of that code).  MIXED:
 // some frames keep their scene data in global scratch (frame_mem).
-template <bool AUX, bool MIXED>
+template <bool AUX, bool MIXED, int SHADE>
 __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     __shared__ FrameLds S;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -1512,8 +1541,8 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
         for (int item = blockIdx.x, seq = 0; item < a.n_fitems; item += gridDim.x) {
             const int f = a.fitems[item];
             if (f < 0) continue;  // this workgroup's schedule is shorter
-            const bool stop = MIXED && a.frames[f].mode != 0 ? frame_render<AUX, true>(a, S, item, seq, gen)
-                                                             : frame_render<AUX, false>(a, S, item, seq, gen);
+            const bool stop = MIXED && a.frames[f].mode != 0 ? frame_render<AUX, true, SHADE>(a, S, item, seq, gen)
+                                                             : frame_render<AUX, false, SHADE>(a, S, item, seq, gen);
             if (stop) break;
             ++seq;
         }
@@ -1537,6 +1566,28 @@ size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap) {
     const size_t rest = sizeof(int) * (7 * kBlock + 1) + sizeof(float) * 9 * kBlock + sizeof(float4) * kMaxLights +
                         sizeof(int) * (kMaxLights + 16);
     return vis + bin + rest;
+}
+
+// Shadow cameras of the spot lights gathered per shadow frame (slot k <- light
+// spot_light[k]), with the shadow frames' near plane (0.01 m).
+__global__ __launch_bounds__(kBlock) void k_shadow_cams(const int32_t *spot_light, int n, const float *sview,
+                                                         const float *sintr, float *view, float *intr, float *nearp) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int64_t l = spot_light[k];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) view[12 * (int64_t)k + q] = sview[12 * l + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) intr[4 * (int64_t)k + q] = sintr[4 * l + q];
+    nearp[k] = 0.01f;
+}
+
+hipError_t launch_shadow_cams(const int32_t *spot_light, int n_spot, const float *shadow_view, const float *shadow_intr,
+                              float *view, float *intr, float *nearp, hipStream_t stream) {
+    if (n_spot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_shadow_cams, dim3((n_spot + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, spot_light, n_spot,
+                       shadow_view, shadow_intr, view, intr, nearp);
+    return hipGetLastError();
 }
 
 hipError_t launch_vertex(const RenderArgs &a, hipStream_t stream) {
@@ -1586,14 +1637,25 @@ hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu) {
     if (a.n_fitems <= 0 || a.f_grid <= 0) return hipSuccess;
     const int grid = a.f_grid;  // the schedule's grid (at most the CU count)
     const bool aux = a.out_alpha || a.out_track, mixed = a.fscratch != nullptr;
-    if (aux && mixed)
-        hipLaunchKernelGGL((k_frame<true, true>), dim3(grid), dim3(kFT), 0, stream, a);
-    else if (aux)
-        hipLaunchKernelGGL((k_frame<true, false>), dim3(grid), dim3(kFT), 0, stream, a);
-    else if (mixed)
-        hipLaunchKernelGGL((k_frame<false, true>), dim3(grid), dim3(kFT), 0, stream, a);
-    else
-        hipLaunchKernelGGL((k_frame<false, false>), dim3(grid), dim3(kFT), 0, stream, a);
+    const dim3 g(grid), b(kFT);
+#define ORRB_FRAME(AUX_, MIXED_, SHADE_) hipLaunchKernelGGL((k_frame<AUX_, MIXED_, SHADE_>), g, b, 0, stream, a)
+    switch (a.shade_mode) {
+        case 2:  // depth only (shadow maps); no auxiliary outputs
+            if (mixed) ORRB_FRAME(false, true, 2); else ORRB_FRAME(false, false, 2);
+            break;
+        case 1:  // spot lights with shadow maps
+            if (aux && mixed) ORRB_FRAME(true, true, 1);
+            else if (aux) ORRB_FRAME(true, false, 1);
+            else if (mixed) ORRB_FRAME(false, true, 1);
+            else ORRB_FRAME(false, false, 1);
+            break;
+        default:
+            if (aux && mixed) ORRB_FRAME(true, true, 0);
+            else if (aux) ORRB_FRAME(true, false, 0);
+            else if (mixed) ORRB_FRAME(false, true, 0);
+            else ORRB_FRAME(false, false, 0);
+    }
+#undef ORRB_FRAME
     return hipGetLastError();
 }
 

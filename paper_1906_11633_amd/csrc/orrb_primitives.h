@@ -201,6 +201,85 @@ struct CamF {
     float cx, cy, ifx, ify, expo;
 };
 
+// A spot light (light type 2) in a frame's view space, with its shadow map: unit
+// axis, cosines of the inner and outer half-angles, T = shadow camera o view^-1 (view
+// space -> shadow camera space, row-major 3x4), the shadow camera's intrinsics and the
+// map's slot.  A light's type word holds 2 | (index of this record << 4).
+struct SpotLight {
+    float ax, ay, az;
+    float cin, cout;
+    float T[12];
+    float fx, fy, cx, cy;
+    int slot;
+};
+constexpr float kShadowBias = 0.02f;  // lit if (1 - bias) w <= the map's depth
+
+// The view-space record of global spot light l for a frame with world->camera view V
+// (fp32 inputs, FP64 arithmetic, rounded once).
+ORRB_INLINE SpotLight spot_setup(const RenderArgs &a, const float *V, int l) {
+    SpotLight r;
+    const float *d = a.light_dir + 3 * (int64_t)l;
+    double ax[3];
+    for (int k = 0; k < 3; ++k)
+        ax[k] = (double)V[k * 4 + 0] * d[0] + (double)V[k * 4 + 1] * d[1] + (double)V[k * 4 + 2] * d[2];
+    const double inv = 1.0 / sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    r.ax = (float)(ax[0] * inv);
+    r.ay = (float)(ax[1] * inv);
+    r.az = (float)(ax[2] * inv);
+    r.cin = a.light_cone[2 * (int64_t)l];
+    r.cout = a.light_cone[2 * (int64_t)l + 1];
+    // V^-1 of the rigid view [R | t] is [R^T | -R^T t]
+    double Vi[12];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) Vi[i * 4 + j] = V[j * 4 + i];
+        Vi[i * 4 + 3] = -((double)V[0 * 4 + i] * V[3] + (double)V[1 * 4 + i] * V[7] + (double)V[2 * 4 + i] * V[11]);
+    }
+    const float *Sv = a.shadow_view + 12 * (int64_t)l;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double t = (double)Sv[i * 4 + 0] * Vi[0 * 4 + j] + (double)Sv[i * 4 + 1] * Vi[1 * 4 + j] +
+                       (double)Sv[i * 4 + 2] * Vi[2 * 4 + j];
+            if (j == 3) t += Sv[i * 4 + 3];
+            r.T[i * 4 + j] = (float)t;
+        }
+    const float *K = a.shadow_intr + 4 * (int64_t)l;
+    r.fx = K[0];
+    r.fy = K[1];
+    r.cx = K[2];
+    r.cy = K[3];
+    r.slot = a.spot_slot[l];
+    return r;
+}
+
+// Fraction of the 3 x 3 shadow-map texels around view-space point p's texel that see
+// it (percentage-closer filtering; empty and off-map texels count as lit, a point not
+// in front of the shadow camera is lit).
+ORRB_INLINE float shadow_pcf(const SpotLight &sp, const float *maps, int N, float px, float py, float pz) {
+#pragma clang fp contract(off)
+    const float qx = sp.T[0] * px + sp.T[1] * py + sp.T[2] * pz + sp.T[3];
+    const float qy = sp.T[4] * px + sp.T[5] * py + sp.T[6] * pz + sp.T[7];
+    const float qz = sp.T[8] * px + sp.T[9] * py + sp.T[10] * pz + sp.T[11];
+    const float w = -qz;
+    if (!(w > 0.f)) return 1.0f;
+    const float u = sp.fx * (qx / w) + sp.cx, v = -sp.fy * (qy / w) + sp.cy;
+    const float fu = floorf(u), fv = floorf(v);
+    if (!(fu > -2.f && fu < (float)N + 1.f && fv > -2.f && fv < (float)N + 1.f)) return 1.0f;  // every texel off the map
+    const int ti = (int)fu, tj = (int)fv;
+    const float wb = (1.0f - kShadowBias) * w;
+    const float *map = maps + (int64_t)sp.slot * N * N;
+    int lit = 0;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+        for (int di = -1; di <= 1; ++di) {
+            const int x = ti + di, y = tj + dj;
+            float z = 0.f;
+            if (x >= 0 && y >= 0 && x < N && y < N) z = map[(int64_t)y * N + x];
+            lit += (z == 0.f || wb <= z) ? 1 : 0;
+        }
+    return (float)lit * (1.0f / 9.0f);
+}
+
 struct PixelOut {
     float r0, r1, r2, n0, n1, n2;
 };
@@ -238,9 +317,11 @@ ORRB_INLINE float spec_pow(float u, float m) {
 // Shade the covered pixel (i, j) at eye depth z of the positive-area triangle a, b, c:
 // perspective-correct smooth normal from the unit object-space vertex normals and R,
 // then exposure * sum over lights of A * max(0, n.l) * (albedo + k_s * max(0, n.h)^m).
+template <bool SPOT = false>
 ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc, float iwa, float iwb, float iwc,
                                  float4 na4, float4 nb4, float4 nc4, const float *R, int i, int j, float z,
-                                 const CamF &cam, const float4 *light, const int *ltype, int nl, const Material &m) {
+                                 const CamF &cam, const float4 *light, const int *ltype, int nl, const Material &m,
+                                 const SpotLight *spot = nullptr, const float *maps = nullptr, int shadow_res = 0) {
 #pragma clang fp contract(off)
     const Edges e = edge_eval(xa, ya, xb, yb, xc, yc, (i << 8) + 128, (j << 8) + 128, extent_flag(xa, ya, xb, yb, xc, yc));
     // perspective-correct weights are proportional to E_k / w_k
@@ -258,9 +339,10 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
     float r0 = 0.f, r1 = 0.f, r2 = 0.f;
     for (int l = 0; l < nl; ++l) {
         const float4 Lq = light[l];
+        const int lt = ltype[l];
         float3 ld;
         float A;
-        if (ltype[l] == 0) {
+        if (lt == 0 || (SPOT && (lt & 15) == 2)) {
             const float3 d = f3(Lq.x - pp.x, Lq.y - pp.y, Lq.z - pp.z);
             const float D = dot3(d, d);
             const float dinv = rsqrtf(D);
@@ -272,6 +354,14 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
         }
         const float ndl = dot3(n, ld);
         if (ndl <= 0.f) continue;
+        if (SPOT && (lt & 15) == 2) {  // cone (smoothstep) and filtered shadow
+            const SpotLight &sp = spot[lt >> 4];
+            const float c = -(ld.x * sp.ax + ld.y * sp.ay + ld.z * sp.az);
+            const float t = fminf(fmaxf((c - sp.cout) / (sp.cin - sp.cout), 0.f), 1.f);
+            const float cone = t * t * (3.0f - 2.0f * t);
+            if (cone <= 0.f) continue;
+            A = A * cone * shadow_pcf(sp, maps, shadow_res, pp.x, pp.y, pp.z);
+        }
         float s = 0.f;
         const float3 hh = f3(ld.x + v.x, ld.y + v.y, ld.z + v.z);
         const float H2 = dot3(hh, hh);

@@ -99,7 +99,8 @@ class Layout:
         a = self._arrays
         p = lambda x: x.ctypes.data_as(C.c_void_p)
         desc = L.LayoutDesc(int(a["sob"].shape[0] - 1), p(a["sob"]), p(a["om"]), p(a["slb"]), p(a["lt"]),
-                            int(a["fs"].shape[0]), p(a["fs"]), p(a["w"]), p(a["h"]))
+                            int(a["fs"].shape[0]), p(a["fs"]), p(a["w"]), p(a["h"]),
+                            int(getattr(batch, "shadow_res", 0) or 0))
         h = C.c_void_p()
         L.check(ctx.lib.orrb_layout_create(ctx.handle, C.byref(desc), C.byref(h)))
         self.handle = h
@@ -150,6 +151,10 @@ def device_state(batch, device="cuda") -> Dict[str, torch.Tensor]:
     grain = getattr(batch, "grain", None)
     if grain is not None:
         out["grain"] = torch.from_numpy(np.ascontiguousarray(grain, np.float32)).to(device)
+    for k in ("light_dir", "light_cone", "shadow_view", "shadow_intr"):  # spot lights
+        v = getattr(batch, k, None)
+        if v is not None:
+            out[k] = torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(device)
     return out
 
 
@@ -234,7 +239,9 @@ def _params(state) -> L.Params:
     grain = s.get("grain")
     gh, gw = (int(grain.shape[-2]), int(grain.shape[-1])) if grain is not None else (0, 0)
     return L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
-                    _ptr(s["light_intensity"]), _ptr(s["exposure"]), _ptr(s.get("post")), _ptr(grain), gw, gh)
+                    _ptr(s["light_intensity"]), _ptr(s["exposure"]), _ptr(s.get("post")), _ptr(grain), gw, gh,
+                    _ptr(s.get("light_dir")), _ptr(s.get("light_cone")), _ptr(s.get("shadow_view")),
+                    _ptr(s.get("shadow_intr")))
 
 
 def _structs(state, out):
