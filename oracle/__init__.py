@@ -48,7 +48,7 @@ def open_library(path: str):
     """Open a compiled oracle library and declare its entry points."""
     lib = C.CDLL(path)
     P = C.c_void_p
-    inputs = [P] * 17 + [C.c_int32] + [P] * 8 + [P] * 6 + [C.c_int32]
+    inputs = [P] * 17 + [C.c_int32] + [P] * 8 + [P] * 6 + [C.c_int32] + [P] * 6
     lib.oracle_render.argtypes = inputs + [P] * 9 + [C.c_int32]
     lib.oracle_render.restype = C.c_int
     lib.oracle_shade_grad.argtypes = inputs + [C.c_int32, P, P, P, P, P, P, P, P, P, P, C.c_int32]
@@ -126,6 +126,28 @@ class _Packed:
         self.shadow_slot = np.full(nl, -1, np.int32)
         self.shadow_slot[self.light_type == 2] = np.arange(int((self.light_type == 2).sum()), dtype=np.int32)
         self.shadow_maps = np.zeros(max(1, int((self.light_type == 2).sum())) * max(1, self.shadow_res) ** 2)
+        # materials with pattern textures and emission (None when the batch has none)
+        uvs = [getattr(m, "uv", None) for m in meshes]
+        self.mesh_uv = (np.ascontiguousarray(np.concatenate(
+            [np.asarray(u, np.float32) if u is not None else np.zeros((m.pos.shape[0], 2), np.float32)
+             for u, m in zip(uvs, meshes)]), np.float64) if any(u is not None for u in uvs) else None)
+        texs = getattr(b, "textures", None)
+        ot = getattr(b, "object_texture", None)
+        if texs is not None and ot is not None:
+            info, off = [], 0
+            for t in texs:
+                H, W = t.shape[0], t.shape[1]
+                info.append((off, W, H))
+                off += W * H
+            self.tex_texels = np.ascontiguousarray(np.concatenate(
+                [np.asarray(t, np.float32).reshape(-1, 3) for t in texs]), np.float64)
+            self.tex_info = np.ascontiguousarray(info, np.int64)
+            self.obj_tex = np.ascontiguousarray(ot, np.int32)
+            self.obj_txf = p64(np.asarray(b.tex_xform, np.float32))
+        else:
+            self.tex_texels = self.tex_info = self.obj_tex = self.obj_txf = None
+        em = getattr(b, "emission", None)
+        self.emission = None if em is None else p64(np.asarray(em, np.float32))
 
     def args(self):
         return [_ptr(self.mesh_vbegin), _ptr(self.mesh_tbegin), _ptr(self.mesh_pos), _ptr(self.mesh_nrm),
@@ -137,7 +159,8 @@ class _Packed:
                 _ptr(self.intr), _ptr(self.near), _ptr(self.exposure), _ptr(self.width),
                 _ptr(self.height), _ptr(self.pixel_offset), _ptr(self.light_dir), _ptr(self.light_cone),
                 _ptr(self.shadow_view), _ptr(self.shadow_intr), _ptr(self.shadow_maps), _ptr(self.shadow_slot),
-                self.shadow_res]
+                self.shadow_res, _ptr(self.mesh_uv), _ptr(self.tex_texels), _ptr(self.tex_info), _ptr(self.obj_tex),
+                _ptr(self.obj_txf), _ptr(self.emission)]
 
 
 def _pack(batch):
@@ -231,6 +254,8 @@ def shade_grad(batch, target_rgb=None, pixel_weight=None, threads: int = 0, dl_d
     loss = np.zeros(1)
     if pk.has_spot:
         raise ValueError("the oracle's adjoint does not cover spot lights")
+    if pk.obj_tex is not None or pk.emission is not None:
+        raise ValueError("the oracle's adjoint does not cover textured or emissive materials")
     rc = _load().oracle_shade_grad(*pk.args(), pk.n_scenes, _ptr(target), _ptr(wmask), _ptr(upstream),
                                    _ptr(loss), _ptr(g["albedo"]), _ptr(g["roughness"]), _ptr(g["specular"]),
                                    _ptr(g["light_vec"]), _ptr(g["light_intensity"]), _ptr(g["exposure"]),

@@ -59,6 +59,14 @@ typedef struct {
     const double *light_dir, *light_cone, *shadow_view, *shadow_intr, *shadow_maps;
     const int32_t *shadow_slot;
     int32_t shadow_res;
+    /* materials with pattern textures and emission (NULL when unused): per-vertex UVs
+     * of the mesh pool, the textures (RGB texels, row-major, tex_info[3k] = first texel,
+     * width, height), each object's texture (-1 none) and UV transform (su, sv, ou, ov),
+     * and its emissive power */
+    const double *mesh_uv, *tex_texels;
+    const int64_t *tex_info;
+    const int32_t *obj_tex;
+    const double *obj_txf, *emission;
 } Inputs;
 
 /* per-vertex results of the vertex stage for one (frame, object) */
@@ -67,6 +75,7 @@ typedef struct {
     int64_t X, Y;    /* snapped position, 1/256 px */
     double w;        /* eye depth */
     double n[3];     /* unit view-space normal */
+    double uv[2];    /* texture coordinates (0 without UVs) */
 } Vert;
 
 /* per-pixel visibility record */
@@ -134,6 +143,8 @@ static void vertex_stage(const Inputs *in, int f, int o, Vert *out) {
         }
         for (int i = 0; i < 3; i++) q->n[i] = M[i * 4 + 0] * nn[0] + M[i * 4 + 1] * nn[1] + M[i * 4 + 2] * nn[2];
         normalize3(q->n);
+        q->uv[0] = in->mesh_uv ? in->mesh_uv[2 * (v0 + v)] : 0.0;
+        q->uv[1] = in->mesh_uv ? in->mesh_uv[2 * (v0 + v) + 1] : 0.0;
     }
 }
 
@@ -250,6 +261,7 @@ typedef struct {
     double n[3];    /* unit view-space normal */
     double p[3];    /* view-space position */
     double v[3];    /* unit direction to the eye */
+    double uv[2];   /* perspective-correct texture coordinates */
 } Frag;
 
 static void fragment(const Inputs *in, int f, Vert **vt_of, const Pix *q, int i, int j, Frag *fr) {
@@ -268,6 +280,7 @@ static void fragment(const Inputs *in, int f, Vert **vt_of, const Pix *q, int i,
     double be0 = z * b0 / a->w, be1 = z * b1 / b->w, be2 = z * b2 / c->w;
     for (int k = 0; k < 3; k++) fr->n[k] = be0 * a->n[k] + be1 * b->n[k] + be2 * c->n[k];
     normalize3(fr->n);
+    for (int k = 0; k < 2; k++) fr->uv[k] = be0 * a->uv[k] + be1 * b->uv[k] + be2 * c->uv[k];
     const double *K = in->intr + 4 * (int64_t)f;
     fr->z = z;
     fr->p[0] = z * ((i + 0.5 - K[2]) / K[0]);
@@ -275,6 +288,34 @@ static void fragment(const Inputs *in, int f, Vert **vt_of, const Pix *q, int i,
     fr->p[2] = -z;
     double pl = sqrt(dot3(fr->p, fr->p));
     for (int k = 0; k < 3; k++) fr->v[k] = -fr->p[k] / pl;
+}
+
+/* Bilinear sample of texture t at (u, v) with repeat addressing: texel (i, j) is
+ * centred at ((i + 1/2) / W, (j + 1/2) / H), row j = 0 first. */
+static void tex_sample(const Inputs *in, int t, double u, double v, double *rgb) {
+    int64_t off = in->tex_info[3 * (int64_t)t], W = in->tex_info[3 * (int64_t)t + 1], H = in->tex_info[3 * (int64_t)t + 2];
+    double x = u * (double)W - 0.5, y = v * (double)H - 0.5;
+    double fx = floor(x), fy = floor(y), ax = x - fx, ay = y - fy;
+    int64_t i0 = (int64_t)fmod(fx, (double)W), j0 = (int64_t)fmod(fy, (double)H);
+    if (i0 < 0) i0 += W;
+    if (j0 < 0) j0 += H;
+    int64_t i1 = (i0 + 1) % W, j1 = (j0 + 1) % H;
+    const double *T = in->tex_texels + 3 * off;
+    for (int c = 0; c < 3; c++)
+        rgb[c] = (1 - ay) * ((1 - ax) * T[3 * (j0 * W + i0) + c] + ax * T[3 * (j0 * W + i1) + c]) +
+                 ay * ((1 - ax) * T[3 * (j1 * W + i0) + c] + ax * T[3 * (j1 * W + i1) + c]);
+}
+
+/* The albedo at a fragment of object o: the tint times its pattern texture at the
+ * transformed UV (u su + ou, v sv + ov), if it has one. */
+static void fragment_albedo(const Inputs *in, int o, const Frag *fr, double *alb) {
+    for (int c = 0; c < 3; c++) alb[c] = in->albedo[3 * (int64_t)o + c];
+    int t = in->obj_tex ? in->obj_tex[o] : -1;
+    if (t < 0) return;
+    const double *x = in->obj_txf + 4 * (int64_t)o;
+    double rgb[3];
+    tex_sample(in, t, fr->uv[0] * x[0] + x[2], fr->uv[1] * x[1] + x[3], rgb);
+    for (int c = 0; c < 3; c++) alb[c] *= rgb[c];
 }
 
 /* A light expressed in the frame's view space. */
@@ -496,8 +537,10 @@ static void render_frame(const Inputs *in, int f, double *rgb, double *depth, do
             fragment(in, f, fw.vt_of, q, i, j, &fr);
             int o = q->obj;
             double r = in->roughness[o], ks = in->specular[o], mexp = 2.0 / (r * r) - 2.0;
-            const double *alb = in->albedo + 3 * (int64_t)o;
-            double U[3] = {0, 0, 0};
+            double alb[3];
+            fragment_albedo(in, o, &fr, alb);
+            double E = in->emission ? in->emission[o] : 0.0;
+            double U[3] = {E * alb[0], E * alb[1], E * alb[2]};
             for (int l = 0; l < nL; l++) {
                 LTerm t;
                 light_term(L + l, &fr, mexp, &t, in->shadow_res);
@@ -531,14 +574,15 @@ static void render_frame(const Inputs *in, int f, double *rgb, double *depth, do
         const double *intr, const double *near_, const double *exposure, const int32_t *width,                \
         const int32_t *height, const int64_t *pixel_offset, const double *light_dir, const double *light_cone,      \
         const double *shadow_view, const double *shadow_intr, const double *shadow_maps,                        \
-        const int32_t *shadow_slot, int32_t shadow_res
+        const int32_t *shadow_slot, int32_t shadow_res, const double *mesh_uv, const double *tex_texels,        \
+        const int64_t *tex_info, const int32_t *obj_tex, const double *obj_txf, const double *emission
 
 #define FILL_INPUTS(in)                                                                                         \
     Inputs in = {mesh_vbegin, mesh_tbegin, mesh_pos, mesh_nrm, mesh_idx, scene_object_begin, object_mesh,      \
                  object_seg, object_pose, object_visible, albedo, roughness, specular, scene_light_begin,      \
                  light_type, light_vec, light_intensity, frame_scene, width, height, view, intr, near_,        \
                  exposure, pixel_offset, light_dir, light_cone, shadow_view, shadow_intr, shadow_maps,         \
-                 shadow_slot, shadow_res}
+                 shadow_slot, shadow_res, mesh_uv, tex_texels, tex_info, obj_tex, obj_txf, emission}
 
 static void set_threads(int n_threads) {
 #ifdef _OPENMP
@@ -582,6 +626,7 @@ int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const 
     FILL_INPUTS(in);
     for (int64_t l = 0; l < scene_light_begin[n_scenes]; l++)
         if (light_type[l] == 2) return 2; /* spot lights: no adjoint (shadow visibility is not differentiated) */
+    if (obj_tex || emission) return 2;   /* textured or emissive materials: no adjoint */
     int err = 0;
     double *scene_loss = (double *)calloc((size_t)n_scenes + 1, sizeof(double));
     if (!scene_loss) return 1;

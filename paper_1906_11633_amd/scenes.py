@@ -45,6 +45,7 @@ class Mesh:
     pos: np.ndarray  # f32 [V,3]
     nrm: np.ndarray  # f32 [V,3]
     idx: np.ndarray  # i32 [T,3], counter-clockwise seen from outside
+    uv: Optional[np.ndarray] = None  # f32 [V,2] texture coordinates
 
     @property
     def n_verts(self) -> int:
@@ -67,6 +68,7 @@ def capsule_mesh(radius: float, length: float, slices: int = 16, stacks: int = 8
     phis = 2.0 * np.pi * np.arange(S) / S
     pos = [(0.0, 0.0, h + r)]
     nrm = [(0.0, 0.0, 1.0)]
+    uv = [(0.0, 0.0)]
     rings = []
     # top hemisphere rings, polar angle from +z
     for k in range(1, T + 1):
@@ -77,6 +79,7 @@ def capsule_mesh(radius: float, length: float, slices: int = 16, stacks: int = 8
             ring.append(len(pos))
             pos.append((r * d[0], r * d[1], h + r * d[2]))
             nrm.append(d)
+            uv.append((ph / (2 * np.pi), (r - r * d[2]) / (2 * h + 2 * r)))
         rings.append(ring)
     # bottom hemisphere rings, from the equator down
     for k in range(T, 0, -1):
@@ -87,10 +90,12 @@ def capsule_mesh(radius: float, length: float, slices: int = 16, stacks: int = 8
             ring.append(len(pos))
             pos.append((r * d[0], r * d[1], -h + r * d[2]))
             nrm.append(d)
+            uv.append((ph / (2 * np.pi), (2 * h + r - r * d[2]) / (2 * h + 2 * r)))
         rings.append(ring)
     bottom = len(pos)
     pos.append((0.0, 0.0, -h - r))
     nrm.append((0.0, 0.0, -1.0))
+    uv.append((0.0, 1.0))
     tris = []
     for s in range(S):
         s1 = (s + 1) % S
@@ -105,7 +110,8 @@ def capsule_mesh(radius: float, length: float, slices: int = 16, stacks: int = 8
     for s in range(S):
         s1 = (s + 1) % S
         tris.append((last[s], bottom, last[s1]))
-    return Mesh(np.asarray(pos, np.float32), np.asarray(nrm, np.float32), np.asarray(tris, np.int32))
+    return Mesh(np.asarray(pos, np.float32), np.asarray(nrm, np.float32), np.asarray(tris, np.int32),
+                np.asarray(uv, np.float32))
 
 
 _BOX_FACES = (  # (N, U, V) with U x V = N
@@ -122,7 +128,7 @@ def box_mesh(n: int = 1) -> Mesh:
     """Unit cube [-1/2, 1/2]^3, each face split into n x n quads (12 n^2 triangles,
     6 (n+1)^2 vertices), with flat per-face normals."""
     n = int(n)
-    pos, nrm, tris = [], [], []
+    pos, nrm, tris, uv = [], [], [], []
     for N, U, V in _BOX_FACES:
         N, U, V = np.array(N, float), np.array(U, float), np.array(V, float)
         base = len(pos)
@@ -131,13 +137,15 @@ def box_mesh(n: int = 1) -> Mesh:
                 p = (i / n - 0.5) * U + (j / n - 0.5) * V + 0.5 * N
                 pos.append(p)
                 nrm.append(N)
+                uv.append((i / n, j / n))
         for j in range(n):
             for i in range(n):
                 v00 = base + j * (n + 1) + i
                 v10, v01, v11 = v00 + 1, v00 + (n + 1), v00 + (n + 1) + 1
                 tris.append((v00, v10, v11))
                 tris.append((v00, v11, v01))
-    return Mesh(np.asarray(pos, np.float32), np.asarray(nrm, np.float32), np.asarray(tris, np.int32))
+    return Mesh(np.asarray(pos, np.float32), np.asarray(nrm, np.float32), np.asarray(tris, np.int32),
+                np.asarray(uv, np.float32))
 
 
 def plane_mesh(nx: int, ny: int, sx: float = 1.0, sy: float = 1.0) -> Mesh:
@@ -157,7 +165,8 @@ def plane_mesh(nx: int, ny: int, sx: float = 1.0, sy: float = 1.0) -> Mesh:
     pos = np.asarray(pos, np.float32)
     nrm = np.zeros_like(pos)
     nrm[:, 2] = 1.0
-    return Mesh(pos, nrm, np.asarray(tris, np.int32))
+    uv = np.stack([pos[:, 0] / sx + 0.5, pos[:, 1] / sy + 0.5], 1).astype(np.float32)
+    return Mesh(pos, nrm, np.asarray(tris, np.int32), uv)
 
 
 def triangle_mesh(p0, p1, p2) -> Mesh:
@@ -297,6 +306,13 @@ class Batch:
     shadow_view: Optional[np.ndarray] = None  # f32 [L, 3, 4]
     shadow_intr: Optional[np.ndarray] = None  # f32 [L, 4]
     shadow_res: int = 0
+    # materials with pattern textures and emission, optional: the resident texture pool
+    # (RGB [H, W, 3] arrays), each object's texture (-1 none), its UV transform (su, sv,
+    # ou, ov) and its emissive power
+    textures: Optional[list] = None
+    object_texture: Optional[np.ndarray] = None  # i32 [O]
+    tex_xform: Optional[np.ndarray] = None       # f32 [O, 4]
+    emission: Optional[np.ndarray] = None        # f32 [O]
 
     @property
     def n_scenes(self) -> int:
@@ -369,7 +385,11 @@ class Batch:
             light_dir=None if self.light_dir is None else self.light_dir[lights],
             light_cone=None if self.light_cone is None else self.light_cone[lights],
             shadow_view=None if self.shadow_view is None else self.shadow_view[lights],
-            shadow_intr=None if self.shadow_intr is None else self.shadow_intr[lights], shadow_res=self.shadow_res)
+            shadow_intr=None if self.shadow_intr is None else self.shadow_intr[lights], shadow_res=self.shadow_res,
+            textures=self.textures,
+            object_texture=None if self.object_texture is None else self.object_texture[objs],
+            tex_xform=None if self.tex_xform is None else self.tex_xform[objs],
+            emission=None if self.emission is None else self.emission[objs])
 
     def replace(self, **kw) -> "Batch":
         d = dict(self.__dict__)
@@ -633,6 +653,80 @@ def with_postprocessing(batch: Batch, seed: int = 0) -> Batch:
     """The batch with randomized post-processing parameters and grain texture."""
     post, grain = postprocess_params(seed, batch.n_frames, batch.frame_scene)
     return batch.replace(post=post, grain=grain)
+
+
+# ----------------------------------------------------------------------------------
+# materials: pattern textures (MaterialRandomizer) and the fixed-hue HSV sampler
+# (FixedHueMaterialRandomizer)
+# ----------------------------------------------------------------------------------
+
+
+def hsv_to_rgb(h, s, v) -> np.ndarray:
+    """HSV (hue in turns, [0, 1)) to RGB, the hexcone model (Smith 1978)."""
+    h = float(h) % 1.0
+    i = int(math.floor(h * 6.0)) % 6
+    f = h * 6.0 - math.floor(h * 6.0)
+    p, q, t = v * (1 - s), v * (1 - f * s), v * (1 - (1 - f) * s)
+    return np.array([(v, t, p), (q, v, p), (p, v, t), (p, q, v), (t, p, v), (v, p, q)][i], float)
+
+
+def fixed_hue_material(rng: np.random.Generator, base_hsv, radius, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                       metallic=(0.0, 1.0), glossiness=(0.0, 0.95), emissive_prob=0.0, emissive_power=(0.0, 0.0)):
+    """A material near calibrated values: hue, saturation and value each moved by
+    U[-radius, radius] around base_hsv (hue wrapping around the colour circle) and
+    clamped to [lo, hi]; metallic level and glossiness uniform in their ranges; emissive
+    with probability emissive_prob, with power uniform in its range.  Returns (albedo
+    RGB, roughness = 1 - glossiness, specular = metallic, emission)."""
+    d = rng.uniform(-1.0, 1.0, 3) * np.asarray(radius, float)
+    hsv = np.asarray(base_hsv, float) + d
+    hsv[0] %= 1.0
+    hsv = np.clip(hsv, lo, hi)
+    spec = rng.uniform(*metallic)
+    rough = 1.0 - rng.uniform(*glossiness)
+    emit = rng.uniform(*emissive_power) if rng.uniform() < emissive_prob else 0.0
+    return hsv_to_rgb(*hsv), rough, spec, emit
+
+
+def pattern_texture(rng: np.random.Generator, size: int = 64, cells: int = 8) -> np.ndarray:
+    """A random pattern texture: a cells x cells checker of random colours with a
+    random stripe overlay (RGB in [0, 1], [size, size, 3])."""
+    cols = rng.uniform(0.2, 1.0, (cells, cells, 3))
+    idx = np.arange(size) * cells // size
+    tex = cols[idx[:, None], idx[None, :]]
+    period = int(rng.integers(4, 16))
+    stripe = ((np.arange(size)[None, :] + np.arange(size)[:, None]) // period) % 2
+    return (tex * (0.75 + 0.25 * stripe[..., None])).astype(np.float32)
+
+
+def with_materials(batch: Batch, seed: int = 0, n_textures: int = 8, textured_prob: float = 0.7,
+                   block_hsv=(0.08, 0.8, 0.8), block_radius=(0.04, 0.1, 0.1)) -> Batch:
+    """The batch with randomized materials: each object gets, with probability
+    textured_prob, one of n_textures random pattern textures with tiling U[0.5, 4] and
+    offset U[0, 1) per axis (MaterialRandomizer); each scene's last object (the hand
+    scenes' block) is redrawn near a calibrated hue by the fixed-hue sampler, emissive
+    with probability 0.2.  Draws come from default_rng([seed, 0x7E47, scene])."""
+    pool_rng = np.random.default_rng([seed, 0x7E47])
+    textures = [pattern_texture(pool_rng) for _ in range(n_textures)]
+    O = batch.n_objects
+    tex = np.full(O, -1, np.int32)
+    xf = np.tile(np.array([1, 1, 0, 0], np.float32), (O, 1))
+    em = np.zeros(O, np.float32)
+    alb = batch.albedo.copy()
+    rough = batch.roughness.copy()
+    spec = batch.specular.copy()
+    for sc in range(batch.n_scenes):
+        rng = np.random.default_rng([seed, 0x7E47, sc])
+        ob, oe = int(batch.scene_object_begin[sc]), int(batch.scene_object_begin[sc + 1])
+        for o in range(ob, oe):
+            if rng.uniform() < textured_prob:
+                tex[o] = int(rng.integers(0, n_textures))
+                xf[o, :2] = rng.uniform(0.5, 4.0, 2)
+                xf[o, 2:] = rng.uniform(0.0, 1.0, 2)
+        if oe > ob:
+            a, r, k, e = fixed_hue_material(rng, block_hsv, block_radius, emissive_prob=0.2, emissive_power=(0.1, 0.5))
+            alb[oe - 1], rough[oe - 1], spec[oe - 1], em[oe - 1] = a, max(r, 0.05), k, e
+    return batch.replace(textures=textures, object_texture=tex, tex_xform=xf, emission=em, albedo=alb,
+                         roughness=rough, specular=spec)
 
 
 # ----------------------------------------------------------------------------------

@@ -18,7 +18,9 @@ import oracle
 from tests import test_oracle_edge_cases as E
 from tests import test_oracle_geometry as G
 from tests import test_oracle_grad as D
+from tests import test_oracle_materials as MA
 from tests import test_oracle_shading as SH
+from tests import test_oracle_shadows as SD
 
 
 def pin(fn, *args):
@@ -81,8 +83,8 @@ MUTANTS = [
     ("no_distance_clamp", "t->A = L->I / (t->D > LIGHT_EPS ? t->D : LIGHT_EPS);", "t->A = L->I / t->D;",
      [pin(E.test_point_light_distance_clamp_closed_form)]),
     ("clamp_epsilon", "#define LIGHT_EPS 1e-4 ", "#define LIGHT_EPS 1e-5 ", [pin(E.test_point_light_distance_clamp_closed_form)]),
-    ("phong_exponent", "double r = in->roughness[o], ks = in->specular[o], mexp = 2.0 / (r * r) - 2.0;\n            const double *alb",
-     "double r = in->roughness[o], ks = in->specular[o], mexp = 2.0 / r - 2.0;\n            const double *alb",
+    ("phong_exponent", "double r = in->roughness[o], ks = in->specular[o], mexp = 2.0 / (r * r) - 2.0;\n            double alb[3];",
+     "double r = in->roughness[o], ks = in->specular[o], mexp = 2.0 / r - 2.0;\n            double alb[3];",
      [pin(SH.test_off_mirror_highlight_half_angle, 0.5, 0.4)]),
     ("half_vector_difference", "double hh[3] = {t->l[0] + fr->v[0], t->l[1] + fr->v[1], t->l[2] + fr->v[2]};",
      "double hh[3] = {t->l[0] - fr->v[0], t->l[1] - fr->v[1], t->l[2] - fr->v[2]};",
@@ -111,6 +113,32 @@ MUTANTS = [
      [pin(E.test_directional_and_point_gradients_rotated_camera)]),
     ("adjoint_exposure_term", "g_exposure[f] += g[0] * U[0] + g[1] * U[1] + g[2] * U[2];",
      "g_exposure[f] += g[0] * U[0] + g[1] * U[1] + g[1] * U[2];", FD_PINS),
+    # spot lights and shadow maps
+    ("shadow_bias_sign", "double wb = (1.0 - SHADOW_BIAS) * w;", "double wb = (1.0 + SHADOW_BIAS) * w;",
+     [pin(SD.test_occluder_shadow_is_its_central_projection)]),
+    ("shadow_v_flip", "double u = L->sK[0] * (q[0] / w) + L->sK[2], v = -L->sK[1] * (q[1] / w) + L->sK[3];",
+     "double u = L->sK[0] * (q[0] / w) + L->sK[2], v = L->sK[1] * (q[1] / w) + L->sK[3];",
+     [pin(SD.test_light_behind_a_ground_point_and_ambiguity_report)]),
+    ("shadow_empty_texel_dark", "if (z == 0 || wb <= z) lit++;", "if (wb <= z) lit++;",
+     [pin(SD.test_lone_plane_is_fully_lit_and_cone_is_smoothstep)]),
+    ("spot_cone_no_smoothstep", "return t * t * (3 - 2 * t);", "return t;",
+     [pin(SD.test_lone_plane_is_fully_lit_and_cone_is_smoothstep)]),
+    ("shadow_pcf_one_texel", "for (int dj = -1; dj <= 1; dj++) {", "for (int dj = 0; dj <= 0; dj++) {",
+     [pin(SD.test_lone_plane_is_fully_lit_and_cone_is_smoothstep)]),
+    # pattern textures and emission
+    ("tex_bilinear_weights_swapped", "rgb[c] = (1 - ay) * ((1 - ax) * T[3 * (j0 * W + i0) + c] + ax * T[3 * (j0 * W + i1) + c]) +",
+     "rgb[c] = (1 - ay) * (ax * T[3 * (j0 * W + i0) + c] + (1 - ax) * T[3 * (j0 * W + i1) + c]) +",
+     [pin(MA.test_bilinear_weights_quarter_texel)]),
+    ("tex_no_half_texel", "double x = u * (double)W - 0.5, y = v * (double)H - 0.5;", "double x = u * (double)W, y = v * (double)H;",
+     [pin(MA.test_pixel_centres_on_texel_centres_show_the_texels)]),
+    ("tex_offset_tiling_order", "tex_sample(in, t, fr->uv[0] * x[0] + x[2], fr->uv[1] * x[1] + x[3], rgb);",
+     "tex_sample(in, t, (fr->uv[0] + x[2]) * x[0], (fr->uv[1] + x[3]) * x[1], rgb);",
+     [pin(MA.test_tiling_and_offset_are_periodic_shifts)]),
+    ("uv_wrong_weight", "for (int k = 0; k < 2; k++) fr->uv[k] = be0 * a->uv[k] + be1 * b->uv[k] + be2 * c->uv[k];",
+     "for (int k = 0; k < 2; k++) fr->uv[k] = be0 * a->uv[k] + be2 * b->uv[k] + be1 * c->uv[k];",
+     [pin(MA.test_pixel_centres_on_texel_centres_show_the_texels)]),
+    ("emission_dropped", "double U[3] = {E * alb[0], E * alb[1], E * alb[2]};", "double U[3] = {0, 0, 0};",
+     [pin(MA.test_emission_adds_power_times_albedo)]),
 ]
 
 

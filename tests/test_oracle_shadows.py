@@ -18,8 +18,8 @@ OCC_SIDE = 0.4    # occluder side: its shadow on the ground has side OCC_SIDE * 
 N = 128           # shadow map size
 
 
-def _scene(occluder=True, inner_deg=30.0, outer_deg=38.0, res=(96, 96), light_xy=(0.0, 0.0)):
-    ground = S.plane_mesh(16, 16, 4.0, 4.0)
+def _scene(occluder=True, inner_deg=30.0, outer_deg=38.0, res=(96, 96), light_xy=(0.0, 0.0), ground_side=4.0):
+    ground = S.plane_mesh(16, 16, ground_side, ground_side)
     occ = S.plane_mesh(2, 2, OCC_SIDE, OCC_SIDE)
     extra = [(occ, S.make_pose(np.eye(3), (0.0, 0.0, OCC_H)))] if occluder else []
     C = S.look_at_c2w((0.0, -0.8, 3.2), (0.0, 0.0, 0.0), (0, 0, 1))
@@ -109,6 +109,28 @@ def test_spot_cone_inside_equals_point_light_outside_dark():
     assert np.all(np.diff(r[order]) <= 1e-12)  # falls off with the angle
 
 
+def test_lone_plane_is_fully_lit_and_cone_is_smoothstep():
+    """A plane smaller than the light's footprint, alone: it only meets itself in the
+    shadow map (within the bias) and empty texels beyond its edges, so every pixel gets
+    the full light; inside the inner cone the spot light is the point light, and
+    between the cones it is the point light times smoothstep of the cosine of the angle
+    to the axis between the two cone cosines."""
+    inner, outer = 10.0, 25.0
+    b = _scene(occluder=False, inner_deg=inner, outer_deg=outer, res=(128, 128), ground_side=1.2)
+    out = oracle.render(b)
+    pt = oracle.render(b.replace(light_type=np.array([0], np.int32)))
+    P, rgb, obj = _ground_points(b, out)
+    _, rgb_pt, _ = _ground_points(b, pt)
+    g = (obj == 0) & (rgb_pt[..., 0] > 0)
+    c = LIGHT_H / np.sqrt(P[..., 0] ** 2 + P[..., 1] ** 2 + LIGHT_H ** 2)  # cos of the angle to the axis
+    ci, co = np.cos(np.radians(inner)), np.cos(np.radians(outer))
+    t = np.clip((c - np.float32(co)) / (np.float32(ci) - np.float32(co)), 0, 1)
+    expect = rgb_pt[..., 0] * t * t * (3 - 2 * t)
+    assert g.sum() > 2000 and (g & (t > 0.05) & (t < 0.95)).sum() > 300
+    # the shaded point comes from snapped vertices: within ~1e-5 of the exact ray hit
+    np.testing.assert_allclose(rgb[..., 0][g], expect[g], rtol=2e-4, atol=1e-12)
+
+
 def test_shadow_map_is_the_depth_render_from_the_light():
     """The shadow frame of the occluder scene holds the occluder at its distance
     LIGHT_H - OCC_H and the ground at LIGHT_H, seen straight down."""
@@ -120,15 +142,17 @@ def test_shadow_map_is_the_depth_render_from_the_light():
 
 
 def test_light_behind_a_ground_point_and_ambiguity_report():
-    """Moving the light sideways moves the shadow by the projection ratio; the pixels the
-    oracle reports as ambiguous lie along the shadow's edge only."""
-    b = _scene(occluder=True, light_xy=(0.3, 0.0))
+    """Moving the light sideways (in x and y) moves the shadow by the projection ratio;
+    the pixels the oracle reports as ambiguous lie along the shadow's edge only."""
+    lx, ly = 0.3, 0.2
+    b = _scene(occluder=True, light_xy=(lx, ly))
     out = oracle.render(b)
     P, rgb, obj = _ground_points(b, out)
     half = 0.5 * OCC_SIDE * LIGHT_H / (LIGHT_H - OCC_H)
-    cx = 0.3 - 0.3 * LIGHT_H / (LIGHT_H - OCC_H)  # shadow centre: projection of x = 0 from x = 0.3
+    k = LIGHT_H / (LIGHT_H - OCC_H)
+    cx, cy = lx - lx * k, ly - ly * k  # shadow centre: the occluder's centre projected from the light
     texel = 2 * LIGHT_H * math.tan(math.radians(39.0)) / N
-    m = np.maximum(np.abs(P[..., 0] - cx), np.abs(P[..., 1]))
+    m = np.maximum(np.abs(P[..., 0] - cx), np.abs(P[..., 1] - cy))
     inside = (obj == 0) & (m < half - 3 * texel)
     assert inside.sum() > 100 and np.all(rgb[inside] == 0)
     amb = out["shadow_amb"].reshape(rgb.shape[:2]).astype(bool)
