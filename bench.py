@@ -170,6 +170,21 @@ def measure_shadows(args, r, S, torch):
                 event_ms_median=_pct(ev, 50), event_ms_p90=_pct(ev, 90))
 
 
+def measure_materials(args, r, S, torch):
+    """The workload with randomized materials: pattern textures with random tiling and
+    offset on about 70% of the objects, the block drawn by the fixed-hue sampler,
+    sometimes emissive."""
+    b = S.with_materials(S.config2(2, args.scenes, args.res), seed=2)
+    job = r.prepare(b)
+    out = r.alloc_outputs(job)
+    for _ in range(3):
+        r.render(job, out)
+    n = max(10, args.steps // 4)
+    dt = _timed(lambda: r.render(job, out), n, torch)
+    return dict(frames=b.n_frames, textured_objects=int((b.object_texture >= 0).sum()),
+                textures=len(b.textures), ms_per_step=round(dt * 1e3, 4), frames_per_s=round(b.n_frames / dt, 1))
+
+
 def measure_extras(args, r, S):
     """Shading-gradient throughput (64 scenes x 3 cameras at 200x200), the serving loop
     (Poisson 2000 req/s of 1-32 scenes at 64/128/200 px), and the uneven batch (1024
@@ -383,6 +398,8 @@ def main(argv=None):
     extra["aux_outputs"] = measure_aux(args, r, S, batch, job, torch, kernel_ms["k_frame"])
     print(f"[bench] with alpha, tracker and rgb8: {extra['aux_outputs']['ms_per_step']:.3f} ms/step, "
           f"k_post {extra['aux_outputs']['k_post']['ms']:.3f} ms", file=sys.stderr, flush=True)
+    extra["materials"] = measure_materials(args, r, S, torch)
+    print(f"[bench] textured materials: {extra['materials']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     extra["spot_shadows"] = measure_shadows(args, r, S, torch)
     print(f"[bench] three shadow-casting spot lights: {extra['spot_shadows']['ms_per_step']:.3f} ms/step",
           file=sys.stderr, flush=True)

@@ -102,6 +102,17 @@ const char *orrb_last_error(void);
 orrb_status orrb_add_mesh(orrb_context *ctx, const float *pos, const float *nrm, int32_t n_verts,
                           const int32_t *idx, int32_t n_tris, int32_t *mesh_id);
 
+/* Texture coordinates of mesh `mesh_id`'s vertices (host [V,2], copied; meshes start
+ * with all 0).  Errors: ORRB_ERR_INVALID_ARGUMENT for an unknown mesh or a non-finite
+ * value. */
+orrb_status orrb_set_mesh_uv(orrb_context *ctx, int32_t mesh_id, const float *uv);
+
+/* Add a pattern texture to the context's resident pool (SSMS: textures are shared, Sec.
+ * 3): host RGB texels [height, width, 3], row 0 first, copied.  *tex_id receives its id
+ * (0, 1, 2, ... in call order).  Errors: ORRB_ERR_INVALID_ARGUMENT for a size outside
+ * [1, ORRB_MAX_DIM] or a non-finite value. */
+orrb_status orrb_add_texture(orrb_context *ctx, const float *rgb, int32_t width, int32_t height, int32_t *tex_id);
+
 /* --------------------------------------------------------------------------------- */
 /* layout: the structure of a batch (host arrays, validated and copied)               */
 /* --------------------------------------------------------------------------------- */
@@ -223,6 +234,17 @@ typedef struct {                  /* sampled randomization parameters */
     const float *light_cone;      /* [L,2] cos(inner half-angle), cos(outer half-angle) */
     const float *shadow_view;     /* [L,3,4] world -> shadow camera (rigid) */
     const float *shadow_intr;     /* [L,4] fx, fy, cx, cy in shadow-map pixels */
+    /* Materials (Sec. 4.3.1 MaterialRandomizer: pattern textures with randomized tiling
+     * and offset; FixedHueMaterialRandomizer: emissive power).  Each may be NULL.  An
+     * object with texture t >= 0 (a resident texture, orrb_add_texture) takes as albedo
+     * its tint times the texture at (u su + ou, v sv + ov), where (u, v) is the
+     * perspective-correct interpolation of the mesh's vertex UVs (orrb_set_mesh_uv) and
+     * the sample is bilinear between texel centres ((i + 1/2)/W, (j + 1/2)/H), row 0
+     * first, repeating; ids outside the pool mean no texture.  An emissive object adds
+     * emission x albedo to the sum over lights (before exposure). */
+    const int32_t *texture;       /* [O] texture id, -1 = none */
+    const float *tex_xform;       /* [O,4] su, sv, ou, ov (needed with texture) */
+    const float *emission;        /* [O] emissive power >= 0 */
 } orrb_params;
 
 #define ORRB_POST_WORDS 12
@@ -378,7 +400,8 @@ typedef struct {                  /* device destinations, overwritten (not accum
  * analytic derivative of the shading function in include/orrb.h's conventions,
  * evaluated per pixel in FP64 and reduced in a fixed order, so repeated calls are
  * bit-identical.  Sub-gradient 0 is taken where a max(0, .) is inactive.  Scenes with
- * more than 1024 objects, and layouts with spot lights, return ORRB_ERR_UNSUPPORTED.  `workspace` needs
+ * more than 1024 objects, layouts with spot lights and textured or emissive materials
+ * return ORRB_ERR_UNSUPPORTED.  `workspace` needs
  * orrb_layout_info.grad_workspace_bytes.  Asynchronous on `stream`. */
 orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
                                 const orrb_cameras *cameras, const orrb_params *params, const uint64_t *vis,

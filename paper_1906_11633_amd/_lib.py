@@ -66,7 +66,8 @@ class Cameras(C.Structure):
 class Params(C.Structure):
     _fields_ = [("albedo", P), ("roughness", P), ("specular", P), ("light_vec", P),
                 ("light_intensity", P), ("exposure", P), ("post", P), ("grain", P), ("grain_w", C.c_int32),
-                ("grain_h", C.c_int32), ("light_dir", P), ("light_cone", P), ("shadow_view", P), ("shadow_intr", P)]
+                ("grain_h", C.c_int32), ("light_dir", P), ("light_cone", P), ("shadow_view", P), ("shadow_intr", P),
+                ("texture", P), ("tex_xform", P), ("emission", P)]
 
 
 class Outputs(C.Structure):
@@ -102,6 +103,8 @@ SIGNATURES = {
     "orrb_destroy": (None, [P]),
     "orrb_last_error": (C.c_char_p, []),
     "orrb_add_mesh": (C.c_int, [P, P, P, C.c_int32, P, C.c_int32, C.POINTER(C.c_int32)]),
+    "orrb_set_mesh_uv": (C.c_int, [P, C.c_int32, P]),
+    "orrb_add_texture": (C.c_int, [P, P, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     "orrb_layout_create": (C.c_int, [P, C.POINTER(LayoutDesc), C.POINTER(P)]),
     "orrb_layout_destroy": (None, [P]),
     "orrb_layout_info_get": (C.c_int, [P, C.POINTER(LayoutInfo)]),

@@ -76,7 +76,16 @@ struct RenderArgs {
     const int32_t *spot_slot;  // per light: shadow-map slot
     const float *shadow_maps;  // [slots, N, N] eye depths from the lights (0: empty)
     int32_t shadow_res;        // N
-    int32_t shade_mode;        // frame kernel: 0 plain, 1 with spot lights, 2 depth only (no shading)
+    int32_t shade_mode;        // frame kernel: bit 0 spot lights, bit 1 textures / emission; 4 depth only
+    // materials: per-vertex UVs, resident textures, each object's texture, UV transform
+    // and emission (null when unused)
+    const float2 *mesh_uv;
+    const float4 *tex_texels;
+    const int4 *tex_info;      // first texel, width, height
+    int32_t n_tex;
+    const int32_t *obj_tex;
+    const float *tex_xform;
+    const float *emission;
     // post-processing of rgb8
     const float *post;   // [F, ORRB_POST_WORDS] or null
     const float *grain;  // [3, grain_h, grain_w] or null

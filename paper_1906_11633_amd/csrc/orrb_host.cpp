@@ -147,6 +147,12 @@ struct orrb_context {
     std::vector<int4> tri;
     std::vector<int32_t> mesh_vbegin{0}, mesh_tbegin{0};
     DevBuf d_pos, d_nrm, d_tri;
+    // per-vertex texture coordinates of the pool (0 until orrb_set_mesh_uv) and the
+    // resident pattern textures (RGB texels as float4, per texture: first texel, w, h)
+    std::vector<float2> uv;
+    std::vector<float4> texels;
+    std::vector<int4> tex_info;
+    DevBuf d_uv, d_texels, d_tex_info;
     int n_layouts = 0;
     uint64_t generation = 0;  // bumped whenever the mesh pool grows (its buffers may move)
 };
@@ -513,6 +519,13 @@ static void fill_args(const orrb_context *ctx, const orrb_layout *L, const orrb_
     a->mesh_pos = (const float4 *)ctx->d_pos.p;
     a->mesh_nrm = (const float4 *)ctx->d_nrm.p;
     a->mesh_tri = (const int4 *)ctx->d_tri.p;
+    a->mesh_uv = (const float2 *)ctx->d_uv.p;
+    a->tex_texels = (const float4 *)ctx->d_texels.p;
+    a->tex_info = (const int4 *)ctx->d_tex_info.p;
+    a->n_tex = (int32_t)ctx->tex_info.size();
+    a->obj_tex = par->texture;
+    a->tex_xform = par->tex_xform;
+    a->emission = par->emission;
     a->pose = sc->object_pose;
     a->seg = sc->object_seg;
     a->visible = sc->object_visible;
@@ -606,14 +619,17 @@ orrb_status orrb_add_mesh(orrb_context *ctx, const float *pos, const float *nrm,
         ctx->nrm.push_back(make_float4((float)(nx * inv), (float)(ny * inv), (float)(nz * inv), 0.f));
     }
     for (int64_t t = 0; t < n_tris; ++t) ctx->tri.push_back(make_int4(idx[3 * t], idx[3 * t + 1], idx[3 * t + 2], 0));
+    ctx->uv.resize(ctx->pos.size(), make_float2(0.f, 0.f));
     ScopedDevice sd(ctx->device);
     hipError_t e = ctx->d_pos.upload(ctx->pos.data(), sizeof(float4) * ctx->pos.size());
     if (e == hipSuccess) e = ctx->d_nrm.upload(ctx->nrm.data(), sizeof(float4) * ctx->nrm.size());
     if (e == hipSuccess) e = ctx->d_tri.upload(ctx->tri.data(), sizeof(int4) * ctx->tri.size());
+    if (e == hipSuccess) e = ctx->d_uv.upload(ctx->uv.data(), sizeof(float2) * ctx->uv.size());
     if (e != hipSuccess) {
         ctx->pos.resize(v0);
         ctx->nrm.resize(v0);
         ctx->tri.resize(t0);
+        ctx->uv.resize(v0);
         return fail(e == hipErrorOutOfMemory ? ORRB_ERR_OUT_OF_MEMORY : ORRB_ERR_DEVICE, "mesh upload failed: %s",
                     hipGetErrorString(e));
     }
@@ -621,6 +637,53 @@ orrb_status orrb_add_mesh(orrb_context *ctx, const float *pos, const float *nrm,
     ctx->mesh_vbegin.push_back((int32_t)ctx->pos.size());
     ctx->mesh_tbegin.push_back((int32_t)ctx->tri.size());
     *mesh_id = (int32_t)ctx->mesh_vbegin.size() - 2;
+    return ORRB_OK;
+}
+
+orrb_status orrb_set_mesh_uv(orrb_context *ctx, int32_t mesh_id, const float *uv) {
+    g_last_error.clear();
+    if (!ctx || !uv) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL argument");
+    const int n_meshes = (int)ctx->mesh_vbegin.size() - 1;
+    if (mesh_id < 0 || mesh_id >= n_meshes) return fail(ORRB_ERR_INVALID_ARGUMENT, "unknown mesh %d", mesh_id);
+    const int32_t v0 = ctx->mesh_vbegin[mesh_id], nv = ctx->mesh_vbegin[mesh_id + 1] - v0;
+    for (int64_t k = 0; k < 2 * (int64_t)nv; ++k)
+        if (!std::isfinite(uv[k])) return fail(ORRB_ERR_INVALID_ARGUMENT, "non-finite uv at vertex %lld", (long long)(k / 2));
+    std::vector<float2> old(ctx->uv.begin() + v0, ctx->uv.begin() + v0 + nv);
+    for (int32_t v = 0; v < nv; ++v) ctx->uv[v0 + v] = make_float2(uv[2 * v], uv[2 * v + 1]);
+    ScopedDevice sd(ctx->device);
+    const hipError_t e = ctx->d_uv.upload(ctx->uv.data(), sizeof(float2) * ctx->uv.size());
+    if (e != hipSuccess) {
+        std::copy(old.begin(), old.end(), ctx->uv.begin() + v0);
+        return fail(e == hipErrorOutOfMemory ? ORRB_ERR_OUT_OF_MEMORY : ORRB_ERR_DEVICE, "uv upload failed: %s",
+                    hipGetErrorString(e));
+    }
+    ctx->generation++;
+    return ORRB_OK;
+}
+
+orrb_status orrb_add_texture(orrb_context *ctx, const float *rgb, int32_t width, int32_t height, int32_t *tex_id) {
+    g_last_error.clear();
+    if (!ctx || !rgb || !tex_id) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL argument");
+    if (width < 1 || height < 1 || width > ORRB_MAX_DIM || height > ORRB_MAX_DIM)
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "texture size %dx%d out of range", width, height);
+    const int64_t n = (int64_t)width * height;
+    if ((int64_t)ctx->texels.size() + n > 0x7fffffff) return fail(ORRB_ERR_UNSUPPORTED, "texture pool would exceed 2^31 texels");
+    for (int64_t k = 0; k < 3 * n; ++k)
+        if (!std::isfinite(rgb[k])) return fail(ORRB_ERR_INVALID_ARGUMENT, "non-finite texel value at %lld", (long long)(k / 3));
+    const size_t t0 = ctx->texels.size();
+    for (int64_t k = 0; k < n; ++k) ctx->texels.push_back(make_float4(rgb[3 * k], rgb[3 * k + 1], rgb[3 * k + 2], 0.f));
+    ctx->tex_info.push_back(make_int4((int)t0, width, height, 0));
+    ScopedDevice sd(ctx->device);
+    hipError_t e = ctx->d_texels.upload(ctx->texels.data(), sizeof(float4) * ctx->texels.size());
+    if (e == hipSuccess) e = ctx->d_tex_info.upload(ctx->tex_info.data(), sizeof(int4) * ctx->tex_info.size());
+    if (e != hipSuccess) {
+        ctx->texels.resize(t0);
+        ctx->tex_info.pop_back();
+        return fail(e == hipErrorOutOfMemory ? ORRB_ERR_OUT_OF_MEMORY : ORRB_ERR_DEVICE, "texture upload failed: %s",
+                    hipGetErrorString(e));
+    }
+    ctx->generation++;
+    *tex_id = (int32_t)ctx->tex_info.size() - 1;
     return ORRB_OK;
 }
 
@@ -939,7 +1002,9 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     a.grain_w = par->grain_w;
     a.grain_h = par->grain_h;
     // shading mode of the frame kernel: depth only when nothing shaded is written
-    a.shade_mode = (!out->rgb && !out->normal && !out->rgb8) ? 2 : L->shadow ? 1 : 0;
+    a.shade_mode = (!out->rgb && !out->normal && !out->rgb8) ? 4
+                   : (L->shadow ? 1 : 0) | ((par->texture || par->emission) ? 2 : 0);
+    if (par->texture && !par->tex_xform) return fail(ORRB_ERR_INVALID_ARGUMENT, "texture needs tex_xform");
     if (L->shadow) {
         a.light_dir = par->light_dir;
         a.light_cone = par->light_cone;
@@ -1017,6 +1082,8 @@ orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const o
         (L->n_lights > 0 && (!gr->light_vec || !gr->light_intensity)) || (L->n_frames > 0 && !gr->exposure))
         return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL gradient destination");
     if (L->n_spot > 0) return fail(ORRB_ERR_UNSUPPORTED, "the shading adjoint does not cover spot lights");
+    if (par->texture || par->emission)
+        return fail(ORRB_ERR_UNSUPPORTED, "the shading adjoint does not cover textured or emissive materials");
     if (L->max_scene_objects > grad_max_objects())
         return fail(ORRB_ERR_UNSUPPORTED, "a scene has %d objects; the adjoint supports %d", L->max_scene_objects,
                     grad_max_objects());

@@ -395,10 +395,11 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
             const int4 tv = a.mesh_tri[mtb + (tri - tbase)];
             // the winning triangle is front-facing: same vertex order as in set-up
             const int4 pa = a.vtx_pos[vb + tv.x], pb = a.vtx_pos[vb + tv.z], pc = a.vtx_pos[vb + tv.y];
-            o = shade_pixel<true>(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, __int_as_float(pa.z), __int_as_float(pb.z),
+            const MatTex mt = mat_inputs(a, obj, mvb, tv);
+            o = shade_pixel<true, true>(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, __int_as_float(pa.z), __int_as_float(pb.z),
                             __int_as_float(pc.z), a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z], a.mesh_nrm[mvb + tv.y], R,
                             i, j, z, cam, L.light, L.light_type, fi.n_lights, object_material(a, obj), L.spot,
-                            a.shadow_maps, a.shadow_res);
+                            a.shadow_maps, a.shadow_res, &mt, a.tex_texels, a.tex_info);
             segv = a.seg[obj];
             triv = tri;
         }
@@ -1185,9 +1186,9 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
         if ((q & 3) != 3) F.o_R[k][(q >> 2) * 3 + (q & 3)] = (float)m;
     }
     if (tid < fi.n_lights) {
-        if constexpr (SHADE == 1) {
+        if constexpr (SHADE == 1 || SHADE == 3) {
             frame_light(a, f, fi, tid, S.light, S.light_type, S.spot);
-        } else if constexpr (SHADE == 0) {
+        } else if constexpr (SHADE != 4) {
             const int l = fi.light_begin + tid;
             S.light[tid] = view_light(a.view + 12 * (int64_t)f, a.light_vec + 3 * (int64_t)l, a.light_type[l],
                                       a.light_intensity[l]);
@@ -1492,14 +1493,17 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
                 const int4 tv = frame_tri(a, F, k, tri);
                 const int vb = F.o_vbase[k], mvb = F.o_mvb[k];
                 const int va = vb + tv.x, vbb = vb + tv.z, vc = vb + tv.y;  // positive-area order
-                if constexpr (SHADE == 2) {  // depth only (shadow maps): no shading
+                if constexpr (SHADE == 4) {  // depth only (shadow maps): no shading
                     o[h] = PixelOut{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 } else {
-                    o[h] = shade_pixel<SHADE == 1>(F.X[va], F.Y[va], F.X[vbb], F.Y[vbb], F.X[vc], F.Y[vc], F.iw[va],
-                                                   F.iw[vbb], F.iw[vc], a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z],
-                                                   a.mesh_nrm[mvb + tv.y], F.o_R[k], pi, pj, z, cam, S.light,
-                                                   S.light_type, fi.n_lights, F.o_mat[k], S.spot, a.shadow_maps,
-                                                   a.shadow_res);
+                    constexpr bool kSpot = (SHADE & 1) != 0, kMat = (SHADE & 2) != 0;
+                    MatTex mt;
+                    if constexpr (kMat) mt = mat_inputs(a, fi.obj_begin + k, mvb, tv);
+                    o[h] = shade_pixel<kSpot, kMat>(F.X[va], F.Y[va], F.X[vbb], F.Y[vbb], F.X[vc], F.Y[vc], F.iw[va],
+                                                    F.iw[vbb], F.iw[vc], a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z],
+                                                    a.mesh_nrm[mvb + tv.y], F.o_R[k], pi, pj, z, cam, S.light,
+                                                    S.light_type, fi.n_lights, F.o_mat[k], S.spot, a.shadow_maps,
+                                                    a.shadow_res, &mt, a.tex_texels, a.tex_info);
                 }
                 kk[h] = key & ~0xffff0000ull;
                 sg[h] = F.o_seg[k];
@@ -1640,14 +1644,26 @@ hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu) {
     const dim3 g(grid), b(kFT);
 #define ORRB_FRAME(AUX_, MIXED_, SHADE_) hipLaunchKernelGGL((k_frame<AUX_, MIXED_, SHADE_>), g, b, 0, stream, a)
     switch (a.shade_mode) {
-        case 2:  // depth only (shadow maps); no auxiliary outputs
-            if (mixed) ORRB_FRAME(false, true, 2); else ORRB_FRAME(false, false, 2);
+        case 4:  // depth only (shadow maps); no auxiliary outputs
+            if (mixed) ORRB_FRAME(false, true, 4); else ORRB_FRAME(false, false, 4);
             break;
         case 1:  // spot lights with shadow maps
             if (aux && mixed) ORRB_FRAME(true, true, 1);
             else if (aux) ORRB_FRAME(true, false, 1);
             else if (mixed) ORRB_FRAME(false, true, 1);
             else ORRB_FRAME(false, false, 1);
+            break;
+        case 2:  // textured / emissive materials
+            if (aux && mixed) ORRB_FRAME(true, true, 2);
+            else if (aux) ORRB_FRAME(true, false, 2);
+            else if (mixed) ORRB_FRAME(false, true, 2);
+            else ORRB_FRAME(false, false, 2);
+            break;
+        case 3:  // both
+            if (aux && mixed) ORRB_FRAME(true, true, 3);
+            else if (aux) ORRB_FRAME(true, false, 3);
+            else if (mixed) ORRB_FRAME(false, true, 3);
+            else ORRB_FRAME(false, false, 3);
             break;
         default:
             if (aux && mixed) ORRB_FRAME(true, true, 0);

@@ -314,14 +314,68 @@ ORRB_INLINE float spec_pow(float u, float m) {
     return __builtin_amdgcn_exp2f(m * l2);
 }
 
+// A pixel's material inputs beyond the LDS material (textured / emissive shading):
+// the winning triangle's vertex UVs (positive-area order), the object's texture id,
+// UV transform and emissive power.
+struct MatTex {
+    float2 uva, uvb, uvc;
+    int tex;
+    float su, sv, ou, ov;
+    float emit;
+};
+
+// Material inputs of global object o whose mesh vertices start at mvb, for the mesh
+// triangle tv (a, b, c = tv.x, tv.z, tv.y in positive-area order).
+ORRB_INLINE MatTex mat_inputs(const RenderArgs &a, int o, int mvb, int4 tv) {
+    MatTex t;
+    t.tex = a.obj_tex ? a.obj_tex[o] : -1;
+    if (t.tex >= a.n_tex) t.tex = -1;  // not a resident texture: none
+    t.su = t.sv = 1.f;
+    t.ou = t.ov = 0.f;
+    t.uva = t.uvb = t.uvc = make_float2(0.f, 0.f);
+    if (t.tex >= 0) {
+        const float4 x = *reinterpret_cast<const float4 *>(a.tex_xform + 4 * (int64_t)o);
+        t.su = x.x;
+        t.sv = x.y;
+        t.ou = x.z;
+        t.ov = x.w;
+        t.uva = a.mesh_uv[mvb + tv.x];
+        t.uvb = a.mesh_uv[mvb + tv.z];
+        t.uvc = a.mesh_uv[mvb + tv.y];
+    }
+    t.emit = a.emission ? a.emission[o] : 0.f;
+    return t;
+}
+
+// Bilinear sample of a texture at (u, v), repeating: texel (i, j) is centred at
+// ((i + 1/2) / W, (j + 1/2) / H), row 0 first.
+ORRB_INLINE float3 tex_bilinear(const float4 *texels, int4 info, float u, float v) {
+#pragma clang fp contract(off)
+    const int W = info.y, H = info.z;
+    const float x = u * (float)W - 0.5f, y = v * (float)H - 0.5f;
+    const float fx = floorf(x), fy = floorf(y), ax = x - fx, ay = y - fy;
+    int i0 = (int)fmodf(fx, (float)W), j0 = (int)fmodf(fy, (float)H);
+    if (i0 < 0) i0 += W;
+    if (j0 < 0) j0 += H;
+    const int i1 = i0 + 1 == W ? 0 : i0 + 1, j1 = j0 + 1 == H ? 0 : j0 + 1;
+    const float4 *T = texels + info.x;
+    const float4 t00 = T[j0 * W + i0], t01 = T[j0 * W + i1], t10 = T[j1 * W + i0], t11 = T[j1 * W + i1];
+    const float b0 = 1.f - ax, b1 = 1.f - ay;
+    return f3(b1 * (b0 * t00.x + ax * t01.x) + ay * (b0 * t10.x + ax * t11.x),
+              b1 * (b0 * t00.y + ax * t01.y) + ay * (b0 * t10.y + ax * t11.y),
+              b1 * (b0 * t00.z + ax * t01.z) + ay * (b0 * t10.z + ax * t11.z));
+}
+
 // Shade the covered pixel (i, j) at eye depth z of the positive-area triangle a, b, c:
 // perspective-correct smooth normal from the unit object-space vertex normals and R,
 // then exposure * sum over lights of A * max(0, n.l) * (albedo + k_s * max(0, n.h)^m).
-template <bool SPOT = false>
+template <bool SPOT = false, bool MAT = false>
 ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc, float iwa, float iwb, float iwc,
                                  float4 na4, float4 nb4, float4 nc4, const float *R, int i, int j, float z,
                                  const CamF &cam, const float4 *light, const int *ltype, int nl, const Material &m,
-                                 const SpotLight *spot = nullptr, const float *maps = nullptr, int shadow_res = 0) {
+                                 const SpotLight *spot = nullptr, const float *maps = nullptr, int shadow_res = 0,
+                                 const MatTex *mt = nullptr, const float4 *texels = nullptr,
+                                 const int4 *tex_info = nullptr) {
 #pragma clang fp contract(off)
     const Edges e = edge_eval(xa, ya, xb, yb, xc, yc, (i << 8) + 128, (j << 8) + 128, extent_flag(xa, ya, xb, yb, xc, yc));
     // perspective-correct weights are proportional to E_k / w_k
@@ -336,7 +390,22 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
     const float pinv = rsqrtf(dot3(pp, pp));
     const float3 v = f3(-pp.x * pinv, -pp.y * pinv, -pp.z * pinv);
     const float mexp = 2.0f * __builtin_amdgcn_rcpf(m.rough * m.rough) - 2.0f;
+    float al0 = m.al0, al1 = m.al1, al2 = m.al2;
     float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+    if (MAT) {  // pattern texture at the perspective-correct UV, then emission
+        if (mt->tex >= 0) {
+            const float inv = 1.0f / (t0 + t1 + t2);
+            const float u = (t0 * mt->uva.x + t1 * mt->uvb.x + t2 * mt->uvc.x) * inv;
+            const float v = (t0 * mt->uva.y + t1 * mt->uvb.y + t2 * mt->uvc.y) * inv;
+            const float3 tx = tex_bilinear(texels, tex_info[mt->tex], u * mt->su + mt->ou, v * mt->sv + mt->ov);
+            al0 *= tx.x;
+            al1 *= tx.y;
+            al2 *= tx.z;
+        }
+        r0 = mt->emit * al0;
+        r1 = mt->emit * al1;
+        r2 = mt->emit * al2;
+    }
     for (int l = 0; l < nl; ++l) {
         const float4 Lq = light[l];
         const int lt = ltype[l];
@@ -373,9 +442,9 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
             if (u < 1.0f) s = (mexp == 0.f) ? 1.0f : spec_pow(u, mexp);
         }
         const float An = A * ndl;
-        r0 = fmaf(An, fmaf(m.ks, s, m.al0), r0);
-        r1 = fmaf(An, fmaf(m.ks, s, m.al1), r1);
-        r2 = fmaf(An, fmaf(m.ks, s, m.al2), r2);
+        r0 = fmaf(An, fmaf(m.ks, s, al0), r0);
+        r1 = fmaf(An, fmaf(m.ks, s, al1), r1);
+        r2 = fmaf(An, fmaf(m.ks, s, al2), r2);
     }
     PixelOut o;
     o.r0 = r0 * cam.expo;

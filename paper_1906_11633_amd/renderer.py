@@ -45,6 +45,7 @@ class Context:
         L.check(self.lib.orrb_create(self.device, C.byref(h)))
         self.handle = h
         self._mesh_ids: Dict[int, int] = {}
+        self._tex_ids: Dict[int, int] = {}
         self._keep = []  # meshes whose ids are cached (keeps id() stable)
 
     def add_mesh(self, mesh) -> int:
@@ -60,7 +61,24 @@ class Context:
                                        C.byref(mid)))
         self._mesh_ids[key] = mid.value
         self._keep.append(mesh)
+        uv = getattr(mesh, "uv", None)
+        if uv is not None:
+            uvc = np.ascontiguousarray(uv, np.float32)
+            L.check(self.lib.orrb_set_mesh_uv(self.handle, mid.value, uvc.ctypes.data_as(C.c_void_p)))
         return mid.value
+
+    def add_texture(self, rgb) -> int:
+        """Upload a pattern texture (RGB [H, W, 3]) to the resident pool once; its id."""
+        key = id(rgb)
+        if key in self._tex_ids:
+            return self._tex_ids[key]
+        arr = np.ascontiguousarray(rgb, np.float32)
+        tid = C.c_int32()
+        L.check(self.lib.orrb_add_texture(self.handle, arr.ctypes.data_as(C.c_void_p), int(arr.shape[1]),
+                                          int(arr.shape[0]), C.byref(tid)))
+        self._tex_ids[key] = tid.value
+        self._keep.append(rgb)
+        return tid.value
 
     def wait_timeouts(self) -> int:
         """Frame-kernel waits that reached their bound on this device so far (0 unless
@@ -151,11 +169,23 @@ def device_state(batch, device="cuda") -> Dict[str, torch.Tensor]:
     grain = getattr(batch, "grain", None)
     if grain is not None:
         out["grain"] = torch.from_numpy(np.ascontiguousarray(grain, np.float32)).to(device)
-    for k in ("light_dir", "light_cone", "shadow_view", "shadow_intr"):  # spot lights
+    for k in ("light_dir", "light_cone", "shadow_view", "shadow_intr", "tex_xform", "emission"):
         v = getattr(batch, k, None)
         if v is not None:
             out[k] = torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(device)
     return out
+
+
+def texture_state(ctx: "Context", batch, device="cuda") -> Dict[str, torch.Tensor]:
+    """Each object's resident texture id (the batch's textures uploaded to the context
+    once), as a device tensor; empty if the batch has no textured materials."""
+    ot = getattr(batch, "object_texture", None)
+    if ot is None or getattr(batch, "textures", None) is None:
+        return {}
+    ids = np.array([ctx.add_texture(t) for t in batch.textures], np.int32)
+    ot = np.asarray(ot, np.int64)
+    mapped = np.where(ot >= 0, ids[np.clip(ot, 0, max(len(ids) - 1, 0))] if len(ids) else -1, -1).astype(np.int32)
+    return {"texture": torch.from_numpy(mapped).to(device)}
 
 
 @dataclass
@@ -179,6 +209,8 @@ class Renderer:
     def prepare(self, batch, state: Optional[Dict[str, torch.Tensor]] = None) -> Job:
         lay = Layout(self.ctx, batch)
         st = state if state is not None else device_state(batch, f"cuda:{self.device}")
+        if state is None:
+            st.update(texture_state(self.ctx, batch, f"cuda:{self.device}"))
         inf = lay.info
         ws = torch.empty(max(int(inf.workspace_bytes_any), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
         return Job(lay, st, int(inf.total_pixels), ws)
@@ -241,7 +273,8 @@ def _params(state) -> L.Params:
     return L.Params(_ptr(s["albedo"]), _ptr(s["roughness"]), _ptr(s["specular"]), _ptr(s["light_vec"]),
                     _ptr(s["light_intensity"]), _ptr(s["exposure"]), _ptr(s.get("post")), _ptr(grain), gw, gh,
                     _ptr(s.get("light_dir")), _ptr(s.get("light_cone")), _ptr(s.get("shadow_view")),
-                    _ptr(s.get("shadow_intr")))
+                    _ptr(s.get("shadow_intr")), _ptr(s.get("texture")), _ptr(s.get("tex_xform")),
+                    _ptr(s.get("emission")))
 
 
 def _structs(state, out):
