@@ -84,8 +84,9 @@ typedef struct orrb_layout orrb_layout;
 /* Create a context on HIP device `hip_device`.  *out receives the handle. */
 orrb_status orrb_create(int hip_device, orrb_context **out);
 
-/* Destroy a context and free its mesh pool.  Layouts of the context must be destroyed
- * first.  NULL is ignored. */
+/* Destroy a context and free its mesh and texture pools.  If layouts of the context are
+ * still alive, the context stays until the last of them is destroyed (then it is freed
+ * with it); the handle must not be used after this call either way.  NULL is ignored. */
 void orrb_destroy(orrb_context *ctx);
 
 /* Message of the calling thread's last failure ("" if none); valid until that

@@ -7,14 +7,17 @@
 // parameters moves geometry.
 //
 //   k_grad_tile    one workgroup per (frame, 32x32 tile): per pixel, rebuild the
-//                  fragment from its key (exact edge functions of the snapped
-//                  vertices, perspective-correct normal, view-space position) and
-//                  evaluate the analytic adjoint of the shading in FP64; reduce the
-//                  tile in a fixed order (wave shuffles, then waves in order) into a
+//                  fragment from its key (exact edge functions of the snapped vertices,
+//                  perspective-correct normal, view-space position: the forward's own
+//                  fp32 arithmetic) and evaluate the analytic adjoint of the shading in
+//                  fp32; every sum is FP64.  Per object: each wave adds its pixels'
+//                  terms per distinct object (wave reductions), then the four waves in
+//                  order; lights and exposure likewise.  The tile's sums go to a
 //                  per-tile FP64 partial vector.
-//   k_grad_reduce  one thread per output parameter: sums the partials of the tiles
-//                  that can touch it, in a fixed order, and writes the gradient.
-// No floating-point atomics: the result is deterministic.
+//   k_grad_reduce  per (scene, 64 parameters): the four waves sum interleaved quarters
+//                  of the scene's tile partials, then combine in order, and write the
+//                  gradient.
+// No floating-point atomics: repeated calls are bit-identical.
 #include "orrb_primitives.h"
 
 namespace orrb {
@@ -22,19 +25,24 @@ namespace orrb {
 constexpr int kGTile = 32;
 constexpr int kGPix = kGTile * kGTile;      // pixels per tile
 constexpr int kGPer = kGPix / kBlock;       // pixels per thread
+constexpr int kGWaves = kBlock / kWave;
 constexpr int kGMaxObj = 1024;              // objects per scene supported by the adjoint
+constexpr int kGPresent = 64;               // distinct objects per tile summed per wave in LDS
+constexpr int kGChunk = 64;                 // parameters per reduce workgroup
 
 struct GradLds {
-    double light_q[kMaxLights][3];
-    double light_qn[kMaxLights];  // directional: |R_V u| before normalization
-    double light_I[kMaxLights];
+    float4 light[kMaxLights];     // view space: point position / unit direction to the light; w = intensity
+    float light_qn[kMaxLights];   // directional: |R_V u| before normalization
     int light_type[kMaxLights];
-    int pix_obj[kGPix];
-    double pix_val[5][kGPix];
+    int o_tbase[kGMaxObj];        // scene triangle base of each object (object lookup)
+    int pix_obj[kGPix];           // local object of each pixel's fragment, -1 none
+    float pix_val[5][kGPix];      // its albedo (3), roughness and specular terms
     unsigned char present[kGMaxObj];
-    double wacc[kBlock / kWave][4 * kMaxLights + 1];  // per-wave light / exposure sums
-    double red[kBlock / kWave][5];
-    double out[5];
+    int slot_of[kGMaxObj];        // present objects: their compact slot
+    int slot_obj[kGPresent];
+    double oacc[kGWaves][kGPresent][5];               // per-wave object sums
+    double wacc[kGWaves][4 * kMaxLights + 1];         // per-wave light / exposure sums
+    int n_present;
 };
 
 // Sum over the wave (fixed butterfly order).
@@ -43,28 +51,6 @@ ORRB_INLINE double wave_sum(double x) {
     for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
     return x;
 }
-
-// Sum of v[0..5) over the workgroup, fixed order; every thread gets the result.
-ORRB_INLINE void block_sum5(double (&v)[5], GradLds &S) {
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const double x = wave_sum(v[k]);
-        if (lane == 0) S.red[wave][k] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < 5) {
-        double x = 0.0;
-        for (int w = 0; w < kBlock / kWave; ++w) x += S.red[w][threadIdx.x];
-        S.out[threadIdx.x] = x;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 5; ++k) v[k] = S.out[k];
-    __syncthreads();
-}
-
-ORRB_INLINE double dot3d(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 __global__ __launch_bounds__(kBlock) void k_grad_tile(GradArgs g) {
     __shared__ GradLds S;
@@ -75,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_tile(GradArgs g) {
     const int W = fi.width, H = fi.height;
     const int ntx = (W + kGTile - 1) / kGTile;
     const int x0 = (it.y % ntx) * kGTile, y0 = (it.y / ntx) * kGTile;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const int nl = fi.n_lights, n_obj = fi.n_obj;
     const float *V = a.view + 12 * (int64_t)f;
 
@@ -90,159 +76,166 @@ __global__ __launch_bounds__(kBlock) void k_grad_tile(GradArgs g) {
         }
         double qn = 1.0;
         if (type != 0) {
-            qn = sqrt(dot3d(q, q));
-            const double inv = 1.0 / qn;
-            for (int r = 0; r < 3; ++r) q[r] *= inv;
+            qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+            for (int r = 0; r < 3; ++r) q[r] /= qn;
         }
-        for (int r = 0; r < 3; ++r) S.light_q[tid][r] = q[r];
-        S.light_qn[tid] = qn;
-        S.light_I[tid] = a.light_intensity[l];
+        // the forward's view-space light (view_light), so the fragment terms agree
+        S.light[tid] = view_light(V, u, type, a.light_intensity[l]);
+        S.light_qn[tid] = (float)qn;
         S.light_type[tid] = type;
     }
-    for (int k = tid; k < n_obj; k += kBlock) S.present[k] = 0;
-    for (int k = tid; k < (kBlock / kWave) * (4 * kMaxLights + 1); k += kBlock) (&S.wacc[0][0])[k] = 0.0;
+    for (int k = tid; k < n_obj; k += kBlock) {
+        S.o_tbase[k] = a.objs[fi.obj_begin + k].scene_tbase;
+        S.present[k] = 0;
+    }
+    for (int k = tid; k < kGWaves * (4 * kMaxLights + 1); k += kBlock) (&S.wacc[0][0])[k] = 0.0;
+    for (int k = tid; k < kGWaves * kGPresent * 5; k += kBlock) (&S.oacc[0][0][0])[k] = 0.0;
     __syncthreads();
-    const int lane = lane_id(), wave = tid / kWave;
 
-    const float *K = a.intr + 4 * (int64_t)f;
-    const double fx = K[0], fy = K[1], cx = K[2], cy = K[3];
-    const double e = a.exposure[f];
+    const CamF cam = frame_camera(a, f);
+    const float e = cam.expo;
     const int64_t HW = (int64_t)W * H, po = fi.pixel_offset;
     for (int q = 0; q < kGPer; ++q) {
         const int p = tid + kBlock * q;
         const int li = p & (kGTile - 1), lj = p / kGTile;
         const int i = x0 + li, j = y0 + lj;
         int obj_local = -1;
-        double ov[5] = {0, 0, 0, 0, 0};
-        // fragment state (valid when obj_local >= 0)
-        double n[3] = {0, 0, 1}, pp[3] = {0, 0, -1}, v[3] = {0, 0, 1}, al[3] = {0, 0, 0}, gc[3] = {0, 0, 0};
-        double r = 1.0, ks = 0.0, m = 0.0, G = 0.0;
+        float ov[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f;
+        float3 n = f3(0.f, 0.f, 1.f), pp = f3(0.f, 0.f, -1.f), v = f3(0.f, 0.f, 1.f);
+        float al0 = 0.f, al1 = 0.f, al2 = 0.f, r = 1.f, ks = 0.f, m = 0.f, G = 0.f;
         if (i < W && j < H) {
             const int64_t pix = (int64_t)j * W + i;
             const unsigned long long key = g.vis[po + pix];
-            gc[0] = g.grad_rgb[3 * po + pix];
-            gc[1] = g.grad_rgb[3 * po + HW + pix];
-            gc[2] = g.grad_rgb[3 * po + 2 * HW + pix];
-            if (key != kEmptyKey && (gc[0] != 0.0 || gc[1] != 0.0 || gc[2] != 0.0)) {
+            gc0 = g.grad_rgb[3 * po + pix];
+            gc1 = g.grad_rgb[3 * po + HW + pix];
+            gc2 = g.grad_rgb[3 * po + 2 * HW + pix];
+            if (key != kEmptyKey && (gc0 != 0.f || gc1 != 0.f || gc2 != 0.f)) {
                 const int tri = (int)(unsigned)(key & 0xffffffffu);
-                const double z = (double)__uint_as_float((unsigned)(key >> 32));
-                int lo = 0, hi = n_obj;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (a.objs[fi.obj_begin + mid].scene_tbase <= tri) lo = mid; else hi = mid;
-                }
-                obj_local = lo;
-                const int o = fi.obj_begin + lo;
+                const float z = __uint_as_float((unsigned)(key >> 32));
+                obj_local = find_slot(S.o_tbase, n_obj, tri);
+                const int o = fi.obj_begin + obj_local;
                 const ObjInfo ob = a.objs[o];
                 const int4 tv = a.mesh_tri[ob.mesh_tbegin + (tri - ob.scene_tbase)];
                 const int64_t vb = fi.vbase + ob.scene_vbase;
                 const int4 pa = a.vtx_pos[vb + tv.x], pb = a.vtx_pos[vb + tv.z], pc = a.vtx_pos[vb + tv.y];
                 const Edges ed = edge_eval(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, (i << 8) + 128, (j << 8) + 128,
                                            extent_flag(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y));
-                const double tw[3] = {(double)ed.e0 * __int_as_float(pa.z), (double)ed.e1 * __int_as_float(pb.z),
-                                      (double)ed.e2 * __int_as_float(pc.z)};
-                const float4 *rot = a.obj_rot + 3 * (int64_t)(fi.oi_base + lo);
+                const float t0 = ed.e0 * __int_as_float(pa.z), t1 = ed.e1 * __int_as_float(pb.z),
+                            t2 = ed.e2 * __int_as_float(pc.z);
+                const float4 na = a.mesh_nrm[ob.mesh_vbegin + tv.x], nb = a.mesh_nrm[ob.mesh_vbegin + tv.z],
+                             nc = a.mesh_nrm[ob.mesh_vbegin + tv.y];
+                const float4 *rot = a.obj_rot + 3 * (int64_t)(fi.oi_base + obj_local);
                 const float4 R0 = rot[0], R1 = rot[1], R2 = rot[2];
-                const int vi[3] = {tv.x, tv.z, tv.y};
-                n[0] = n[1] = n[2] = 0.0;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const float4 nm = a.mesh_nrm[ob.mesh_vbegin + vi[k]];
-                    const double rr[3] = {(double)R0.x * nm.x + (double)R0.y * nm.y + (double)R0.z * nm.z,
-                                          (double)R1.x * nm.x + (double)R1.y * nm.y + (double)R1.z * nm.z,
-                                          (double)R2.x * nm.x + (double)R2.y * nm.y + (double)R2.z * nm.z};
-                    const double sc = tw[k] / sqrt(dot3d(rr, rr));
-                    n[0] += sc * rr[0];
-                    n[1] += sc * rr[1];
-                    n[2] += sc * rr[2];
+                const float R[9] = {R0.x, R0.y, R0.z, R1.x, R1.y, R1.z, R2.x, R2.y, R2.z};
+                {
+#pragma clang fp contract(off)
+                    const float4 no = make_float4(fmaf(t0, na.x, fmaf(t1, nb.x, t2 * nc.x)),
+                                                  fmaf(t0, na.y, fmaf(t1, nb.y, t2 * nc.y)),
+                                                  fmaf(t0, na.z, fmaf(t1, nb.z, t2 * nc.z)), 0.f);
+                    n = rotate_normal(R, no);
+                    pp = f3(z * (((float)i + 0.5f - cam.cx) * cam.ifx), -z * (((float)j + 0.5f - cam.cy) * cam.ify), -z);
+                    const float pinv = rsqrtf(dot3(pp, pp));
+                    v = f3(-pp.x * pinv, -pp.y * pinv, -pp.z * pinv);
                 }
-                const double ninv = 1.0 / sqrt(dot3d(n, n));
-                n[0] *= ninv;
-                n[1] *= ninv;
-                n[2] *= ninv;
-                pp[0] = z * ((i + 0.5 - cx) / fx);
-                pp[1] = z * (-(j + 0.5 - cy) / fy);
-                pp[2] = -z;
-                const double pinv = 1.0 / sqrt(dot3d(pp, pp));
-                v[0] = -pp[0] * pinv;
-                v[1] = -pp[1] * pinv;
-                v[2] = -pp[2] * pinv;
                 r = a.roughness[o];
                 ks = a.specular[o];
-                m = 2.0 / (r * r) - 2.0;
-                al[0] = a.albedo[3 * o + 0];
-                al[1] = a.albedo[3 * o + 1];
-                al[2] = a.albedo[3 * o + 2];
-                G = gc[0] + gc[1] + gc[2];
+                m = 2.0f * __builtin_amdgcn_rcpf(r * r) - 2.0f;
+                al0 = a.albedo[3 * o + 0];
+                al1 = a.albedo[3 * o + 1];
+                al2 = a.albedo[3 * o + 2];
+                G = gc0 + gc1 + gc2;
             }
         }
         const bool frag = obj_local >= 0;
-        double U[3] = {0, 0, 0}, sAnd = 0, sAnds = 0, sAndsln = 0;
+        float U0 = 0.f, U1 = 0.f, U2 = 0.f, sAnd = 0.f, sAnds = 0.f, sAndsln = 0.f;
         for (int l = 0; l < nl; ++l) {  // wave-uniform trip count
-            double gq[3] = {0, 0, 0}, gI = 0.0;
+#pragma clang fp contract(off)
+            float gq0 = 0.f, gq1 = 0.f, gq2 = 0.f, gI = 0.f;
             const bool point = S.light_type[l] == 0;
             if (frag) {
-                double ld[3], D = 1.0, dist = 1.0, A;
+                const float4 Lq = S.light[l];
+                float3 ld;
+                float D = 1.f, dist = 1.f, A;
                 if (point) {
-                    const double d[3] = {S.light_q[l][0] - pp[0], S.light_q[l][1] - pp[1], S.light_q[l][2] - pp[2]};
-                    D = dot3d(d, d);
-                    dist = sqrt(D);
-                    for (int k = 0; k < 3; ++k) ld[k] = d[k] / dist;
-                    A = S.light_I[l] / (D > 1e-4 ? D : 1e-4);
+                    const float3 d = f3(Lq.x - pp.x, Lq.y - pp.y, Lq.z - pp.z);
+                    D = dot3(d, d);
+                    const float dinv = rsqrtf(D);
+                    dist = D * dinv;
+                    ld = f3(d.x * dinv, d.y * dinv, d.z * dinv);
+                    A = Lq.w * __builtin_amdgcn_rcpf(fmaxf(D, 1e-4f));
                 } else {
-                    for (int k = 0; k < 3; ++k) ld[k] = S.light_q[l][k];
-                    A = S.light_I[l];
+                    ld = f3(Lq.x, Lq.y, Lq.z);
+                    A = Lq.w;
                 }
-                const double ndl = dot3d(n, ld);
-                if (ndl > 0.0) {  // max(0, n.l) inactive: no contribution, sub-gradient 0
-                    const double hh[3] = {ld[0] + v[0], ld[1] + v[1], ld[2] + v[2]};
-                    const double H2 = dot3d(hh, hh);
-                    double s = 0.0, ndh = 0.0, hl = 0.0, h[3] = {0, 0, 0};
-                    if (H2 >= 1e-12) {
-                        hl = sqrt(H2);
-                        for (int k = 0; k < 3; ++k) h[k] = hh[k] / hl;
-                        const double c2 = dot3d(n, h);
-                        ndh = c2 > 0.0 ? c2 : 0.0;
-                        s = ndh > 0.0 ? pow(ndh, m) : 0.0;
-                    }
-                    double Gh = 0.0;
-                    for (int c = 0; c < 3; ++c) {
-                        U[c] += A * ndl * (al[c] + ks * s);
-                        Gh += gc[c] * (al[c] + ks * s);
-                    }
-                    sAnd += A * ndl;
-                    sAnds += A * ndl * s;
-                    if (ndh > 0.0) sAndsln += A * ndl * s * log(ndh);
-                    gI = e * Gh * ndl * (point ? 1.0 / (D > 1e-4 ? D : 1e-4) : 1.0);
-                    if (point) {
-                        if (D > 1e-4) {
-                            const double kk = -2.0 * S.light_I[l] / (D * D);
-                            for (int c = 0; c < 3; ++c) gq[c] += e * Gh * ndl * kk * (ld[c] * dist);
+                const float ndl = dot3(n, ld);
+                if (ndl > 0.f) {  // max(0, n.l) inactive: no contribution, sub-gradient 0
+                    const float3 hh = f3(ld.x + v.x, ld.y + v.y, ld.z + v.z);
+                    const float H2 = dot3(hh, hh);
+                    float s = 0.f, ndh = 0.f, lnh = 0.f, hinv = 0.f;
+                    float3 h = f3(0.f, 0.f, 0.f), w = f3(0.f, 0.f, 0.f);
+                    if (H2 >= 1e-12f) {
+                        hinv = rsqrtf(H2);
+                        h = f3(hh.x * hinv, hh.y * hinv, hh.z * hinv);
+                        const float3 dd = f3(n.x - h.x, n.y - h.y, n.z - h.z);
+                        const float u = 0.5f * dot3(dd, dd);  // 1 - n.h, without cancellation
+                        if (u < 1.0f) {
+                            ndh = 1.0f - u;
+                            const float l2 = log2_one_minus(u);
+                            s = m == 0.f ? 1.0f : __builtin_amdgcn_exp2f(m * l2);
+                            lnh = l2 * 0.69314718055994531f;
+                            // n - (n.h) h = (n - h) + u h
+                            w = f3(dd.x + u * h.x, dd.y + u * h.y, dd.z + u * h.z);
                         }
-                        for (int c = 0; c < 3; ++c) gq[c] += e * Gh * A * (n[c] - ndl * ld[c]) / dist;
-                        if (H2 >= 1e-12 && ndh > 0.0 && m != 0.0) {
-                            double w[3];
-                            for (int c = 0; c < 3; ++c) w[c] = n[c] - ndh * h[c];
-                            const double lw = dot3d(ld, w);
-                            const double coef = e * G * A * ndl * ks * m * pow(ndh, m - 1.0) / (hl * dist);
-                            for (int c = 0; c < 3; ++c) gq[c] += coef * (w[c] - lw * ld[c]);
+                    }
+                    const float c0 = fmaf(ks, s, al0), c1 = fmaf(ks, s, al1), c2 = fmaf(ks, s, al2);
+                    const float An = A * ndl;
+                    U0 = fmaf(An, c0, U0);
+                    U1 = fmaf(An, c1, U1);
+                    U2 = fmaf(An, c2, U2);
+                    const float Gh = gc0 * c0 + gc1 * c1 + gc2 * c2;
+                    sAnd += An;
+                    sAnds += An * s;
+                    if (ndh > 0.f) sAndsln += An * s * lnh;
+                    // n.h^(m - 1) = s / n.h; hl = |l + v| = 1 / hinv
+                    const float spec = (ndh > 0.f && m != 0.f) ? e * G * An * ks * m * (s / ndh) * hinv : 0.f;
+                    if (point) {
+                        const float Ainv = __builtin_amdgcn_rcpf(fmaxf(D, 1e-4f));
+                        gI = e * Gh * ndl * Ainv;
+                        if (D > 1e-4f) {  // d A / d q through 1 / D
+                            const float kk = e * Gh * ndl * (-2.0f * Lq.w) * Ainv * Ainv;
+                            gq0 = kk * (ld.x * dist);
+                            gq1 = kk * (ld.y * dist);
+                            gq2 = kk * (ld.z * dist);
+                        }
+                        const float dinv = 1.0f / dist;
+                        const float kn = e * Gh * A * dinv;
+                        gq0 += kn * (n.x - ndl * ld.x);
+                        gq1 += kn * (n.y - ndl * ld.y);
+                        gq2 += kn * (n.z - ndl * ld.z);
+                        if (spec != 0.f) {
+                            const float lw = dot3(ld, w), ks2 = spec * dinv;
+                            gq0 += ks2 * (w.x - lw * ld.x);
+                            gq1 += ks2 * (w.y - lw * ld.y);
+                            gq2 += ks2 * (w.z - lw * ld.z);
                         }
                     } else {
                         // directional: l = a / |a| with a = -R_V u reaches the shade through
-                        // n.l and h = (l + v) / |l + v|; dL/dl, then dL/da = (I - l l^T)
-                        // dL/dl / |a|; gq holds dL/d(R_V u) = -dL/da (rotated to world below)
-                        double gl[3];
-                        for (int c = 0; c < 3; ++c) gl[c] = e * Gh * A * n[c];
-                        if (H2 >= 1e-12 && ndh > 0.0 && m != 0.0) {
-                            const double coef = e * G * A * ndl * ks * m * pow(ndh, m - 1.0) / hl;
-                            for (int c = 0; c < 3; ++c) gl[c] += coef * (n[c] - ndh * h[c]);
-                        }
-                        const double lg = dot3d(ld, gl);
-                        for (int c = 0; c < 3; ++c) gq[c] = -(gl[c] - lg * ld[c]) / S.light_qn[l];
+                        // n.l and h = (l + v) / |l + v|; dL/da = (I - l l^T) dL/dl / |a|;
+                        // gq holds dL/d(R_V u) = -dL/da (rotated to world below)
+                        gI = e * Gh * ndl;
+                        const float kn = e * Gh * A;
+                        float3 gl = f3(kn * n.x, kn * n.y, kn * n.z);
+                        if (spec != 0.f) gl = f3(gl.x + spec * w.x, gl.y + spec * w.y, gl.z + spec * w.z);
+                        const float lg = dot3(ld, gl), qi = 1.0f / S.light_qn[l];
+                        gq0 = -(gl.x - lg * ld.x) * qi;
+                        gq1 = -(gl.y - lg * ld.y) * qi;
+                        gq2 = -(gl.z - lg * ld.z) * qi;
                     }
                 }
             }
-            const double s0 = wave_sum(gq[0]), s1 = wave_sum(gq[1]), s2 = wave_sum(gq[2]), s3 = wave_sum(gI);
+            const double s0 = wave_sum((double)gq0), s1 = wave_sum((double)gq1), s2 = wave_sum((double)gq2),
+                         s3 = wave_sum((double)gI);
             if (lane == 0) {
                 S.wacc[wave][4 * l + 0] += s0;
                 S.wacc[wave][4 * l + 1] += s1;
@@ -251,97 +244,161 @@ __global__ __launch_bounds__(kBlock) void k_grad_tile(GradArgs g) {
             }
         }
         {
-            const double se = wave_sum(gc[0] * U[0] + gc[1] * U[1] + gc[2] * U[2]);
+            const double se = wave_sum((double)gc0 * U0 + (double)gc1 * U1 + (double)gc2 * U2);
             if (lane == 0) S.wacc[wave][4 * kMaxLights] += se;
         }
         if (frag) {
-            ov[0] = e * gc[0] * sAnd;
-            ov[1] = e * gc[1] * sAnd;
-            ov[2] = e * gc[2] * sAnd;
-            ov[3] = e * G * ks * sAndsln * (-4.0 / (r * r * r));
+            ov[0] = e * gc0 * sAnd;
+            ov[1] = e * gc1 * sAnd;
+            ov[2] = e * gc2 * sAnd;
+            ov[3] = e * G * ks * sAndsln * (-4.0f / (r * r * r));
             ov[4] = e * G * sAnds;
+            S.present[obj_local] = 1;
         }
         S.pix_obj[p] = obj_local;
+#pragma unroll
         for (int k = 0; k < 5; ++k) S.pix_val[k][p] = ov[k];
-        if (obj_local >= 0) S.present[obj_local] = 1;
     }
     __syncthreads();
 
+    // compact slots of the objects present in the tile (wave 0: a scan over the flags)
+    if (wave == 0) {
+        int base = 0;
+        for (int k0 = 0; k0 < n_obj; k0 += kWave) {
+            const int k = k0 + lane;
+            const bool pr = k < n_obj && S.present[k];
+            const unsigned long long mk = __ballot(pr);
+            if (pr) {
+                const int sl = base + lanes_below(mk);
+                S.slot_of[k] = sl;
+                if (sl < kGPresent) S.slot_obj[sl] = k;
+            }
+            base += __popcll(mk);
+        }
+        if (lane == 0) S.n_present = base;
+    }
+    __syncthreads();
+    const int n_present = S.n_present;
     double *part = g.partial + g.gitem_pbase[blockIdx.x];
-    // objects present in the tile: fixed-order masked sums; absent ones get zeros
-    for (int k = 0; k < n_obj; ++k) {
-        if (!S.present[k]) {
-            if (tid < 5) part[5 * k + tid] = 0.0;
-            continue;
-        }
-        double v5[5] = {0, 0, 0, 0, 0};
+    if (n_present <= kGPresent) {
+        // each wave adds its pixels (rows of 64 in order) per distinct object
         for (int q = 0; q < kGPer; ++q) {
-            const int p = tid + kBlock * q;
-            if (S.pix_obj[p] == k)
-                for (int c = 0; c < 5; ++c) v5[c] += S.pix_val[c][p];
+            const int p = wave * kWave + lane + kBlock * q;
+            const int k = S.pix_obj[p];
+            unsigned long long pend = __ballot(k >= 0);
+            while (pend) {
+                const int k0 = __builtin_amdgcn_readlane(k, __builtin_ctzll(pend));
+                const bool mine = k == k0;
+                pend &= ~__ballot(mine);
+                const int sl = S.slot_of[k0];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const double x = wave_sum(mine ? (double)S.pix_val[c][p] : 0.0);
+                    if (lane == 0) S.oacc[wave][sl][c] += x;
+                }
+            }
         }
-        block_sum5(v5, S);
-        if (tid < 5) part[5 * k + tid] = v5[tid];
+        __syncthreads();
+        for (int k = tid; k < 5 * n_obj; k += kBlock) {
+            const int o = k / 5, c = k - 5 * o;
+            double x = 0.0;
+            if (S.present[o]) {
+                const int sl = S.slot_of[o];
+                for (int w = 0; w < kGWaves; ++w) x += S.oacc[w][sl][c];
+            }
+            part[k] = x;
+        }
+    } else {
+        // many objects in one tile: each present object in turn, every wave, then in order
+        for (int k = 0; k < n_obj; ++k) {
+            if (!S.present[k]) {
+                if (tid < 5) part[5 * k + tid] = 0.0;
+                continue;
+            }
+            for (int q = 0; q < kGPer; ++q) {
+                const int p = wave * kWave + lane + kBlock * q;
+                const bool mine = S.pix_obj[p] == k;
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const double x = wave_sum(mine ? (double)S.pix_val[c][p] : 0.0);
+                    if (lane == 0) S.oacc[wave][0][c] += x;
+                }
+            }
+            __syncthreads();
+            if (tid < 5) {
+                double x = 0.0;
+                for (int w = 0; w < kGWaves; ++w) x += S.oacc[w][0][tid];
+                part[5 * k + tid] = x;
+            }
+            __syncthreads();
+            if (tid < kGWaves * 5) (&S.oacc[0][0][0])[(tid / 5) * kGPresent * 5 + tid % 5] = 0.0;
+            __syncthreads();
+        }
     }
     // lights (view -> world: dL/dq_world = R_V^T dL/dq_view) and exposure: waves summed in order
     double *lp = part + 5 * n_obj;
     if (tid < nl) {
         const int l = tid;
         double gv[4] = {0, 0, 0, 0};
-        for (int w = 0; w < kBlock / kWave; ++w)
+        for (int w = 0; w < kGWaves; ++w)
             for (int c = 0; c < 4; ++c) gv[c] += S.wacc[w][4 * l + c];
-        // dq_world = R_V^T dq_view
         for (int c = 0; c < 3; ++c)
             lp[4 * l + c] = (double)V[0 * 4 + c] * gv[0] + (double)V[1 * 4 + c] * gv[1] + (double)V[2 * 4 + c] * gv[2];
         lp[4 * l + 3] = gv[3];
     }
     if (tid == kBlock - 1) {
         double se = 0.0;
-        for (int w = 0; w < kBlock / kWave; ++w) se += S.wacc[w][4 * kMaxLights];
+        for (int w = 0; w < kGWaves; ++w) se += S.wacc[w][4 * kMaxLights];
         lp[4 * nl] = se;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_grad_reduce(GradArgs g) {
-    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t n_obj_p = 5 * (int64_t)g.n_objects, n_light_p = 4 * (int64_t)g.n_lights;
-    if (idx >= n_obj_p + n_light_p + g.n_frames) return;
-    int scene, slot, f_only = -1;
-    if (idx < n_obj_p) {
-        const int o = (int)(idx / 5), k = (int)(idx % 5);
-        scene = g.obj_scene[o];
-        slot = 5 * g.obj_local[o] + k;
-    } else if (idx < n_obj_p + n_light_p) {
-        const int l = (int)((idx - n_obj_p) / 4), k = (int)((idx - n_obj_p) % 4);
-        scene = g.light_scene[l];
-        slot = -1 - (4 * g.light_local[l] + k);  // relative to the light block
-    } else {
-        f_only = (int)(idx - n_obj_p - n_light_p);
-        scene = g.r.frames[f_only].scene;
-        slot = 0;
-    }
+// Grid: x over 64-parameter chunks, y over scenes.  A scene's parameters: 5 per object,
+// 4 per light, then 1 per frame (its exposure).  Wave w sums the scene's tile partials
+// t = w, w + 4, ... in order; the four results are added in order.
+__global__ __launch_bounds__(kBlock) void k_grad_reduce(GradArgs g, int s_base) {
+    __shared__ double red[kGWaves][kGChunk];
+    const int sc = s_base + (int)blockIdx.y;
+    const int ob = g.scene_obj_begin[sc], no = g.scene_obj_begin[sc + 1] - ob;
+    const int lb = g.scene_light_begin[sc], nl = g.scene_light_begin[sc + 1] - lb;
+    const int fb = g.scene_frame_begin[sc], nf = g.scene_frame_begin[sc + 1] - fb;
+    const int n_par = 5 * no + 4 * nl + nf;
+    const int p = blockIdx.x * kGChunk + lane_id(), wave = threadIdx.x / kWave;
+    if (blockIdx.x * kGChunk >= n_par) return;  // whole block past the scene's parameters
     double acc = 0.0;
-    for (int fk = g.scene_frame_begin[scene]; fk < g.scene_frame_begin[scene + 1]; ++fk) {
-        const int f = g.scene_frames[fk];
-        if (f_only >= 0 && f != f_only) continue;
-        const FrameInfo fi = g.r.frames[f];
-        int off;
-        if (f_only >= 0) off = 5 * fi.n_obj + 4 * fi.n_lights;
-        else if (slot >= 0) off = slot;
-        else off = 5 * fi.n_obj + (-1 - slot);
-        for (int it = g.frame_item_begin[f]; it < g.frame_item_begin[f + 1]; ++it) acc += g.partial[g.gitem_pbase[it] + off];
+    if (p < n_par) {
+        int off, f_only = -1;
+        if (p < 5 * no) off = p;
+        else if (p < 5 * no + 4 * nl) off = p;  // lights follow the objects in every tile's vector
+        else f_only = g.scene_frames[fb + (p - 5 * no - 4 * nl)], off = 5 * no + 4 * nl;
+        int t = 0;  // the tile's position in the scene's list
+        for (int fk = 0; fk < nf; ++fk) {
+            const int f = g.scene_frames[fb + fk];
+            const int i0 = g.frame_item_begin[f], i1 = g.frame_item_begin[f + 1];
+            if (f_only >= 0 && f != f_only) {
+                t += i1 - i0;
+                continue;
+            }
+            for (int it = i0; it < i1; ++it, ++t)
+                if ((t & (kGWaves - 1)) == wave) acc += g.partial[g.gitem_pbase[it] + off];
+        }
     }
-    if (idx < n_obj_p) {
-        const int o = (int)(idx / 5), k = (int)(idx % 5);
-        if (k < 3) g.g_albedo[3 * o + k] = (float)acc;
-        else if (k == 3) g.g_rough[o] = (float)acc;
-        else g.g_spec[o] = (float)acc;
-    } else if (idx < n_obj_p + n_light_p) {
-        const int l = (int)((idx - n_obj_p) / 4), k = (int)((idx - n_obj_p) % 4);
-        if (k < 3) g.g_lpos[3 * l + k] = (float)acc;
-        else g.g_lint[l] = (float)acc;
+    red[wave][lane_id()] = acc;
+    __syncthreads();
+    if (wave != 0 || p >= n_par) return;
+    double x = 0.0;
+    for (int w = 0; w < kGWaves; ++w) x += red[w][lane_id()];
+    if (p < 5 * no) {
+        const int o = ob + p / 5, k = p % 5;
+        if (k < 3) g.g_albedo[3 * o + k] = (float)x;
+        else if (k == 3) g.g_rough[o] = (float)x;
+        else g.g_spec[o] = (float)x;
+    } else if (p < 5 * no + 4 * nl) {
+        const int l = lb + (p - 5 * no) / 4, k = (p - 5 * no) % 4;
+        if (k < 3) g.g_lpos[3 * l + k] = (float)x;
+        else g.g_lint[l] = (float)x;
     } else {
-        g.g_expo[f_only] = (float)acc;
+        g.g_expo[g.scene_frames[fb + (p - 5 * no - 4 * nl)]] = (float)x;
     }
 }
 
@@ -353,9 +410,11 @@ hipError_t launch_grad(const GradArgs &g, hipStream_t stream) {
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const int64_t n = 5 * (int64_t)g.n_objects + 4 * (int64_t)g.n_lights + g.n_frames;
-    if (n > 0) {
-        hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, g);
+    const int chunks = (g.max_scene_params + kGChunk - 1) / kGChunk;
+    constexpr int kMaxY = 32768;  // scenes per launch (grid y)
+    for (int s0 = 0; s0 < g.n_scenes && e == hipSuccess; s0 += kMaxY) {
+        const int ns = g.n_scenes - s0 < kMaxY ? g.n_scenes - s0 : kMaxY;
+        hipLaunchKernelGGL(k_grad_reduce, dim3(chunks > 0 ? chunks : 1, ns), dim3(kBlock), 0, stream, g, s0);
         e = hipGetLastError();
     }
     return e;

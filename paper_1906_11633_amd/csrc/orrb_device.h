@@ -122,8 +122,10 @@ struct GradArgs {
     const int32_t *scene_frames, *scene_frame_begin;  // frames of each scene (CSR)
     const int32_t *frame_item_begin;                  // [F+1] item range of each frame
     const int32_t *obj_scene, *obj_local, *light_scene, *light_local;
+    const int32_t *scene_obj_begin, *scene_light_begin;  // [S+1] each
     float *g_albedo, *g_rough, *g_spec, *g_lpos, *g_lint, *g_expo;
     int32_t n_objects, n_lights, n_frames;
+    int32_t n_scenes, max_scene_params;  // parameters of a scene: 5 per object, 4 per light, 1 per frame
 };
 
 // launchers (defined in orrb_kernels.hip and orrb_adjoint.hip)

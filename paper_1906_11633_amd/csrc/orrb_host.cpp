@@ -90,7 +90,8 @@ struct ScopedDevice {
     int prev = -1;
     explicit ScopedDevice(int dev) {
         if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
+        // a failed switch must not leave its error for the caller's next HIP call
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) (void)hipGetLastError();
     }
     ~ScopedDevice() {
         int cur = -1;
@@ -154,6 +155,7 @@ struct orrb_context {
     std::vector<int4> tex_info;
     DevBuf d_uv, d_texels, d_tex_info;
     int n_layouts = 0;
+    bool destroy_pending = false;  // orrb_destroy called while layouts were alive: freed with the last one
     uint64_t generation = 0;  // bumped whenever the mesh pool grows (its buffers may move)
 };
 
@@ -193,7 +195,8 @@ struct orrb_layout {
     std::vector<int2> vitems_all, gitems;
     std::vector<int64_t> gitem_pbase;
     std::vector<int32_t> frame_item_begin, scene_frame_begin, scene_frames, obj_scene, obj_local, light_scene,
-        light_local;
+        light_local, scene_obj_begin, scene_light_begin;
+    int max_scene_params = 0;
     uint64_t signature = 0;  // hash of the batch structure (autotuner cache key)
     uint64_t generation = 0; // bumped whenever the tuning or the device tables change
     int64_t grad_partials = 0;
@@ -202,7 +205,7 @@ struct orrb_layout {
     Packed gtab;
     size_t g_frames_all = 0, g_vitems_all = 0, g_gitems = 0, g_gitem_pbase = 0, g_frame_item_begin = 0,
            g_scene_frame_begin = 0, g_scene_frames = 0, g_obj_scene = 0, g_obj_local = 0, g_light_scene = 0,
-           g_light_local = 0;
+           g_light_local = 0, g_scene_obj_begin = 0, g_scene_light_begin = 0;
 };
 
 // --------------------------------------------------------------------------------------
@@ -449,6 +452,13 @@ static void build_grad_tables(orrb_layout *L, const orrb_layout_desc *d) {
         }
         L->max_scene_objects = std::max(L->max_scene_objects, d->scene_object_begin[s + 1] - d->scene_object_begin[s]);
     }
+    L->scene_obj_begin.assign(d->scene_object_begin, d->scene_object_begin + S + 1);
+    L->scene_light_begin.assign(d->scene_light_begin, d->scene_light_begin + S + 1);
+    for (int s = 0; s < S; ++s)
+        L->max_scene_params = std::max(L->max_scene_params,
+                                       5 * (d->scene_object_begin[s + 1] - d->scene_object_begin[s]) +
+                                           4 * (d->scene_light_begin[s + 1] - d->scene_light_begin[s]) +
+                                           (L->scene_frame_begin[s + 1] - L->scene_frame_begin[s]));
 }
 
 static orrb_status upload_grad_tables(orrb_layout *L) {
@@ -466,6 +476,8 @@ static orrb_status upload_grad_tables(orrb_layout *L) {
     L->g_obj_local = P.add(L->obj_local);
     L->g_light_scene = P.add(L->light_scene);
     L->g_light_local = P.add(L->light_local);
+    L->g_scene_obj_begin = P.add(L->scene_obj_begin);
+    L->g_scene_light_begin = P.add(L->scene_light_begin);
     HIP_TRY(P.upload());
     L->grad_ready = true;
     return ORRB_OK;
@@ -585,6 +597,10 @@ orrb_status orrb_create(int hip_device, orrb_context **out) {
 
 void orrb_destroy(orrb_context *ctx) {
     if (!ctx) return;
+    if (ctx->n_layouts > 0) {  // layouts still point into the pool: free it with the last of them
+        ctx->destroy_pending = true;
+        return;
+    }
     ScopedDevice sd(ctx->device);
     delete ctx;
 }
@@ -881,10 +897,12 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
 
 void orrb_layout_destroy(orrb_layout *L) {
     if (!L) return;
-    ScopedDevice sd(L->ctx->device);
+    orrb_context *ctx = L->ctx;
+    ScopedDevice sd(ctx->device);
     if (L->shadow) orrb_layout_destroy(L->shadow);
-    L->ctx->n_layouts--;
+    ctx->n_layouts--;
     delete L;
+    if (ctx->destroy_pending && ctx->n_layouts == 0) delete ctx;
 }
 
 orrb_status orrb_layout_info_get(const orrb_layout *L, orrb_layout_info *info) {
@@ -1130,6 +1148,10 @@ orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const o
     g.n_objects = (int32_t)L->n_objects;
     g.n_lights = (int32_t)L->n_lights;
     g.n_frames = (int32_t)L->n_frames;
+    g.scene_obj_begin = L->gtab.at<int32_t>(L->g_scene_obj_begin);
+    g.scene_light_begin = L->gtab.at<int32_t>(L->g_scene_light_begin);
+    g.n_scenes = (int32_t)L->n_scenes;
+    g.max_scene_params = L->max_scene_params;
     ScopedDevice sd(ctx->device);
     const hipError_t e = launch_grad(g, (hipStream_t)stream);
     if (e != hipSuccess) return fail(ORRB_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));

@@ -297,9 +297,10 @@ ORRB_INLINE float3 rotate_normal(const float *R, float4 q) {
 // u < 1/16, where forming 1 - u would lose the low bits of u, and from the hardware
 // log2 otherwise (1 - u is then within 2^-25 of exact).  Against the exact power the
 // error stays below 3e-7 absolute and, where the power exceeds 1e-5, 1e-5 relative.
-ORRB_INLINE float spec_pow(float u, float m) {
+// log2(1 - u) for 0 <= u < 1, as spec_pow forms it (series below 1/16).
+ORRB_INLINE float log2_one_minus(float u) {
 #pragma clang fp contract(off)
-    float l2;  // log2(1 - u)
+    float l2;
     if (u < 0.0625f) {
         float p = fmaf(u, 1.0f / 7.0f, 1.0f / 6.0f);
         p = fmaf(u, p, 0.2f);
@@ -311,7 +312,12 @@ ORRB_INLINE float spec_pow(float u, float m) {
     } else {
         l2 = __builtin_amdgcn_logf(1.0f - u);
     }
-    return __builtin_amdgcn_exp2f(m * l2);
+    return l2;
+}
+
+ORRB_INLINE float spec_pow(float u, float m) {
+#pragma clang fp contract(off)
+    return __builtin_amdgcn_exp2f(m * log2_one_minus(u));
 }
 
 // A pixel's material inputs beyond the LDS material (textured / emissive shading):
