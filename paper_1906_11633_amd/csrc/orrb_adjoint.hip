@@ -45,11 +45,30 @@ struct GradLds {
     int n_present;
 };
 
-// Sum over the wave (fixed butterfly order).
+// Shift of a double across lanes by a DPP control (both halves moved alike; lanes
+// without a source get 0.0).
+template <int CTRL, int ROW_MASK>
+ORRB_INLINE double dpp_d(double x) {
+    const unsigned long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the wave in a fixed order: an inclusive DPP scan (shifts by 1, 2, 4, 8 in
+// each 16-lane row, then rows 0 -> 1, 2 -> 3 and 1 -> 2, 3), whose last lane holds the
+// total, broadcast to every lane.  No LDS round trips.
 ORRB_INLINE double wave_sum(double x) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
-    return x;
+    x += dpp_d<0x111, 0xf>(x);
+    x += dpp_d<0x112, 0xf>(x);
+    x += dpp_d<0x114, 0xf>(x);
+    x += dpp_d<0x118, 0xf>(x);
+    x += dpp_d<0x142, 0xa>(x);
+    x += dpp_d<0x143, 0xc>(x);
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, kWave - 1);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), kWave - 1);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 __global__ __launch_bounds__(kBlock) void k_grad_tile(GradArgs g) {
