@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kPostBlock) void k_post(RenderArgs a, int f_base) {
 hipError_t launch_post(const RenderArgs &a, hipStream_t stream, int n_frames, int64_t max_frame_pixels) {
     if (n_frames <= 0 || !a.out_rgb8) return hipSuccess;
     const int64_t per_block = (int64_t)kPostBlock * kPostPix;
-    const int64_t gx = std::min<int64_t>((max_frame_pixels + per_block - 1) / per_block, 8);
+    const int64_t gx = (max_frame_pixels + per_block - 1) / per_block;  // one 1024-pixel chunk per block
     constexpr int kMaxY = 32768;  // frames per launch (grid y)
     for (int f0 = 0; f0 < n_frames; f0 += kMaxY) {
         const int nf = min(kMaxY, n_frames - f0);

@@ -509,20 +509,27 @@ ORRB_INLINE void track_init(orrb_track *t, double e0, double e1, double e2, doub
     *t = r;
 }
 
+// Reductions over the wave by an inclusive DPP scan (shifts by 1, 2, 4, 8 inside each
+// 16-lane row, then rows 0 -> 1, 2 -> 3 and 1 -> 2, 3; lanes without a source take the
+// identity); the last lane holds the result, which every lane receives.
+template <class Op>
+ORRB_INLINE int wave_reduce(int v, int identity, Op op) {
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x111, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x112, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x114, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x118, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x142, 0xa, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x143, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, kWave - 1);
+}
 ORRB_INLINE int wave_min(int v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
+    return wave_reduce(v, 0x7fffffff, [](int x, int y) { return min(x, y); });
 }
 ORRB_INLINE int wave_max(int v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
+    return wave_reduce(v, -0x7fffffff - 1, [](int x, int y) { return max(x, y); });
 }
 ORRB_INLINE unsigned wave_sum(unsigned v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += (unsigned)__shfl_xor((int)v, o);
-    return v;
+    return (unsigned)wave_reduce((int)v, 0, [](int x, int y) { return (int)((unsigned)x + (unsigned)y); });
 }
 
 // Add the wave's pixels to their tracker records: lane L holds pixel (i, j) of record
