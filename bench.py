@@ -185,21 +185,15 @@ def measure_materials(args, r, S, torch):
                 textures=len(b.textures), ms_per_step=round(dt * 1e3, 4), frames_per_s=round(b.n_frames / dt, 1))
 
 
-def measure_extras(args, r, S):
-    """Shading-gradient throughput (64 scenes x 3 cameras at 200x200), the serving loop
-    (Poisson 2000 req/s of 1-32 scenes at 64/128/200 px), and the uneven batch (1024
-    scenes, 64-256 px, 2k-50k triangles) autotuned and replayed from a HIP graph
-    against its one-scene-per-launch form."""
+def measure_grad(args, r, S):
+    """Shading-gradient throughput: 64 scenes x 3 cameras at 200x200."""
     import torch
-    import oracle
-    from paper_1906_11633_amd.renderer import Graph, Layout, autotune, render_batch, shade_backward
-    from paper_1906_11633_amd.serving import ScenePool, Server, poisson_trace
+    from paper_1906_11633_amd.renderer import shade_backward
     ex = {}
-    # shading gradient
     base, target = S.config4(4, 64, 200)
     job = r.prepare(base)
     out = r.render(job, vis=True)
-    tgt = torch.from_numpy(oracle.render(target)["rgb"].astype("float32")).cuda()
+    tgt = r.render(r.prepare(target))["rgb"]  # the target image, rendered by the same kernels
     grad_rgb = (2.0 * (out["rgb"] - tgt)).contiguous()
     ws = torch.empty(int(job.layout.info.grad_workspace_bytes), dtype=torch.uint8, device="cuda")
     step = lambda: shade_backward(r.ctx, job.layout, job.state, out["vis"], grad_rgb, ws)
@@ -217,8 +211,13 @@ def measure_extras(args, r, S):
                                             peak=HBM_PEAK_GBS, unit="GB/s",
                                             frac=round(gbytes / (gms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
     print(f"[bench] backward {dt * 1e3:.3f} ms for {base.n_frames} frames", file=sys.stderr, flush=True)
-    del job, out, grad_rgb, ws
-    # serving
+    return ex
+
+
+def measure_serving(args, r, S):
+    """The serving loop: Poisson 2000 req/s of 1-32 scenes at 64/128/200 px."""
+    from paper_1906_11633_amd.serving import ScenePool, Server, poisson_trace
+    ex = {}
     pool = ScenePool(r.ctx, 256)
     warm = Server(r.ctx, pool)
     warm.run(poisson_trace(pool, 2000.0, 0.3, seed=99))
@@ -231,26 +230,13 @@ def measure_extras(args, r, S):
     ex["serving"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
     ex["serving"].update(rate_req_per_s=2000.0, budget_gb=64, warmup_s=1.0, measured_s=args.serving_seconds)
     print(f"[bench] serving p50 {st['p50_ms']:.3f} ms p99 {st['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
-    del srv, warm, pool
-    # uneven batch: autotuned, one graph replay per step, vs one scene per launch
-    b3 = S.config3(3, 1024)
-    job3 = r.prepare(b3)
-    out3 = r.alloc_outputs(job3)
-    tuning, _ = autotune(r.ctx, job3.layout, job3.state, out3, job3.workspace)
-    inf3 = job3.layout.info
-    # kernels one render of this layout launches: the frame kernel for frames on the
-    # frame path, the vertex and raster kernels for any on the tiled path
-    g_nodes = (1 if inf3.frame_path_frames > 0 else 0) + (2 if inf3.tile_items > 0 else 0)
-    stream = torch.cuda.Stream()
-    g = Graph(r.ctx, job3.layout, job3.state, out3, job3.workspace, stream)
-    with torch.cuda.stream(stream):
-        for _ in range(3):
-            g.replay(stream)
-        dt3 = _timed(lambda: g.replay(stream), 20, torch)
-        ev3 = _event_times(lambda: g.replay(stream), 20, torch, stream)
-    g.close()
-    bytes3 = BYTES_PER_PIXEL * b3.total_pixels
-    ms3 = sorted(ev3)[len(ev3) // 2]
+    return ex
+
+
+def _uneven_plain(r, b3, job3, out3):
+    """Seconds per pass of the uneven batch rendered one scene (3 frames) per launch."""
+    import torch
+    from paper_1906_11633_amd.renderer import Layout, render_batch
     plain = []
     st3 = job3.state
     po = b3.pixel_offset
@@ -270,16 +256,46 @@ def measure_extras(args, r, S):
         plain.append((Layout(r.ctx, b3.select_scenes([s])), sst, sout))
     run_plain = lambda: [render_batch(r.ctx, lay, sst, sout, job3.workspace) for lay, sst, sout in plain]
     run_plain()
-    dtp = _timed(run_plain, 3, torch)
+    return _timed(run_plain, 3, torch)
+
+
+def measure_uneven(args, r, S):
+    """The uneven batch (1024 scenes, 64-256 px, 2k-50k triangles) autotuned and
+    replayed from a HIP graph, against its one-scene-per-launch form (unless
+    --no-plain)."""
+    import torch
+    from paper_1906_11633_amd.renderer import Graph, Layout, autotune, render_batch
+    ex = {}
+    b3 = S.config3(3, 1024)
+    job3 = r.prepare(b3)
+    out3 = r.alloc_outputs(job3)
+    tuning, _ = autotune(r.ctx, job3.layout, job3.state, out3, job3.workspace)
+    inf3 = job3.layout.info
+    # kernels one render of this layout launches: the frame kernel for frames on the
+    # frame path, the vertex and raster kernels for any on the tiled path
+    g_nodes = (1 if inf3.frame_path_frames > 0 else 0) + (2 if inf3.tile_items > 0 else 0)
+    stream = torch.cuda.Stream()
+    g = Graph(r.ctx, job3.layout, job3.state, out3, job3.workspace, stream)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            g.replay(stream)
+        dt3 = _timed(lambda: g.replay(stream), 20, torch)
+        ev3 = _event_times(lambda: g.replay(stream), 20, torch, stream)
+    g.close()
+    bytes3 = BYTES_PER_PIXEL * b3.total_pixels
+    ms3 = sorted(ev3)[len(ev3) // 2]
+    dtp = None if args.no_plain else _uneven_plain(r, b3, job3, out3)
     ex["uneven_batch"] = dict(frames=b3.n_frames, pixels=b3.total_pixels, tuning=list(tuning),
                               ms_per_step=round(dt3 * 1e3, 3), frames_per_s=round(b3.n_frames / dt3, 1),
                               hbm_frac=round(bytes3 / dt3 / 1e9 / HBM_PEAK_GBS, 4),
-                              plain_frames_per_s=round(b3.n_frames / dtp, 1), batched_over_plain=round(dtp / dt3, 2),
+                              plain_frames_per_s=round(b3.n_frames / dtp, 1) if dtp else None,
+                              batched_over_plain=round(dtp / dt3, 2) if dtp else None,
                               graph_kernel_nodes=g_nodes, event_ms_median=_pct(ev3, 50), event_ms_p90=_pct(ev3, 90),
                               roofline=dict(bound="hbm", kernel="graph replay", bytes_per_call=bytes3,
                                             achieved=round(bytes3 / (ms3 * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS,
                                             unit="GB/s", frac=round(bytes3 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)))
-    print(f"[bench] uneven batch {dt3 * 1e3:.3f} ms/step (graph), plain {dtp * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    print(f"[bench] uneven batch {dt3 * 1e3:.3f} ms/step (graph)" + (f", plain {dtp * 1e3:.3f} ms" if dtp else ""),
+          file=sys.stderr, flush=True)
     return ex
 
 
@@ -296,6 +312,8 @@ def main(argv=None):
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient, serving and uneven-batch parts")
     ap.add_argument("--serving-seconds", type=float, default=10.0)
+    ap.add_argument("--only", choices=["grad", "serving", "uneven", "aux", "materials", "shadows"],
+                    help="run only this part and print its JSON (for profiling one kernel's workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB 5 times (counter calibration)")
     args = ap.parse_args(argv)
@@ -321,6 +339,12 @@ def main(argv=None):
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "launches": 5}), flush=True)
+        return 0
+    if args.only in ("grad", "serving", "uneven", "materials", "shadows"):
+        part = dict(grad=measure_grad, serving=measure_serving, uneven=measure_uneven,
+                    materials=lambda a, r, S: dict(materials=measure_materials(a, r, S, torch)),
+                    shadows=lambda a, r, S: dict(spot_shadows=measure_shadows(a, r, S, torch)))[args.only]
+        print(json.dumps(part(args, Renderer(0), S)), flush=True)
         return 0
     t_gen = time.perf_counter()
     batch = S.config2(2, args.scenes, args.res)
@@ -396,6 +420,9 @@ def main(argv=None):
     extra["store_ceiling_gbs"] = round(bytes_per_launch / (fms * 1e-3) / 1e9, 1)
     extra["store_ceiling_frac"] = round(bytes_per_launch / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     extra["aux_outputs"] = measure_aux(args, r, S, batch, job, torch, kernel_ms["k_frame"])
+    if args.only == "aux":
+        print(json.dumps(dict(aux_outputs=extra["aux_outputs"])), flush=True)
+        return 0
     print(f"[bench] with alpha, tracker and rgb8: {extra['aux_outputs']['ms_per_step']:.3f} ms/step, "
           f"k_post {extra['aux_outputs']['k_post']['ms']:.3f} ms", file=sys.stderr, flush=True)
     extra["materials"] = measure_materials(args, r, S, torch)
@@ -458,7 +485,8 @@ def main(argv=None):
         extra["batched_over_plain"] = round(value / plain_fps, 2)
 
     if not args.no_extras:
-        extra.update(measure_extras(args, r, S))
+        for part in (measure_grad, measure_serving, measure_uneven):
+            extra.update(part(args, r, S))
 
     cpu = None
     if not args.no_cpu_baseline:
