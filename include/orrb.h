@@ -208,7 +208,8 @@ typedef struct {                  /* sampled randomization parameters */
      * grading and grain; used only when orrb_outputs.rgb8 is set).  `post` [F,
      * ORRB_POST_WORDS] per frame, words ORRB_POST_*; NULL = identity grading, no grain.
      * `grain` [3, grain_h, grain_w] noise texture with values in [0, 1) (NULL = no
-     * grain).  Per channel c of pixel (i, j), from the linear rgb:
+     * grain; at most 2^26 texels per plane, else ORRB_ERR_INVALID_ARGUMENT).  Per
+     * channel c of pixel (i, j), from the linear rgb:
      *   1. white balance: c *= (1 + T/5, 1 - G/5, 1 - T/5)[c];
      *   2. clamp to [0, 1] and encode with the sRGB transfer function (IEC 61966-2-1);
      *   3. c = 1/2 + k (Y + s (c - Y) - 1/2), Y = Rec. 709 luma of the encoded pixel;

@@ -1033,8 +1033,10 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
         a.shadow_res = L->shadow_res;
     }
     if (out->rgb8 && !out->rgb) return fail(ORRB_ERR_INVALID_ARGUMENT, "rgb8 needs the rgb destination");
-    if (out->rgb8 && par->grain && (par->grain_w < 1 || par->grain_h < 1))
-        return fail(ORRB_ERR_INVALID_ARGUMENT, "grain texture size %d x %d", par->grain_w, par->grain_h);
+    if (out->rgb8 && par->grain &&
+        (par->grain_w < 1 || par->grain_h < 1 || (int64_t)par->grain_w * par->grain_h > (int64_t)1 << 26))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "grain texture size %d x %d (1 .. 2^26 texels per plane)",
+                    par->grain_w, par->grain_h);
     char *ws = (char *)workspace;
     a.vtx_pos = (int4 *)(ws + w.vtx_pos);
     a.obj_rot = (float4 *)(ws + w.obj_rot);

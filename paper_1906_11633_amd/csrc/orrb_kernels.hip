@@ -432,7 +432,10 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
                     j = ty0 + lj;
                 }
             }
-            track_wave(a.out_track, rec, i, j);
+            if (fi.width <= 1024 && fi.height <= 1024)
+                track_wave<true>(a.out_track, rec, i, j);
+            else
+                track_wave<false>(a.out_track, rec, i, j);
         }
     }
 }
@@ -1466,7 +1469,7 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
                     pi = x0 + (int)((unsigned)p % kFTileW);
                     pj = y0 + (int)((unsigned)p / kFTileW);
                 }
-                track_wave(a.out_track, rec, pi, pj);
+                track_wave<true>(a.out_track, rec, pi, pj);  // frames of at most 256 x 256
             }
         }
 

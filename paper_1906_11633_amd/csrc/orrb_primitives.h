@@ -532,27 +532,48 @@ ORRB_INLINE unsigned wave_sum(unsigned v) {
     return (unsigned)wave_reduce((int)v, 0, [](int x, int y) { return (int)((unsigned)x + (unsigned)y); });
 }
 
+// Two 16-bit lanes of a 32-bit value, reduced pairwise (v_pk_min_u16 / v_pk_max_u16).
+typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
+ORRB_INLINE int pk_min_u16(int x, int y) {
+    return __builtin_bit_cast(int, __builtin_elementwise_min(__builtin_bit_cast(ushort2v, x), __builtin_bit_cast(ushort2v, y)));
+}
+ORRB_INLINE int pk_max_u16(int x, int y) {
+    return __builtin_bit_cast(int, __builtin_elementwise_max(__builtin_bit_cast(ushort2v, x), __builtin_bit_cast(ushort2v, y)));
+}
+
 // Add the wave's pixels to their tracker records: lane L holds pixel (i, j) of record
-// `rec` (-1: none).  Must be called with every lane of the wave active.  One group of
-// global atomics per distinct record in the wave; integer min / max / sums, so the
-// result does not depend on the order of waves or tiles.
+// `rec` (-1: none), 0 <= i, j < 65536.  Must be called with every lane of the wave
+// active.  One group of global atomics per distinct record in the wave; integer min /
+// max / sums, so the result does not depend on the order of waves or tiles.  The
+// column and row travel packed as i | j << 16: their minima and maxima reduce as 16-bit
+// pairs, and so do their sums when NARROW (i, j < 1024: 64 lanes sum below 2^16).
+template <bool NARROW>
 ORRB_INLINE void track_wave(orrb_track *base, int rec, int i, int j) {
     unsigned long long pend = __ballot(rec >= 0);
+    const int ij = (int)((unsigned)i | ((unsigned)j << 16));
     while (pend) {
         const int first = __builtin_ctzll(pend);
         const int r0 = __builtin_amdgcn_readlane(rec, first);
         const bool mine = rec == r0;
         const unsigned long long m = __ballot(mine);
-        const int imin = wave_min(mine ? i : 0x7fffffff), jmin = wave_min(mine ? j : 0x7fffffff);
-        const int imax = wave_max(mine ? i : -1), jmax = wave_max(mine ? j : -1);
-        const unsigned si = wave_sum(mine ? (unsigned)i : 0u), sj = wave_sum(mine ? (unsigned)j : 0u);
+        const unsigned mn = (unsigned)wave_reduce(mine ? ij : -1, -1, pk_min_u16);
+        const unsigned mx = (unsigned)wave_reduce(mine ? ij : 0, 0, pk_max_u16);
+        unsigned si, sj;
+        if constexpr (NARROW) {
+            const unsigned s2 = wave_sum(mine ? (unsigned)ij : 0u);
+            si = s2 & 0xffffu;
+            sj = s2 >> 16;
+        } else {
+            si = wave_sum(mine ? (unsigned)i : 0u);
+            sj = wave_sum(mine ? (unsigned)j : 0u);
+        }
         if (lane_id() == first) {
             orrb_track *t = base + r0;
             atomicAdd(&t->count, (int)__popcll(m));
-            atomicMin(&t->i_min, imin);
-            atomicMin(&t->j_min, jmin);
-            atomicMax(&t->i_max, imax);
-            atomicMax(&t->j_max, jmax);
+            atomicMin(&t->i_min, (int)(mn & 0xffffu));
+            atomicMin(&t->j_min, (int)(mn >> 16));
+            atomicMax(&t->i_max, (int)(mx & 0xffffu));
+            atomicMax(&t->j_max, (int)(mx >> 16));
             atomicAdd((unsigned long long *)&t->sum_i, (unsigned long long)si);
             atomicAdd((unsigned long long *)&t->sum_j, (unsigned long long)sj);
         }

@@ -137,6 +137,16 @@ def test_rgb8_unaligned_sizes_identity_and_no_grain(renderer):
     assert np.array_equal(plain[ok].astype(np.uint8), gpu["rgb8"][ok])
 
 
+def test_rgb8_grain_on_unaligned_widths(renderer):
+    """Grain on 77-pixel-wide frames: four-pixel groups that span two rows, so the
+    grain texel is recomputed inside a group."""
+    b = S.with_postprocessing(S.config2(3, 2, 77), seed=7)
+    assert (b.post[:, 5] > 0).all() and (b.post[:, 7] > 1).any()
+    gpu = _render(renderer, b)
+    ref = oracle.render(b)
+    _check_rgb8(b, gpu, ref)
+
+
 def test_outputs_bit_identical_across_tunings(renderer):
     b = S.with_postprocessing(S.config2(4, 2, 96), seed=2)
     base = _render(renderer, b)
