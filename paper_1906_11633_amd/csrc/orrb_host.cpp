@@ -222,7 +222,8 @@ struct WsLayout {
 
 // Global scratch of the frame kernel for frames whose scene data do not fit in LDS:
 // one slice per workgroup (grid = min(frames, CUs)) with the largest such scene's
-// snapped vertices (12 B each), a survivor entry per triangle (4 B) and
+// snapped vertices (16 B each: X, Y, 1/w and padding, one load), a survivor entry per
+// triangle (4 B) and
 // bin_cap / 128 16-bit bin entries per triangle (at least 4096).
 struct FrameScratch {
     int64_t grid = 0, verts = 0, surv = 0, bins = 0;
@@ -236,7 +237,7 @@ static FrameScratch frame_scratch(int64_t gframes, int64_t frame_kernel_frames, 
     f.verts = verts;
     f.surv = tris;
     f.bins = std::max<int64_t>(4096, (bin_cap / 128) * tris);
-    f.stride = al256(12 * (size_t)verts) + al256(4 * (size_t)f.surv) + al256(2 * (size_t)f.bins);
+    f.stride = al256(16 * (size_t)verts) + al256(4 * (size_t)f.surv) + al256(2 * (size_t)f.bins);
     return f;
 }
 

@@ -510,7 +510,7 @@ struct StageInfo {
 struct FrameLds {
     union {
         struct {  // scenes held in LDS: the snapped vertices
-            int X[kFVMax], Y[kFVMax];
+            int2 XY[kFVMax];
             float iw[kFVMax];
         } v;
         struct {  // larger scenes (vertices, bins, survivors in global scratch): object tables
@@ -575,8 +575,9 @@ bool frame_fits_global(int64_t n_verts, int n_obj, int64_t n_tris, int width, in
 // up once per frame.  Separate instantiations keep LDS accesses LDS instructions.
 template <bool G>
 struct FrameMem {
-    int *X, *Y;
-    float *iw;
+    int2 *xy;   // G = false: snapped (X, Y) per vertex (LDS)
+    float *iw;  // G = false: 1 / w per vertex (LDS)
+    int4 *v4;   // G = true: (X, Y, 1 / w as bits, 0) per vertex, one 16-byte load (scratch)
     unsigned short *bin;
     unsigned *surv;
     int bin_max, surv_max;
@@ -584,6 +585,32 @@ struct FrameMem {
     float (*o_R)[9];
     Material *o_mat;
     unsigned char *vtx_hint;
+
+    ORRB_INLINE int2 vxy(int v) const {
+        if constexpr (G) {
+            const int4 q = v4[v];
+            return make_int2(q.x, q.y);
+        } else {
+            return xy[v];
+        }
+    }
+    // (X, Y, 1 / w as bits, 0)
+    ORRB_INLINE int4 vall(int v) const {
+        if constexpr (G) {
+            return v4[v];
+        } else {
+            const int2 p = xy[v];
+            return make_int4(p.x, p.y, __float_as_int(iw[v]), 0);
+        }
+    }
+    ORRB_INLINE void vput(int v, int X, int Y, float w) const {
+        if constexpr (G)
+            v4[v] = make_int4(X, Y, __float_as_int(w), 0);
+        else {
+            xy[v] = make_int2(X, Y);
+            iw[v] = w;
+        }
+    }
 };
 
 template <bool G>
@@ -592,10 +619,10 @@ ORRB_INLINE FrameMem<G> frame_mem(const RenderArgs &a, FrameLds &S) {
     if constexpr (G) {
         char *base = a.fscratch + (int64_t)blockIdx.x * a.fscratch_stride;
         const int64_t nv = a.fs_verts;
-        F.X = reinterpret_cast<int *>(base);
-        F.Y = F.X + nv;
-        F.iw = reinterpret_cast<float *>(F.Y + nv);
-        F.surv = reinterpret_cast<unsigned *>(F.iw + nv);
+        F.xy = nullptr;
+        F.iw = nullptr;
+        F.v4 = reinterpret_cast<int4 *>(base);
+        F.surv = reinterpret_cast<unsigned *>(F.v4 + nv);
         F.bin = reinterpret_cast<unsigned short *>(F.surv + a.fs_surv);
         F.bin_max = a.fs_bins;
         F.surv_max = a.fs_surv;
@@ -610,9 +637,9 @@ ORRB_INLINE FrameMem<G> frame_mem(const RenderArgs &a, FrameLds &S) {
         F.o_mat = S.m.g.o_mat;
         F.vtx_hint = S.m.g.vtx_hint;
     } else {
-        F.X = S.m.v.X;
-        F.Y = S.m.v.Y;
+        F.xy = S.m.v.XY;
         F.iw = S.m.v.iw;
+        F.v4 = nullptr;
         F.surv = S.u.surv;
         F.bin = S.bin;
         F.bin_max = kFBinMax;
@@ -659,7 +686,8 @@ ORRB_INLINE int4 frame_tri(const RenderArgs &a, const FrameMem<G> &F, int k, int
 struct TriSetup {
     int xa, ya, xb, yb, xc, yc;
     int i0, j0, i1, j1;  // pixel-centre range inside the clip box
-    int va, vb, vc;      // LDS vertex indices
+    int va, vb, vc;      // vertex indices
+    float iwa, iwb, iwc; // 1 / w of the vertices (tile set-up only)
     long long area;
 };
 
@@ -672,8 +700,9 @@ ORRB_INLINE bool tile_setup(const FrameMem<G> &F, int k, int4 tri, int x0, int y
                             int &flags, float &area) {
     const int vb = F.o_vbase[k];
     const int i0v = vb + tri.x, i1v = vb + tri.y, i2v = vb + tri.z;
-    const int xa = F.X[i0v], xb = F.X[i2v], xc = F.X[i1v];
-    const int ya = F.Y[i0v], yb = F.Y[i2v], yc = F.Y[i1v];
+    const int4 pa = F.vall(i0v), pb = F.vall(i2v), pc = F.vall(i1v);
+    const int xa = pa.x, xb = pb.x, xc = pc.x;
+    const int ya = pa.y, yb = pb.y, yc = pc.y;
     const int xmin = min(xa, min(xb, xc)), xmax = max(xa, max(xb, xc));
     const int ymin = min(ya, min(yb, yc)), ymax = max(ya, max(yb, yc));
     T.i0 = max(ceil256(xmin - 128), x0);
@@ -683,6 +712,7 @@ ORRB_INLINE bool tile_setup(const FrameMem<G> &F, int k, int4 tri, int x0, int y
     if (T.i0 > T.i1 || T.j0 > T.j1) return false;
     T.xa = xa; T.ya = ya; T.xb = xb; T.yb = yb; T.xc = xc; T.yc = yc;
     T.va = i0v; T.vb = i2v; T.vc = i1v;
+    T.iwa = __int_as_float(pa.z); T.iwb = __int_as_float(pb.z); T.iwc = __int_as_float(pc.z);
     flags = top_left(xc - xb, yc - yb) | (top_left(xa - xc, ya - yc) << 1) | (top_left(xb - xa, yb - ya) << 2) |
             (max(xmax - xmin, ymax - ymin) > kSmallExtent ? 8 : 0);
     if (!(flags & 8))
@@ -697,9 +727,10 @@ template <bool G>
 ORRB_INLINE bool frame_setup(const FrameMem<G> &F, int k, int4 tri, int cx0, int cy0, int cx1, int cy1, TriSetup &T) {
     const int vb = F.o_vbase[k];
     const int i0v = vb + tri.x, i1v = vb + tri.y, i2v = vb + tri.z;
-    const int x0 = F.X[i0v], x1 = F.X[i1v], x2 = F.X[i2v];
+    const int2 p0 = F.vxy(i0v), p1 = F.vxy(i1v), p2 = F.vxy(i2v);
+    const int x0 = p0.x, x1 = p1.x, x2 = p2.x;
     if (x0 == kInvalidX || x1 == kInvalidX || x2 == kInvalidX) return false;
-    const int y0 = F.Y[i0v], y1 = F.Y[i1v], y2 = F.Y[i2v];
+    const int y0 = p0.y, y1 = p1.y, y2 = p2.y;
     const int xmin = min(x0, min(x1, x2)), xmax = max(x0, max(x1, x2));
     const int ymin = min(y0, min(y1, y2)), ymax = max(y0, max(y1, y2));
     T.i0 = max(ceil256(xmin - 128), cx0);
@@ -737,9 +768,7 @@ ORRB_INLINE int frame_vertex(const FrameLds &S, const FrameMem<G> &F, int v, int
             iw = s.iw;
         }
     }
-    F.X[v] = X;
-    F.Y[v] = Y;
-    F.iw[v] = iw;
+    F.vput(v, X, Y, iw);
     return cull;
 }
 
@@ -1405,10 +1434,13 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
                 if (!frame_setup(F, k, frame_tri(a, F, k, tri), x0, y0, x1, y1, T)) continue;
                 flags = tri_flags(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc);
                 area = (float)T.area;
+                T.iwa = __int_as_float(F.vall(T.va).z);
+                T.iwb = __int_as_float(F.vall(T.vb).z);
+                T.iwc = __int_as_float(F.vall(T.vc).z);
             } else if (!tile_setup(F, k, frame_tri(a, F, k, tri), x0, y0, x1, y1, T, flags, area)) {
                 continue;
             }
-            const float iwa = F.iw[T.va], iwb = F.iw[T.vb], iwc = F.iw[T.vc];
+            const float iwa = T.iwa, iwb = T.iwb, iwc = T.iwc;
             if (!(flags & 8)) {  // small triangle: step the integer edge functions
                 const int b0 = (flags & 1) ? 0 : 1, b1 = (flags & 2) ? 0 : 1, b2 = (flags & 4) ? 0 : 1;
                 EdgeStep es = edge_start(T.xa, T.ya, T.xb, T.yb, T.xc, T.yc, (T.i0 << 8) + 128, (T.j0 << 8) + 128);
@@ -1502,8 +1534,10 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
                     constexpr bool kSpot = (SHADE & 1) != 0, kMat = (SHADE & 2) != 0;
                     MatTex mt;
                     if constexpr (kMat) mt = mat_inputs(a, fi.obj_begin + k, mvb, tv);
-                    o[h] = shade_pixel<kSpot, kMat>(F.X[va], F.Y[va], F.X[vbb], F.Y[vbb], F.X[vc], F.Y[vc], F.iw[va],
-                                                    F.iw[vbb], F.iw[vc], a.mesh_nrm[mvb + tv.x], a.mesh_nrm[mvb + tv.z],
+                    const int4 A = F.vall(va), B = F.vall(vbb), C = F.vall(vc);
+                    o[h] = shade_pixel<kSpot, kMat>(A.x, A.y, B.x, B.y, C.x, C.y, __int_as_float(A.z),
+                                                    __int_as_float(B.z), __int_as_float(C.z), a.mesh_nrm[mvb + tv.x],
+                                                    a.mesh_nrm[mvb + tv.z],
                                                     a.mesh_nrm[mvb + tv.y], F.o_R[k], pi, pj, z, cam, S.light,
                                                     S.light_type, fi.n_lights, F.o_mat[k], S.spot, a.shadow_maps,
                                                     a.shadow_res, &mt, a.tex_texels, a.tex_info);
