@@ -307,7 +307,10 @@ typedef struct {                  /* destinations; rgb, depth, normal, seg may e
     float *alpha;                 /* [P] or NULL: transparency channel (Sec. 4.4), 1 where a
                                      triangle covers the pixel centre, 0 for background */
     uint8_t *rgb8;                /* [3P] or NULL: post-processed 3 x 8-bit RGB, planar like
-                                     rgb (needs rgb: it is computed from the written rgb) */
+                                     rgb.  Without `rgb` (the paper's 3 x 8-bit format) the
+                                     render kernels encode each pixel as they write it; with
+                                     `rgb` a separate pass encodes the written fp32 rgb.  Both
+                                     give the same bytes. */
     orrb_track *track;            /* [sum over frames of the scene's objects] or NULL */
 } orrb_outputs;
 
@@ -419,7 +422,7 @@ typedef struct {
     double raster_ms;          /* summed device time of k_raster_shade launches (tiled path) */
     double frame_ms;           /* summed device time of k_frame launches (frame path) */
     int64_t vertex_launches, raster_launches, frame_launches;
-    double post_ms;            /* summed device time of k_post launches (rgb8 output) */
+    double post_ms;            /* summed device time of k_post launches (rgb8 with rgb) */
     int64_t post_launches;
 } orrb_kernel_times;
 

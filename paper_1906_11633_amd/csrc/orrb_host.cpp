@@ -1033,7 +1033,6 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
         a.shadow_maps = (const float *)((char *)workspace + cw.maps);
         a.shadow_res = L->shadow_res;
     }
-    if (out->rgb8 && !out->rgb) return fail(ORRB_ERR_INVALID_ARGUMENT, "rgb8 needs the rgb destination");
     if (out->rgb8 && par->grain &&
         (par->grain_w < 1 || par->grain_h < 1 || (int64_t)par->grain_w * par->grain_h > (int64_t)1 << 26))
         return fail(ORRB_ERR_INVALID_ARGUMENT, "grain texture size %d x %d (1 .. 2^26 texels per plane)",
@@ -1057,7 +1056,7 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     for (int k = 0; k < 4 && e == hipSuccess; ++k) {
         if (k < 2 && a.n_titems == 0) continue;  // no frame on the tiled path
         if (k == 2 && a.n_fitems == 0) continue;
-        if (k == 3 && !a.out_rgb8) continue;     // no post-processed 8-bit output
+        if (k == 3 && !(a.out_rgb8 && a.out_rgb)) continue;  // 8-bit output alone: encoded by the render kernels
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (T.enabled && timing) {
             e0 = T.get();

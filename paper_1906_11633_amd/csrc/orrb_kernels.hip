@@ -34,7 +34,7 @@
 // (Inside k_frame's LDS tile the ID field also carries the object slot above the 16-bit
 // ID; slots never decrease with the ID, so the order is the same, and the slot bits are
 // cleared before a key is written out.)
-#include "orrb_primitives.h"
+#include "orrb_post.h"
 
 namespace orrb {
 
@@ -347,6 +347,9 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
     const CamF cam = frame_camera(a, f);
     const int64_t HW = (int64_t)fi.width * fi.height, po = fi.pixel_offset;
     const float inv_tw = __builtin_amdgcn_rcpf((float)tw);
+    const bool fused = a.out_rgb8 && !a.out_rgb;  // 8-bit output encoded here (no fp32 rgb)
+    PostFrame pq;
+    if (fused) pq = post_frame(a, f);
     for (int p = tid; p < tw * th; p += kBlock) {
         const int lj = (int)(((float)p + 0.5f) * inv_tw);  // exact: p < 4096, tw <= 64
         const int li = p - lj * tw;
@@ -404,6 +407,20 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
             triv = tri;
         }
         store_pixel(a, po, HW, pix, o, z, segv, triv, key);
+        if (fused) {
+            float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+            if (pq.gi != 0.f) {
+                const unsigned t = grain_texel(a, pq, i, j);
+                n0 = grain_at(pq.g0, t);
+                n1 = grain_at(pq.g1, t);
+                n2 = grain_at(pq.g2, t);
+            }
+            const uchar3 u = post_pixel(pq, o.r0, o.r1, o.r2, n0, n1, n2);
+            uint8_t *d = a.out_rgb8 + 3 * po + pix;
+            d[0] = u.x;
+            d[HW] = u.y;
+            d[2 * HW] = u.z;
+        }
     }
 
     // ---- tracker: every lane of a wave takes part (the trip count is uniform) ----
@@ -499,13 +516,52 @@ struct BgFrame {
     long long po;  // pixel offset of the frame
     int W, H, ntx, vec;
     int n;         // background tiles of the frame
-    int pad;
+    int f;         // the frame
 };
 
 struct StageInfo {
     long long po;  // pixel offset of the frame
-    int W, H, x0, y0, vec, pad;
+    int W, H, x0, y0, vec, f;
 };
+
+// The 8-bit output encoded by the frame kernel itself (rgb8 requested without the fp32
+// rgb): the waves that write tiles out keep the grading constants of the last frame
+// they wrote.
+struct PostCache {
+    int f = -1;
+    PostFrame q;
+    float3 o_bg;  // post_grade of a background pixel (rgb 0)
+};
+
+ORRB_INLINE bool fused_rgb8(const RenderArgs &a) { return a.out_rgb8 && !a.out_rgb; }
+
+// Codes of the lane's four pixels (i .. i + 3, j) of frame f from linear rgb v, stored
+// to the 8-bit planes: one 4-byte store per plane when the group is whole and aligned.
+// v == nullptr: four background pixels (rgb 0).
+ORRB_INLINE void store_codes4(const RenderArgs &a, PostCache &pc, int f, int64_t po, int64_t HW, int64_t pix, int i,
+                              int j, const float (*v)[4], bool vec, int n) {
+    if (pc.f != f) {  // uniform: every lane writes the same frame
+        pc.q = post_frame(a, f);
+        pc.o_bg = post_grade(pc.q, 0.f, 0.f, 0.f);
+        pc.f = f;
+    }
+    unsigned code[3];
+    if (v)
+        post_codes_row(a, pc.q, i, j, v, code);
+    else
+        post_codes_row_bg(a, pc.q, pc.o_bg, i, j, code);
+    uint8_t *dst = a.out_rgb8 + 3 * po + pix;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (vec) {
+            *reinterpret_cast<unsigned *>(dst + c * HW) = code[c];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < n) dst[c * HW + k] = (uint8_t)(code[c] >> (8 * k));
+        }
+    }
+}
 
 struct FrameLds {
     union {
@@ -824,7 +880,8 @@ ORRB_INLINE void store4i(int *p, const int *v, bool vec, int n) {
 // Background (no fragment) for four adjacent pixels: rgb, depth, normal 0, seg and
 // tri_id -1, vis the empty key.
 template <bool AUX>
-ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, int64_t pix, bool vec, int n) {
+ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, int64_t pix, bool vec, int n, int f,
+                                   int i, int j, PostCache &pc) {
     // materialized at each use: hoisted out of the tile loops these constants get
     // spilled, and their reloads would wait for every earlier store of the wave
     float z;
@@ -852,6 +909,7 @@ ORRB_INLINE void store_background4(const RenderArgs &a, int64_t po, int64_t HW, 
             if (q < n) a.out_vis[po + pix + q] = kEmptyKey;
     }
     if (AUX && a.out_alpha) store4f(a.out_alpha + po + pix, zf, vec, n);
+    if (AUX && fused_rgb8(a)) store_codes4(a, pc, f, po, HW, pix, i, j, nullptr, vec, n);
 }
 
 // ---- synchronization of the persistent frame workgroup ----
@@ -913,14 +971,14 @@ ORRB_INLINE bool frame_barrier(const RenderArgs &a, FrameLds &S, int &gen) {
 // every output 16-byte aligned.
 ORRB_INLINE bool frame_vec(const RenderArgs &a, int W, int64_t po) {
     const uintptr_t align = (uintptr_t)a.out_rgb | (uintptr_t)a.out_depth | (uintptr_t)a.out_normal |
-                            (uintptr_t)a.out_seg | (uintptr_t)a.out_tri;
+                            (uintptr_t)a.out_seg | (uintptr_t)a.out_tri | (uintptr_t)a.out_rgb8;
     return ((W | (int)(po & 3)) & 3) == 0 && (align & 15) == 0;
 }
 
 // Wave 0: hand frame seq's background tiles, order[n_busy .. n_tiles), to the store
 // waves.  The slot is reused only after every store wave has moved past the frame that
 // held it before (so none still takes from it) and all its tiles are written.
-ORRB_INLINE void frame_publish(const RenderArgs &a, FrameLds &S, int seq, int64_t po, int W, int H, int ntx, int n_busy,
+ORRB_INLINE void frame_publish(const RenderArgs &a, FrameLds &S, int seq, int f, int64_t po, int W, int H, int ntx, int n_busy,
                                int n_tiles, int lane) {
     const int slot = seq % kFSlots, n_empty = n_tiles - n_busy;
     int stop = 0;
@@ -947,6 +1005,7 @@ ORRB_INLINE void frame_publish(const RenderArgs &a, FrameLds &S, int seq, int64_
         b.ntx = ntx;
         b.vec = frame_vec(a, W, po);
         b.n = n_empty;
+        b.f = f;
         S.bg_next[slot] = 0;
         S.bg_done[slot] = 0;
     }
@@ -1005,7 +1064,7 @@ ORRB_INLINE void stage_pixel(FrameLds &S, int s, int p, const PixelOut &o, int s
 }
 
 // Hand the filled slot to the store waves, with where the tile goes.
-ORRB_INLINE void stage_end(FrameLds &S, int s, int64_t po, int W, int H, int x0, int y0, bool vec, int lane) {
+ORRB_INLINE void stage_end(FrameLds &S, int s, int f, int64_t po, int W, int H, int x0, int y0, bool vec, int lane) {
     if (lane == 0) {
         StageInfo &in = S.stage_info[s];
         in.po = po;
@@ -1014,6 +1073,7 @@ ORRB_INLINE void stage_end(FrameLds &S, int s, int64_t po, int W, int H, int x0,
         in.x0 = x0;
         in.y0 = y0;
         in.vec = vec;
+        in.f = f;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_wave_barrier();
@@ -1048,7 +1108,7 @@ ORRB_INLINE void frame_warm(const RenderArgs &a, int item, int lane) {
 
 // Store wave: write staged tile s (every output plane) and free the slot.
 template <bool AUX>
-ORRB_INLINE void stage_write(const RenderArgs &a, FrameLds &S, int s, int lj, int li0, int lane) {
+ORRB_INLINE void stage_write(const RenderArgs &a, FrameLds &S, int s, int lj, int li0, int lane, PostCache &pc) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     const StageInfo in = S.stage_info[s];
     const int p = lj * kFTileW + li0;
@@ -1106,6 +1166,12 @@ ORRB_INLINE void stage_write(const RenderArgs &a, FrameLds &S, int s, int lj, in
         for (int q = 0; q < 4; ++q) al[q] = key[q] == kEmptyKey ? 0.f : 1.f;
         store4f(a.out_alpha + po + pix, al, vec, n);
     }
+    if (AUX && fused_rgb8(a)) {  // the staged rgb (background 0) encoded on its way out
+        const float rv[3][4] = {{v[0][0], v[0][1], v[0][2], v[0][3]},
+                                {v[1][0], v[1][1], v[1][2], v[1][3]},
+                                {v[2][0], v[2][1], v[2][2], v[2][3]}};
+        store_codes4(a, pc, in.f, po, HW, pix, i0, j, rv, vec, n);
+    }
 }
 
 // Pace a store wave: at most kFPace store instructions in flight, so the CU's memory
@@ -1121,6 +1187,7 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
     // a wave kept for staged tiles answers them without delay (no background tiles)
     const bool staged_only = kFStageWave && wave == kFW - 1;
     int my = store_wave ? 0 : max(0, lds_load(&S.published) - kFSlots);
+    PostCache pc;  // grading constants of the last frame this wave encoded (fused rgb8)
     while (true) {
         // 1: staged tile st claimed, 2: frame my is published, 0: nothing more will come
         int action = 0, st = 0;
@@ -1152,7 +1219,7 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
         action = __builtin_amdgcn_readlane(action, 0);
         if (!action) break;
         if (action == 1) {
-            stage_write<AUX>(a, S, __builtin_amdgcn_readlane(st, 0), lj, li0, lane);
+            stage_write<AUX>(a, S, __builtin_amdgcn_readlane(st, 0), lj, li0, lane, pc);
             if (store_wave && !staged_only) store_pace();
             continue;
         }
@@ -1177,7 +1244,8 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
         const int j = y0 + lj, i0 = x0 + li0;
         const int n_in = j <= y1 ? max(0, min(4, x1 - i0 + 1)) : 0;
         if (n_in > 0)
-            store_background4<AUX>(a, b.po, (int64_t)b.W * b.H, (int64_t)j * b.W + i0, b.vec && n_in == 4, n_in);
+            store_background4<AUX>(a, b.po, (int64_t)b.W * b.H, (int64_t)j * b.W + i0, b.vec && n_in == 4, n_in, b.f,
+                                   i0, j, pc);
         if (store_wave) store_pace();
     }
 }
@@ -1364,7 +1432,7 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
         }
         // queue the tiles no triangle touches for the store waves
         const int n_busy = overflow ? n_tiles : total_ne;
-        frame_publish(a, S, seq, fi.pixel_offset, W, H, ntx, n_busy, n_tiles, lane);
+        frame_publish(a, S, seq, f, fi.pixel_offset, W, H, ntx, n_busy, n_tiles, lane);
     }
     if (frame_barrier<G>(a, S, gen)) return true;
     const bool overflow = S.misc[1] != 0;
@@ -1558,7 +1626,7 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
             stopped = true;
             break;
         }
-        stage_end(S, stg, po, W, H, x0, y0, vec_frame, lane);
+        stage_end(S, stg, f, po, W, H, x0, y0, vec_frame, lane);
     }
     return frame_barrier<G>(a, S, gen);  // the frame's LDS is reused by the next frame
 }
@@ -1677,7 +1745,7 @@ hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu) {
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu) {
     if (a.n_fitems <= 0 || a.f_grid <= 0) return hipSuccess;
     const int grid = a.f_grid;  // the schedule's grid (at most the CU count)
-    const bool aux = a.out_alpha || a.out_track, mixed = a.fscratch != nullptr;
+    const bool aux = a.out_alpha || a.out_track || (a.out_rgb8 && !a.out_rgb), mixed = a.fscratch != nullptr;
     const dim3 g(grid), b(kFT);
 #define ORRB_FRAME(AUX_, MIXED_, SHADE_) hipLaunchKernelGGL((k_frame<AUX_, MIXED_, SHADE_>), g, b, 0, stream, a)
     switch (a.shade_mode) {

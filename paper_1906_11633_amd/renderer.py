@@ -216,13 +216,15 @@ class Renderer:
         return Job(lay, st, int(inf.total_pixels), ws)
 
     def alloc_outputs(self, job: Job, tri_id=False, vis=False, stats=False, alpha=False, rgb8=False,
-                      track=False) -> Dict[str, torch.Tensor]:
+                      track=False, base=("rgb", "depth", "normal", "seg")) -> Dict[str, torch.Tensor]:
+        """Destinations for a render of `job`: the channels named in `base` (any of rgb,
+        depth, normal, seg; rgb8 without rgb is encoded by the render kernels themselves,
+        the paper's 3 x 8-bit format) plus the optional ones."""
         P = job.total_pixels
         dev = f"cuda:{self.device}"
-        out = dict(rgb=torch.empty(3 * P, dtype=torch.float32, device=dev),
-                   depth=torch.empty(P, dtype=torch.float32, device=dev),
-                   normal=torch.empty(3 * P, dtype=torch.float32, device=dev),
-                   seg=torch.empty(P, dtype=torch.int32, device=dev))
+        shapes = dict(rgb=(3 * P, torch.float32), depth=(P, torch.float32), normal=(3 * P, torch.float32),
+                      seg=(P, torch.int32))
+        out = {k: torch.empty(shapes[k][0], dtype=shapes[k][1], device=dev) for k in base}
         if tri_id:
             out["tri_id"] = torch.empty(P, dtype=torch.int32, device=dev)
         if vis:

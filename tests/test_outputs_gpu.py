@@ -147,6 +147,38 @@ def test_rgb8_grain_on_unaligned_widths(renderer):
     _check_rgb8(b, gpu, ref)
 
 
+FUSED = [
+    ("config2-frame-path", lambda: S.with_postprocessing(S.config2(2, 2, 200), seed=5), None),
+    ("config2-tiled", lambda: S.with_postprocessing(S.config2(2, 2, 200), seed=5), (32, 32, 256, 0, 1)),
+    ("width77-frame-path", lambda: S.with_postprocessing(S.config2(3, 2, 77), seed=7), None),
+    ("width77-tiled-persistent", lambda: S.with_postprocessing(S.config2(3, 2, 77), seed=7), (16, 16, 512, 1, 1)),
+    ("uneven-one-launch", lambda: S.with_postprocessing(S.config3(3, 4), seed=3), (32, 32, 512, 0, 2)),
+]
+
+
+@pytest.mark.parametrize("name,make,tuning", FUSED, ids=[c[0] for c in FUSED])
+def test_rgb8_alone_is_encoded_by_the_render_kernels(renderer, name, make, tuning):
+    """rgb8 requested without the fp32 rgb (the paper's 3 x 8-bit format): the render
+    kernels encode while writing, and give the same bytes as the separate pass that
+    encodes a rendered fp32 rgb; the other channels are unchanged."""
+    import torch
+    b = make()
+    job = renderer.prepare(b)
+    if tuning is not None:
+        job.layout.set_tuning(*tuning)
+    print(f"[outputs] fused rgb8 {name} frames={b.n_frames} tuning={job.layout.info.tuning.as_tuple()}", flush=True)
+    both = renderer.render(job, rgb8=True)
+    alone = renderer.alloc_outputs(job, rgb8=True, base=("depth", "seg"))
+    alone["rgb8"].fill_(0x5A)
+    renderer.render(job, alone)
+    torch.cuda.synchronize()
+    for k in ("rgb8", "depth", "seg"):
+        assert torch.equal(both[k], alone[k]), k
+    if name == "config2-frame-path":  # and against the oracle
+        gpu = parity.to_numpy(both)
+        _check_rgb8(b, gpu, oracle.render(b))
+
+
 def test_outputs_bit_identical_across_tunings(renderer):
     b = S.with_postprocessing(S.config2(4, 2, 96), seed=2)
     base = _render(renderer, b)
