@@ -48,7 +48,7 @@ def open_library(path: str):
     """Open a compiled oracle library and declare its entry points."""
     lib = C.CDLL(path)
     P = C.c_void_p
-    inputs = [P] * 17 + [C.c_int32] + [P] * 8 + [P] * 6 + [C.c_int32] + [P] * 6
+    inputs = [P] * 17 + [C.c_int32] + [P] * 8 + [P] * 6 + [C.c_int32] + [P] * 7
     lib.oracle_render.argtypes = inputs + [P] * 9 + [C.c_int32]
     lib.oracle_render.restype = C.c_int
     lib.oracle_shade_grad.argtypes = inputs + [C.c_int32, P, P, P, P, P, P, P, P, P, P, C.c_int32]
@@ -133,6 +133,9 @@ class _Packed:
              for u, m in zip(uvs, meshes)]), np.float64) if any(u is not None for u in uvs) else None)
         texs = getattr(b, "textures", None)
         ot = getattr(b, "object_texture", None)
+        nt = getattr(b, "object_normal_texture", None)
+        if texs is not None and ot is None and nt is not None:
+            ot = np.full(len(nt), -1, np.int32)  # normal textures only
         if texs is not None and ot is not None:
             info, off = [], 0
             for t in texs:
@@ -146,6 +149,7 @@ class _Packed:
             self.obj_txf = p64(np.asarray(b.tex_xform, np.float32))
         else:
             self.tex_texels = self.tex_info = self.obj_tex = self.obj_txf = None
+        self.obj_ntex = (np.ascontiguousarray(nt, np.int32) if texs is not None and nt is not None else None)
         em = getattr(b, "emission", None)
         self.emission = None if em is None else p64(np.asarray(em, np.float32))
 
@@ -160,7 +164,7 @@ class _Packed:
                 _ptr(self.height), _ptr(self.pixel_offset), _ptr(self.light_dir), _ptr(self.light_cone),
                 _ptr(self.shadow_view), _ptr(self.shadow_intr), _ptr(self.shadow_maps), _ptr(self.shadow_slot),
                 self.shadow_res, _ptr(self.mesh_uv), _ptr(self.tex_texels), _ptr(self.tex_info), _ptr(self.obj_tex),
-                _ptr(self.obj_txf), _ptr(self.emission)]
+                _ptr(self.obj_txf), _ptr(self.emission), _ptr(self.obj_ntex)]
 
 
 def _pack(batch):

@@ -67,6 +67,9 @@ typedef struct {
     const int64_t *tex_info;
     const int32_t *obj_tex;
     const double *obj_txf, *emission;
+    /* normal (bump) textures: each object's normal texture (-1 none; NULL when the batch
+     * has none), sampled at the same transformed UV as the pattern texture */
+    const int32_t *obj_ntex;
 } Inputs;
 
 /* per-vertex results of the vertex stage for one (frame, object) */
@@ -318,6 +321,69 @@ static void fragment_albedo(const Inputs *in, int o, const Frag *fr, double *alb
     for (int c = 0; c < 3; c++) alb[c] *= rgb[c];
 }
 
+static void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* The shading normal at a fragment of object o (frame f, mesh triangle `local`): the
+ * interpolated normal n, perturbed by the object's normal texture if it has one.  The
+ * texture sampled (bilinear, repeat) at the pattern texture's transformed UV encodes a
+ * tangent-space direction t = 2 rgb - 1 (normalized).  The tangent frame is the
+ * triangle's: T and B solve e1 = du1 T + dv1 B, e2 = du2 T + dv2 B for the object-space
+ * edges e_k = p_k - p_0 and UV differences (du_k, dv_k), taken to view space by the
+ * composed matrix; T is made orthogonal to n (Gram-Schmidt), B' = h n x T' with h the
+ * sign of (n x T') . B (the UV mapping's handedness), and the shading normal is
+ * normalize(t_x T' + t_y B' + t_z n).  A triangle whose UVs are degenerate (zero UV
+ * area), a tangent parallel to n or t = 0 leaves n unchanged. */
+static void shading_normal(const Inputs *in, int f, int o, int local, const Frag *fr, double *ns) {
+    for (int k = 0; k < 3; k++) ns[k] = fr->n[k];
+    int t = in->obj_ntex ? in->obj_ntex[o] : -1;
+    if (t < 0) return;
+    const double *x = in->obj_txf + 4 * (int64_t)o;
+    double rgb[3];
+    tex_sample(in, t, fr->uv[0] * x[0] + x[2], fr->uv[1] * x[1] + x[3], rgb);
+    double tn[3] = {2 * rgb[0] - 1, 2 * rgb[1] - 1, 2 * rgb[2] - 1};
+    double tl = sqrt(dot3(tn, tn));
+    if (tl == 0) return;
+    for (int k = 0; k < 3; k++) tn[k] /= tl;
+    int m = in->object_mesh[o];
+    const int32_t *tri = in->mesh_idx + 3 * (in->mesh_tbegin[m] + local);
+    int64_t v0 = in->mesh_vbegin[m];
+    const double *p0 = in->mesh_pos + 3 * (v0 + tri[0]), *p1 = in->mesh_pos + 3 * (v0 + tri[1]),
+                 *p2 = in->mesh_pos + 3 * (v0 + tri[2]);
+    const double *u0 = in->mesh_uv + 2 * (v0 + tri[0]), *u1 = in->mesh_uv + 2 * (v0 + tri[1]),
+                 *u2 = in->mesh_uv + 2 * (v0 + tri[2]);
+    double du1 = u1[0] - u0[0], dv1 = u1[1] - u0[1], du2 = u2[0] - u0[0], dv2 = u2[1] - u0[1];
+    double det = du1 * dv2 - du2 * dv1;
+    if (det == 0) return;
+    double To[3], Bo[3];
+    for (int k = 0; k < 3; k++) {
+        double e1 = p1[k] - p0[k], e2 = p2[k] - p0[k];
+        To[k] = (e1 * dv2 - e2 * dv1) / det;
+        Bo[k] = (e2 * du1 - e1 * du2) / det;
+    }
+    double M[12], T[3], B[3];
+    compose(in->view + 12 * (int64_t)f, in->object_pose + 12 * (int64_t)o, M);
+    for (int r = 0; r < 3; r++) {
+        T[r] = M[r * 4 + 0] * To[0] + M[r * 4 + 1] * To[1] + M[r * 4 + 2] * To[2];
+        B[r] = M[r * 4 + 0] * Bo[0] + M[r * 4 + 1] * Bo[1] + M[r * 4 + 2] * Bo[2];
+    }
+    const double *n = fr->n;
+    double nt = dot3(n, T);
+    double Tp[3] = {T[0] - nt * n[0], T[1] - nt * n[1], T[2] - nt * n[2]};
+    double tpl = sqrt(dot3(Tp, Tp));
+    if (tpl == 0) return;
+    for (int k = 0; k < 3; k++) Tp[k] /= tpl;
+    double Bp[3];
+    cross3(n, Tp, Bp);
+    if (dot3(Bp, B) < 0)
+        for (int k = 0; k < 3; k++) Bp[k] = -Bp[k];
+    for (int k = 0; k < 3; k++) ns[k] = tn[0] * Tp[k] + tn[1] * Bp[k] + tn[2] * n[k];
+    normalize3(ns);
+}
+
 /* A light expressed in the frame's view space. */
 typedef struct {
     int type;      /* 0 point, 1 directional, 2 spot (with a shadow map) */
@@ -539,11 +605,13 @@ static void render_frame(const Inputs *in, int f, double *rgb, double *depth, do
             double r = in->roughness[o], ks = in->specular[o], mexp = 2.0 / (r * r) - 2.0;
             double alb[3];
             fragment_albedo(in, o, &fr, alb);
+            Frag fs = fr;  /* lights see the normal-mapped normal; the normal channel keeps n */
+            shading_normal(in, f, o, q->local, &fr, fs.n);
             double E = in->emission ? in->emission[o] : 0.0;
             double U[3] = {E * alb[0], E * alb[1], E * alb[2]};
             for (int l = 0; l < nL; l++) {
                 LTerm t;
-                light_term(L + l, &fr, mexp, &t, in->shadow_res);
+                light_term(L + l, &fs, mexp, &t, in->shadow_res);
                 for (int c = 0; c < 3; c++) U[c] += t.A * t.ndl * (alb[c] + ks * t.s);
                 if (shadow_amb && t.amb && t.ndl > 0 && t.cone > 0) shadow_amb[po + p] = 1;
             }
@@ -575,14 +643,15 @@ static void render_frame(const Inputs *in, int f, double *rgb, double *depth, do
         const int32_t *height, const int64_t *pixel_offset, const double *light_dir, const double *light_cone,      \
         const double *shadow_view, const double *shadow_intr, const double *shadow_maps,                        \
         const int32_t *shadow_slot, int32_t shadow_res, const double *mesh_uv, const double *tex_texels,        \
-        const int64_t *tex_info, const int32_t *obj_tex, const double *obj_txf, const double *emission
+        const int64_t *tex_info, const int32_t *obj_tex, const double *obj_txf, const double *emission,         \
+        const int32_t *obj_ntex
 
 #define FILL_INPUTS(in)                                                                                         \
     Inputs in = {mesh_vbegin, mesh_tbegin, mesh_pos, mesh_nrm, mesh_idx, scene_object_begin, object_mesh,      \
                  object_seg, object_pose, object_visible, albedo, roughness, specular, scene_light_begin,      \
                  light_type, light_vec, light_intensity, frame_scene, width, height, view, intr, near_,        \
                  exposure, pixel_offset, light_dir, light_cone, shadow_view, shadow_intr, shadow_maps,         \
-                 shadow_slot, shadow_res, mesh_uv, tex_texels, tex_info, obj_tex, obj_txf, emission}
+                 shadow_slot, shadow_res, mesh_uv, tex_texels, tex_info, obj_tex, obj_txf, emission, obj_ntex}
 
 static void set_threads(int n_threads) {
 #ifdef _OPENMP
@@ -626,7 +695,7 @@ int oracle_shade_grad(INPUT_ARGS, int32_t n_scenes, const double *target, const 
     FILL_INPUTS(in);
     for (int64_t l = 0; l < scene_light_begin[n_scenes]; l++)
         if (light_type[l] == 2) return 2; /* spot lights: no adjoint (shadow visibility is not differentiated) */
-    if (obj_tex || emission) return 2;   /* textured or emissive materials: no adjoint */
+    if (obj_tex || emission || obj_ntex) return 2;   /* textured or emissive materials: no adjoint */
     int err = 0;
     double *scene_loss = (double *)calloc((size_t)n_scenes + 1, sizeof(double));
     if (!scene_loss) return 1;

@@ -313,6 +313,9 @@ class Batch:
     object_texture: Optional[np.ndarray] = None  # i32 [O]
     tex_xform: Optional[np.ndarray] = None       # f32 [O, 4]
     emission: Optional[np.ndarray] = None        # f32 [O]
+    # each object's normal (bump) texture from the same pool (-1 none), sampled at the
+    # same transformed UV
+    object_normal_texture: Optional[np.ndarray] = None  # i32 [O]
 
     @property
     def n_scenes(self) -> int:
@@ -388,6 +391,7 @@ class Batch:
             shadow_intr=None if self.shadow_intr is None else self.shadow_intr[lights], shadow_res=self.shadow_res,
             textures=self.textures,
             object_texture=None if self.object_texture is None else self.object_texture[objs],
+            object_normal_texture=None if self.object_normal_texture is None else self.object_normal_texture[objs],
             tex_xform=None if self.tex_xform is None else self.tex_xform[objs],
             emission=None if self.emission is None else self.emission[objs])
 
@@ -698,17 +702,41 @@ def pattern_texture(rng: np.random.Generator, size: int = 64, cells: int = 8) ->
     return (tex * (0.75 + 0.25 * stripe[..., None])).astype(np.float32)
 
 
+def bump_texture(rng: np.random.Generator, size: int = 64, waves: int = 4, slope: float = 0.6) -> np.ndarray:
+    """A random normal (bump) texture: the normals of a periodic height field, a sum of
+    `waves` plane waves with integer frequencies 1..6 per axis and random phases, scaled
+    so the steepest slope is about `slope`; stored as RGB = (n + 1) / 2 ([size, size, 3]),
+    tangent-space z up, so it tiles without seams."""
+    y, x = np.mgrid[0:size, 0:size] / size
+    gx = np.zeros((size, size))
+    gy = np.zeros((size, size))
+    for _ in range(waves):
+        fx, fy = rng.integers(1, 7, 2)
+        ph = rng.uniform(0, 2 * np.pi)
+        arg = 2 * np.pi * (fx * x + fy * y) + ph
+        gx += 2 * np.pi * fx * np.cos(arg)
+        gy += 2 * np.pi * fy * np.cos(arg)
+    k = slope / max(np.abs(gx).max(), np.abs(gy).max(), 1e-9)
+    n = np.stack([-k * gx, -k * gy, np.ones_like(gx)], -1)
+    n /= np.linalg.norm(n, axis=-1, keepdims=True)
+    return ((n + 1) / 2).astype(np.float32)
+
+
 def with_materials(batch: Batch, seed: int = 0, n_textures: int = 8, textured_prob: float = 0.7,
-                   block_hsv=(0.08, 0.8, 0.8), block_radius=(0.04, 0.1, 0.1)) -> Batch:
+                   block_hsv=(0.08, 0.8, 0.8), block_radius=(0.04, 0.1, 0.1), n_normal_textures: int = 4,
+                   normal_prob: float = 0.5) -> Batch:
     """The batch with randomized materials: each object gets, with probability
-    textured_prob, one of n_textures random pattern textures with tiling U[0.5, 4] and
-    offset U[0, 1) per axis (MaterialRandomizer); each scene's last object (the hand
-    scenes' block) is redrawn near a calibrated hue by the fixed-hue sampler, emissive
-    with probability 0.2.  Draws come from default_rng([seed, 0x7E47, scene])."""
+    textured_prob, one of n_textures random pattern textures and, with probability
+    normal_prob, one of n_normal_textures normal textures, with tiling U[0.5, 4] and
+    offset U[0, 1) per axis shared by both (MaterialRandomizer); each scene's last object
+    (the hand scenes' block) is redrawn near a calibrated hue by the fixed-hue sampler,
+    emissive with probability 0.2.  Draws come from default_rng([seed, 0x7E47, scene])."""
     pool_rng = np.random.default_rng([seed, 0x7E47])
     textures = [pattern_texture(pool_rng) for _ in range(n_textures)]
+    textures += [bump_texture(pool_rng) for _ in range(n_normal_textures)]
     O = batch.n_objects
     tex = np.full(O, -1, np.int32)
+    ntex = np.full(O, -1, np.int32)
     xf = np.tile(np.array([1, 1, 0, 0], np.float32), (O, 1))
     em = np.zeros(O, np.float32)
     alb = batch.albedo.copy()
@@ -720,13 +748,16 @@ def with_materials(batch: Batch, seed: int = 0, n_textures: int = 8, textured_pr
         for o in range(ob, oe):
             if rng.uniform() < textured_prob:
                 tex[o] = int(rng.integers(0, n_textures))
+            if n_normal_textures and rng.uniform() < normal_prob:
+                ntex[o] = n_textures + int(rng.integers(0, n_normal_textures))
+            if tex[o] >= 0 or ntex[o] >= 0:
                 xf[o, :2] = rng.uniform(0.5, 4.0, 2)
                 xf[o, 2:] = rng.uniform(0.0, 1.0, 2)
         if oe > ob:
             a, r, k, e = fixed_hue_material(rng, block_hsv, block_radius, emissive_prob=0.2, emissive_power=(0.1, 0.5))
             alb[oe - 1], rough[oe - 1], spec[oe - 1], em[oe - 1] = a, max(r, 0.05), k, e
     return batch.replace(textures=textures, object_texture=tex, tex_xform=xf, emission=em, albedo=alb,
-                         roughness=rough, specular=spec)
+                         roughness=rough, specular=spec, object_normal_texture=ntex if n_normal_textures else None)
 
 
 # ----------------------------------------------------------------------------------

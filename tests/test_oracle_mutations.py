@@ -19,6 +19,7 @@ from tests import test_oracle_edge_cases as E
 from tests import test_oracle_geometry as G
 from tests import test_oracle_grad as D
 from tests import test_oracle_materials as MA
+from tests import test_oracle_normal_maps as NM
 from tests import test_oracle_shading as SH
 from tests import test_oracle_shadows as SD
 
@@ -139,6 +140,20 @@ MUTANTS = [
      [pin(MA.test_pixel_centres_on_texel_centres_show_the_texels)]),
     ("emission_dropped", "double U[3] = {E * alb[0], E * alb[1], E * alb[2]};", "double U[3] = {0, 0, 0};",
      [pin(MA.test_emission_adds_power_times_albedo)]),
+    # normal textures
+    ("normal_map_no_handedness", "if (dot3(Bp, B) < 0)", "if (0)",
+     [pin(NM.test_tilt_along_v_follows_the_bitangent_and_mirrored_uvs_flip_it)]),
+    ("normal_map_tangent_bitangent_swapped", "for (int k = 0; k < 3; k++) ns[k] = tn[0] * Tp[k] + tn[1] * Bp[k] + tn[2] * n[k];",
+     "for (int k = 0; k < 3; k++) ns[k] = tn[1] * Tp[k] + tn[0] * Bp[k] + tn[2] * n[k];",
+     [pin(NM.test_tilt_along_u_follows_the_tangent)]),
+    ("normal_map_not_decoded", "double tn[3] = {2 * rgb[0] - 1, 2 * rgb[1] - 1, 2 * rgb[2] - 1};",
+     "double tn[3] = {rgb[0], rgb[1], rgb[2]};", [pin(NM.test_flat_map_changes_nothing)]),
+    ("normal_map_tangent_sign", "To[k] = (e1 * dv2 - e2 * dv1) / det;", "To[k] = (e2 * dv1 - e1 * dv2) / det;",
+     [pin(NM.test_tilt_along_u_follows_the_tangent)]),
+    ("normal_map_tangent_object_space", "T[r] = M[r * 4 + 0] * To[0] + M[r * 4 + 1] * To[1] + M[r * 4 + 2] * To[2];",
+     "T[r] = To[r];", [pin(NM.test_tangent_turns_with_the_pose)]),
+    ("normal_map_ignored_by_lights", "light_term(L + l, &fs, mexp, &t, in->shadow_res);",
+     "light_term(L + l, &fr, mexp, &t, in->shadow_res);", [pin(NM.test_bump_texture_pixel_by_pixel)]),
 ]
 
 
