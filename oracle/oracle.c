@@ -309,15 +309,22 @@ static void tex_sample(const Inputs *in, int t, double u, double v, double *rgb)
                  ay * ((1 - ax) * T[3 * (j1 * W + i0) + c] + ax * T[3 * (j1 * W + i1) + c]);
 }
 
-/* The albedo at a fragment of object o: the tint times its pattern texture at the
- * transformed UV (u su + ou, v sv + ov), if it has one. */
+/* Object o's textures are sampled at the transformed UV (u su + ou, v sv + ov). */
+static void object_uv(const Inputs *in, int o, const Frag *fr, double *uv) {
+    const double *x = in->obj_txf + 4 * (int64_t)o;
+    uv[0] = fr->uv[0] * x[0] + x[2];
+    uv[1] = fr->uv[1] * x[1] + x[3];
+}
+
+/* The albedo at a fragment of object o: the tint times its pattern texture, if it has
+ * one. */
 static void fragment_albedo(const Inputs *in, int o, const Frag *fr, double *alb) {
     for (int c = 0; c < 3; c++) alb[c] = in->albedo[3 * (int64_t)o + c];
     int t = in->obj_tex ? in->obj_tex[o] : -1;
     if (t < 0) return;
-    const double *x = in->obj_txf + 4 * (int64_t)o;
-    double rgb[3];
-    tex_sample(in, t, fr->uv[0] * x[0] + x[2], fr->uv[1] * x[1] + x[3], rgb);
+    double uv[2], rgb[3];
+    object_uv(in, o, fr, uv);
+    tex_sample(in, t, uv[0], uv[1], rgb);
     for (int c = 0; c < 3; c++) alb[c] *= rgb[c];
 }
 
@@ -341,9 +348,9 @@ static void shading_normal(const Inputs *in, int f, int o, int local, const Frag
     for (int k = 0; k < 3; k++) ns[k] = fr->n[k];
     int t = in->obj_ntex ? in->obj_ntex[o] : -1;
     if (t < 0) return;
-    const double *x = in->obj_txf + 4 * (int64_t)o;
-    double rgb[3];
-    tex_sample(in, t, fr->uv[0] * x[0] + x[2], fr->uv[1] * x[1] + x[3], rgb);
+    double uv[2], rgb[3];
+    object_uv(in, o, fr, uv);
+    tex_sample(in, t, uv[0], uv[1], rgb);
     double tn[3] = {2 * rgb[0] - 1, 2 * rgb[1] - 1, 2 * rgb[2] - 1};
     double tl = sqrt(dot3(tn, tn));
     if (tl == 0) return;

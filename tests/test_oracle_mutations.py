@@ -132,8 +132,7 @@ MUTANTS = [
      [pin(MA.test_bilinear_weights_quarter_texel)]),
     ("tex_no_half_texel", "double x = u * (double)W - 0.5, y = v * (double)H - 0.5;", "double x = u * (double)W, y = v * (double)H;",
      [pin(MA.test_pixel_centres_on_texel_centres_show_the_texels)]),
-    ("tex_offset_tiling_order", "tex_sample(in, t, fr->uv[0] * x[0] + x[2], fr->uv[1] * x[1] + x[3], rgb);",
-     "tex_sample(in, t, (fr->uv[0] + x[2]) * x[0], (fr->uv[1] + x[3]) * x[1], rgb);",
+    ("tex_offset_tiling_order", "uv[0] = fr->uv[0] * x[0] + x[2];", "uv[0] = (fr->uv[0] + x[2]) * x[0];",
      [pin(MA.test_tiling_and_offset_are_periodic_shifts)]),
     ("uv_wrong_weight", "for (int k = 0; k < 2; k++) fr->uv[k] = be0 * a->uv[k] + be1 * b->uv[k] + be2 * c->uv[k];",
      "for (int k = 0; k < 2; k++) fr->uv[k] = be0 * a->uv[k] + be2 * b->uv[k] + be1 * c->uv[k];",
