@@ -245,8 +245,17 @@ typedef struct {                  /* sampled randomization parameters */
      * first, repeating; ids outside the pool mean no texture.  An emissive object adds
      * emission x albedo to the sum over lights (before exposure). */
     const int32_t *texture;       /* [O] texture id, -1 = none */
-    const float *tex_xform;       /* [O,4] su, sv, ou, ov (needed with texture) */
+    const float *tex_xform;       /* [O,4] su, sv, ou, ov (needed with texture or normal_texture) */
     const float *emission;        /* [O] emissive power >= 0 */
+    /* Normal (bump) textures (Sec. 4.3.1 MaterialRandomizer: random normal textures),
+     * NULL = none: each object's normal texture id from the same pool (-1 = none),
+     * sampled like `texture` at the same transformed UV.  The bilinear texel rgb encodes
+     * a tangent-space direction t = normalize(2 rgb - 1); the tangent frame is the
+     * triangle's (T, B from its object-space edges and UV differences, rotated with
+     * the object, T orthogonalized against the interpolated normal n, B' = +-n x T' with
+     * the UV mapping's handedness), and the lights see normalize(t_x T' + t_y B' +
+     * t_z n).  The normal channel keeps n.  Degenerate UVs leave n unchanged. */
+    const int32_t *normal_texture; /* [O] */
 } orrb_params;
 
 #define ORRB_POST_WORDS 12

@@ -67,7 +67,7 @@ class Params(C.Structure):
     _fields_ = [("albedo", P), ("roughness", P), ("specular", P), ("light_vec", P),
                 ("light_intensity", P), ("exposure", P), ("post", P), ("grain", P), ("grain_w", C.c_int32),
                 ("grain_h", C.c_int32), ("light_dir", P), ("light_cone", P), ("shadow_view", P), ("shadow_intr", P),
-                ("texture", P), ("tex_xform", P), ("emission", P)]
+                ("texture", P), ("tex_xform", P), ("emission", P), ("normal_texture", P)]
 
 
 class Outputs(C.Structure):

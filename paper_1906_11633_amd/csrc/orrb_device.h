@@ -86,6 +86,7 @@ struct RenderArgs {
     const int32_t *obj_tex;
     const float *tex_xform;
     const float *emission;
+    const int32_t *obj_ntex;  // each object's normal texture (-1 none) or null
     // post-processing of rgb8
     const float *post;   // [F, ORRB_POST_WORDS] or null
     const float *grain;  // [3, grain_h, grain_w] or null

@@ -539,6 +539,7 @@ static void fill_args(const orrb_context *ctx, const orrb_layout *L, const orrb_
     a->obj_tex = par->texture;
     a->tex_xform = par->tex_xform;
     a->emission = par->emission;
+    a->obj_ntex = par->normal_texture;
     a->pose = sc->object_pose;
     a->seg = sc->object_seg;
     a->visible = sc->object_visible;
@@ -1022,8 +1023,9 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     a.grain_h = par->grain_h;
     // shading mode of the frame kernel: depth only when nothing shaded is written
     a.shade_mode = (!out->rgb && !out->normal && !out->rgb8) ? 4
-                   : (L->shadow ? 1 : 0) | ((par->texture || par->emission) ? 2 : 0);
-    if (par->texture && !par->tex_xform) return fail(ORRB_ERR_INVALID_ARGUMENT, "texture needs tex_xform");
+                   : (L->shadow ? 1 : 0) | ((par->texture || par->emission || par->normal_texture) ? 2 : 0);
+    if ((par->texture || par->normal_texture) && !par->tex_xform)
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "texture and normal_texture need tex_xform");
     if (L->shadow) {
         a.light_dir = par->light_dir;
         a.light_cone = par->light_cone;
@@ -1102,7 +1104,7 @@ orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const o
         (L->n_lights > 0 && (!gr->light_vec || !gr->light_intensity)) || (L->n_frames > 0 && !gr->exposure))
         return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL gradient destination");
     if (L->n_spot > 0) return fail(ORRB_ERR_UNSUPPORTED, "the shading adjoint does not cover spot lights");
-    if (par->texture || par->emission)
+    if (par->texture || par->emission || par->normal_texture)
         return fail(ORRB_ERR_UNSUPPORTED, "the shading adjoint does not cover textured or emissive materials");
     if (L->max_scene_objects > grad_max_objects())
         return fail(ORRB_ERR_UNSUPPORTED, "a scene has %d objects; the adjoint supports %d", L->max_scene_objects,

@@ -325,9 +325,10 @@ ORRB_INLINE float spec_pow(float u, float m) {
 // UV transform and emissive power.
 struct MatTex {
     float2 uva, uvb, uvc;
-    int tex;
+    int tex, ntex;              // pattern and normal texture (-1 none)
     float su, sv, ou, ov;
     float emit;
+    float4 pa, pb, pc;          // object-space positions (normal texture only)
 };
 
 // Material inputs of global object o whose mesh vertices start at mvb, for the mesh
@@ -336,10 +337,17 @@ ORRB_INLINE MatTex mat_inputs(const RenderArgs &a, int o, int mvb, int4 tv) {
     MatTex t;
     t.tex = a.obj_tex ? a.obj_tex[o] : -1;
     if (t.tex >= a.n_tex) t.tex = -1;  // not a resident texture: none
+    t.ntex = a.obj_ntex ? a.obj_ntex[o] : -1;
+    if (t.ntex >= a.n_tex) t.ntex = -1;
     t.su = t.sv = 1.f;
     t.ou = t.ov = 0.f;
     t.uva = t.uvb = t.uvc = make_float2(0.f, 0.f);
-    if (t.tex >= 0) {
+    if (t.ntex >= 0) {
+        t.pa = a.mesh_pos[mvb + tv.x];
+        t.pb = a.mesh_pos[mvb + tv.z];
+        t.pc = a.mesh_pos[mvb + tv.y];
+    }
+    if (t.tex >= 0 || t.ntex >= 0) {
         const float4 x = *reinterpret_cast<const float4 *>(a.tex_xform + 4 * (int64_t)o);
         t.su = x.x;
         t.sv = x.y;
@@ -372,6 +380,44 @@ ORRB_INLINE float3 tex_bilinear(const float4 *texels, int4 info, float u, float 
               b1 * (b0 * t00.z + ax * t01.z) + ay * (b0 * t10.z + ax * t11.z));
 }
 
+// The shading normal from a normal texture's bilinear sample rgb at a fragment with
+// unit interpolated normal n: t = normalize(2 rgb - 1) in the triangle's tangent frame.
+// T and B solve e1 = du1 T + dv1 B, e2 = du2 T + dv2 B for the object-space edges and
+// UV differences (vertex order does not matter), rotated with the object by R; T is
+// orthogonalized against n, B' = n x T' flipped to the side of B (the UV mapping's
+// handedness).  Degenerate UVs, a tangent along n or t = 0 leave n.
+ORRB_INLINE float3 normal_mapped(float3 n, float3 rgb, const MatTex &mt, const float *R) {
+#pragma clang fp contract(off)
+    const float3 t = f3(2.0f * rgb.x - 1.0f, 2.0f * rgb.y - 1.0f, 2.0f * rgb.z - 1.0f);
+    const float tl2 = dot3(t, t);
+    const float du1 = mt.uvb.x - mt.uva.x, dv1 = mt.uvb.y - mt.uva.y;
+    const float du2 = mt.uvc.x - mt.uva.x, dv2 = mt.uvc.y - mt.uva.y;
+    const float det = du1 * dv2 - du2 * dv1;
+    if (!(tl2 > 0.f) || det == 0.f) return n;
+    const float id = 1.0f / det;
+    const float3 e1 = f3(mt.pb.x - mt.pa.x, mt.pb.y - mt.pa.y, mt.pb.z - mt.pa.z);
+    const float3 e2 = f3(mt.pc.x - mt.pa.x, mt.pc.y - mt.pa.y, mt.pc.z - mt.pa.z);
+    const float3 To = f3((e1.x * dv2 - e2.x * dv1) * id, (e1.y * dv2 - e2.y * dv1) * id, (e1.z * dv2 - e2.z * dv1) * id);
+    const float3 Bo = f3((e2.x * du1 - e1.x * du2) * id, (e2.y * du1 - e1.y * du2) * id, (e2.z * du1 - e1.z * du2) * id);
+    const float3 T = f3(R[0] * To.x + R[1] * To.y + R[2] * To.z, R[3] * To.x + R[4] * To.y + R[5] * To.z,
+                        R[6] * To.x + R[7] * To.y + R[8] * To.z);
+    const float3 B = f3(R[0] * Bo.x + R[1] * Bo.y + R[2] * Bo.z, R[3] * Bo.x + R[4] * Bo.y + R[5] * Bo.z,
+                        R[6] * Bo.x + R[7] * Bo.y + R[8] * Bo.z);
+    const float nt = dot3(n, T);
+    float3 Tp = f3(T.x - nt * n.x, T.y - nt * n.y, T.z - nt * n.z);
+    const float tp2 = dot3(Tp, Tp);
+    if (!(tp2 > 0.f)) return n;
+    const float tpi = rsqrtf(tp2);
+    Tp = f3(Tp.x * tpi, Tp.y * tpi, Tp.z * tpi);
+    float3 Bp = f3(n.y * Tp.z - n.z * Tp.y, n.z * Tp.x - n.x * Tp.z, n.x * Tp.y - n.y * Tp.x);
+    if (dot3(Bp, B) < 0.f) Bp = f3(-Bp.x, -Bp.y, -Bp.z);
+    const float ti = rsqrtf(tl2);
+    const float3 s = f3((t.x * Tp.x + t.y * Bp.x + t.z * n.x) * ti, (t.x * Tp.y + t.y * Bp.y + t.z * n.y) * ti,
+                        (t.x * Tp.z + t.y * Bp.z + t.z * n.z) * ti);
+    const float si = rsqrtf(dot3(s, s));
+    return f3(s.x * si, s.y * si, s.z * si);
+}
+
 // Shade the covered pixel (i, j) at eye depth z of the positive-area triangle a, b, c:
 // perspective-correct smooth normal from the unit object-space vertex normals and R,
 // then exposure * sum over lights of A * max(0, n.l) * (albedo + k_s * max(0, n.h)^m).
@@ -398,15 +444,19 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
     const float mexp = 2.0f * __builtin_amdgcn_rcpf(m.rough * m.rough) - 2.0f;
     float al0 = m.al0, al1 = m.al1, al2 = m.al2;
     float r0 = 0.f, r1 = 0.f, r2 = 0.f;
-    if (MAT) {  // pattern texture at the perspective-correct UV, then emission
-        if (mt->tex >= 0) {
+    float3 ns = n;  // the normal the lights see
+    if (MAT) {  // textures at the perspective-correct, transformed UV, then emission
+        if (mt->tex >= 0 || mt->ntex >= 0) {
             const float inv = 1.0f / (t0 + t1 + t2);
-            const float u = (t0 * mt->uva.x + t1 * mt->uvb.x + t2 * mt->uvc.x) * inv;
-            const float v = (t0 * mt->uva.y + t1 * mt->uvb.y + t2 * mt->uvc.y) * inv;
-            const float3 tx = tex_bilinear(texels, tex_info[mt->tex], u * mt->su + mt->ou, v * mt->sv + mt->ov);
-            al0 *= tx.x;
-            al1 *= tx.y;
-            al2 *= tx.z;
+            const float u = (t0 * mt->uva.x + t1 * mt->uvb.x + t2 * mt->uvc.x) * inv * mt->su + mt->ou;
+            const float v = (t0 * mt->uva.y + t1 * mt->uvb.y + t2 * mt->uvc.y) * inv * mt->sv + mt->ov;
+            if (mt->tex >= 0) {
+                const float3 tx = tex_bilinear(texels, tex_info[mt->tex], u, v);
+                al0 *= tx.x;
+                al1 *= tx.y;
+                al2 *= tx.z;
+            }
+            if (mt->ntex >= 0) ns = normal_mapped(n, tex_bilinear(texels, tex_info[mt->ntex], u, v), *mt, R);
         }
         r0 = mt->emit * al0;
         r1 = mt->emit * al1;
@@ -427,7 +477,7 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
             ld = f3(Lq.x, Lq.y, Lq.z);
             A = Lq.w;
         }
-        const float ndl = dot3(n, ld);
+        const float ndl = dot3(ns, ld);
         if (ndl <= 0.f) continue;
         if (SPOT && (lt & 15) == 2) {  // cone (smoothstep) and filtered shadow
             const SpotLight &sp = spot[lt >> 4];
@@ -442,7 +492,7 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
         const float H2 = dot3(hh, hh);
         if (H2 >= 1e-12f) {
             const float hinv = rsqrtf(H2);
-            const float3 dd = f3(n.x - hh.x * hinv, n.y - hh.y * hinv, n.z - hh.z * hinv);
+            const float3 dd = f3(ns.x - hh.x * hinv, ns.y - hh.y * hinv, ns.z - hh.z * hinv);
             // 1 - n.h evaluated as |n - h|^2 / 2: no cancellation near the highlight
             const float u = 0.5f * dot3(dd, dd);
             if (u < 1.0f) s = (mexp == 0.f) ? 1.0f : spec_pow(u, mexp);

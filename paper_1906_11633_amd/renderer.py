@@ -177,15 +177,24 @@ def device_state(batch, device="cuda") -> Dict[str, torch.Tensor]:
 
 
 def texture_state(ctx: "Context", batch, device="cuda") -> Dict[str, torch.Tensor]:
-    """Each object's resident texture id (the batch's textures uploaded to the context
-    once), as a device tensor; empty if the batch has no textured materials."""
+    """Each object's resident pattern and normal texture ids (the batch's textures
+    uploaded to the context once), as device tensors; empty if the batch has neither."""
     ot = getattr(batch, "object_texture", None)
-    if ot is None or getattr(batch, "textures", None) is None:
+    nt = getattr(batch, "object_normal_texture", None)
+    if (ot is None and nt is None) or getattr(batch, "textures", None) is None:
         return {}
     ids = np.array([ctx.add_texture(t) for t in batch.textures], np.int32)
-    ot = np.asarray(ot, np.int64)
-    mapped = np.where(ot >= 0, ids[np.clip(ot, 0, max(len(ids) - 1, 0))] if len(ids) else -1, -1).astype(np.int32)
-    return {"texture": torch.from_numpy(mapped).to(device)}
+
+    def mapped(x):
+        x = np.asarray(x, np.int64)
+        m = np.where(x >= 0, ids[np.clip(x, 0, max(len(ids) - 1, 0))] if len(ids) else -1, -1).astype(np.int32)
+        return torch.from_numpy(m).to(device)
+    out = {}
+    if ot is not None:
+        out["texture"] = mapped(ot)
+    if nt is not None:
+        out["normal_texture"] = mapped(nt)
+    return out
 
 
 @dataclass
@@ -276,7 +285,7 @@ def _params(state) -> L.Params:
                     _ptr(s["light_intensity"]), _ptr(s["exposure"]), _ptr(s.get("post")), _ptr(grain), gw, gh,
                     _ptr(s.get("light_dir")), _ptr(s.get("light_cone")), _ptr(s.get("shadow_view")),
                     _ptr(s.get("shadow_intr")), _ptr(s.get("texture")), _ptr(s.get("tex_xform")),
-                    _ptr(s.get("emission")))
+                    _ptr(s.get("emission")), _ptr(s.get("normal_texture")))
 
 
 def _structs(state, out):

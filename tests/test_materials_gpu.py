@@ -1,5 +1,6 @@
 """GPU parity of textured and emissive materials (Sec. 4.3.1 MaterialRandomizer pattern
-textures with tiling and offset; FixedHueMaterialRandomizer colours and emission):
+and normal textures with tiling and offset; FixedHueMaterialRandomizer colours and
+emission):
 resident textures and per-vertex UVs, against the oracle at the parity bar, on every
 path, alone and with shadow-casting spot lights."""
 import numpy as np
@@ -10,6 +11,7 @@ from paper_1906_11633_amd import _lib as L
 from paper_1906_11633_amd import scenes as S
 from tests import parity
 from tests.test_oracle_materials import _plane
+from tests import test_oracle_normal_maps as NM
 
 pytestmark = pytest.mark.gpu
 
@@ -45,14 +47,39 @@ def test_textured_plane(renderer, xform):
     assert st["covered"] == 64 * 64
 
 
+def _mirrored_plane():
+    m = S.plane_mesh(4, 4, 2.0, 2.0)
+    return S.Mesh(m.pos, m.nrm, m.idx, np.stack([m.uv[:, 0], 1 - m.uv[:, 1]], 1).astype(np.float32))
+
+
+NORMAL_PLANES = [
+    ("bump", lambda: NM._plane(S.bump_texture(np.random.default_rng(3)), (0.2, -0.3, 1.0))),
+    ("bump-tiled", lambda: NM._plane(S.bump_texture(np.random.default_rng(4)), (-0.4, 0.1, 1.0),
+                                     xform=(2.5, 1.5, 0.3, 0.6))),
+    ("tilt-mirrored-v", lambda: NM._plane(np.broadcast_to(NM._encode([0.1, 0.5, 0.8]), (4, 4, 3)), (0, 0.4, 1.0),
+                                          mesh=_mirrored_plane())),
+]
+
+
+@pytest.mark.parametrize("name,make", NORMAL_PLANES, ids=[c[0] for c in NORMAL_PLANES])
+def test_normal_textured_plane(renderer, name, make):
+    b = make()
+    gpu, _ = _render(renderer, b)
+    st = parity.compare(b, gpu, oracle.render(b))
+    assert st["covered"] == 64 * 64
+    plain = oracle.render(b.replace(object_normal_texture=None))
+    assert np.abs(plain["rgb"] - gpu["rgb"]).max() > 0.02  # the normal texture shows
+
+
 @pytest.mark.parametrize("tuning", TUNINGS, ids=IDS)
 def test_hand_scenes_with_materials(renderer, tuning):
     b = S.with_materials(S.config2(2, 3, 200), seed=2)
-    assert (b.object_texture >= 0).any() and (b.emission > 0).any()
+    assert (b.object_texture >= 0).any() and (b.emission > 0).any() and (b.object_normal_texture >= 0).any()
     gpu, _ = _render(renderer, b, tuning)
     st = parity.compare(b, gpu, oracle.render(b))
     print(st, flush=True)
-    plain = oracle.render(b.replace(textures=None, object_texture=None, tex_xform=None, emission=None))
+    plain = oracle.render(b.replace(textures=None, object_texture=None, tex_xform=None, emission=None,
+                                    object_normal_texture=None))
     assert np.abs(plain["rgb"] - gpu["rgb"]).max() > 0.05  # the materials show
 
 
