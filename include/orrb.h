@@ -302,7 +302,9 @@ typedef struct {
 #define ORRB_STAT_GUARD_VERTICES    4  /* vertex instances beyond the +-65536 px guard band
                                           (their triangles are discarded) */
 #define ORRB_STAT_TILED_EXTRA_FLUSH 5  /* tiled path: LDS bin flushes beyond one per tile */
-#define ORRB_STATS_WORDS 8             /* words 6 and 7 are reserved (written as 0 + 0) */
+#define ORRB_STAT_INVALID_STATE     6  /* objects, lights and frames whose state breaks a
+                                          precondition, counted by orrb_validate_batch */
+#define ORRB_STATS_WORDS 8             /* word 7 is reserved (written as 0 + 0) */
 
 typedef struct {                  /* destinations; rgb, depth, normal, seg may each be NULL */
     float *rgb;                   /* [3P] */
@@ -334,6 +336,25 @@ typedef struct {                  /* destinations; rgb, depth, normal, seg may e
 orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
                               const orrb_cameras *cameras, const orrb_params *params, const orrb_outputs *out,
                               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Check the per-call state of a render of `layout` against the preconditions the
+ * render kernels assume without testing (they are device data: testing them on the
+ * host would need a copy back).  Enqueues one kernel on `stream` that adds to
+ * stats[ORRB_STAT_INVALID_STATE] (device, [ORRB_STATS_WORDS]) the number of
+ *   objects: pose not a rotation times a uniform scale s > 0 (M^T M = s^2 I within 1e-3
+ *            relative, det > 0), a non-finite value, albedo or specular < 0,
+ *            roughness <= 0, emission < 0, a non-finite UV transform of a textured object;
+ *   lights:  a non-finite value, intensity < 0, a zero directional vector; spot lights:
+ *            a zero axis, cone cosines not 1 >= inner > outer >= -1, a shadow view that is
+ *            not a rotation, shadow focal lengths <= 0;
+ *   frames:  a view that is not a rotation (unit scale), focal lengths <= 0, near <= 0,
+ *            exposure < 0, a non-finite value (post-processing words included);
+ * each element counted once.  Renders nothing and reads no output.  Asynchronous like
+ * orrb_render_batch; the count is read with a copy on the same stream.  Errors:
+ * ORRB_ERR_INVALID_ARGUMENT for NULL arguments or missing arrays the layout needs. */
+orrb_status orrb_validate_batch(orrb_context *ctx, const orrb_layout *layout, const orrb_scenes *scenes,
+                                const orrb_cameras *cameras, const orrb_params *params, uint32_t *stats,
+                                void *stream);
 
 /* For callers that cannot allocate device memory: code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc.  Same as orrb_render_batch

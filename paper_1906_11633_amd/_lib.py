@@ -23,7 +23,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20  # ORRB_NOALLOC_SCRATCH_BYTES
 # words of the per-call stats destination (orrb_outputs.stats)
 STATS_WORDS = 8
 STAT_NAMES = ("wait_timeouts", "bin_overflow_frames", "survivor_resetup_frames", "near_vertices", "guard_vertices",
-              "tiled_extra_flushes")
+              "tiled_extra_flushes", "invalid_state")
 
 
 class OrrbError(RuntimeError):
@@ -104,6 +104,7 @@ SIGNATURES = {
     "orrb_last_error": (C.c_char_p, []),
     "orrb_add_mesh": (C.c_int, [P, P, P, C.c_int32, P, C.c_int32, C.POINTER(C.c_int32)]),
     "orrb_set_mesh_uv": (C.c_int, [P, C.c_int32, P]),
+    "orrb_validate_batch": (C.c_int, [P, P, C.POINTER(Scenes), C.POINTER(Cameras), C.POINTER(Params), P, P]),
     "orrb_add_texture": (C.c_int, [P, P, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     "orrb_layout_create": (C.c_int, [P, C.POINTER(LayoutDesc), C.POINTER(P)]),
     "orrb_layout_destroy": (None, [P]),

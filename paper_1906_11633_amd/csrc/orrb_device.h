@@ -154,6 +154,8 @@ hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu);
 hipError_t launch_shadow_cams(const int32_t *spot_light, int n_spot, const float *shadow_view, const float *shadow_intr,
                               float *view, float *intr, float *nearp, hipStream_t stream);
 hipError_t launch_post(const RenderArgs &a, hipStream_t stream, int n_frames, int64_t max_frame_pixels);
+hipError_t launch_validate(const RenderArgs &a, const float *post, int n_obj, int n_lights, int n_frames,
+                           uint32_t *stats, hipStream_t stream);
 hipError_t read_wait_timeouts(unsigned int *out);  // frame-kernel waits that hit their bound
 bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height);
 bool frame_fits_global(int64_t n_verts, int n_obj, int64_t n_tris, int width, int height);

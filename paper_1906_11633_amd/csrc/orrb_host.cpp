@@ -1088,6 +1088,31 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
     return render_impl(ctx, L, sc, cam, par, out, workspace, workspace_bytes, stream, true);
 }
 
+orrb_status orrb_validate_batch(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+                                const orrb_params *par, uint32_t *stats, void *stream) {
+    g_last_error.clear();
+    if (!ctx || !L || !sc || !cam || !par || !stats) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL handle, struct or stats");
+    if (L->ctx != ctx) return fail(ORRB_ERR_INVALID_ARGUMENT, "layout belongs to another context");
+    if (L->n_frames == 0 && L->n_objects == 0 && L->n_lights == 0) return ORRB_OK;
+    {
+        const orrb_status st = check_inputs(L, sc, cam, par);
+        if (st != ORRB_OK) return st;
+    }
+    if (L->n_spot > 0 && (!par->light_dir || !par->light_cone || !par->shadow_view || !par->shadow_intr))
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "spot lights need light_dir, light_cone, shadow_view and shadow_intr");
+    RenderArgs a;
+    fill_args(ctx, L, sc, cam, par, &a);
+    a.light_dir = par->light_dir;
+    a.light_cone = par->light_cone;
+    a.shadow_view = par->shadow_view;
+    a.shadow_intr = par->shadow_intr;
+    ScopedDevice sd(ctx->device);
+    const hipError_t e = launch_validate(a, par->post, (int)L->n_objects, (int)L->n_lights, (int)L->n_frames, stats,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess) return fail(ORRB_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ORRB_OK;
+}
+
 orrb_status orrb_shade_backward(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
                                 const orrb_params *par, const uint64_t *vis, const float *grad_rgb, const orrb_grads *gr,
                                 void *workspace, size_t workspace_bytes, void *stream) {

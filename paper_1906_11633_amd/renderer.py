@@ -266,6 +266,15 @@ def render_batch(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], o
                                       _ptr(workspace), int(workspace.numel()), C.c_void_p(st.cuda_stream)))
 
 
+def validate_batch(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], stats: torch.Tensor, stream=None):
+    """orrb_validate_batch on `stream`: adds to stats["invalid_state"] the objects, lights
+    and frames of `state` that break the render's preconditions."""
+    sc, cam, par, _ = _structs(state, {})
+    st = stream if stream is not None else torch.cuda.current_stream(ctx.device)
+    L.check(ctx.lib.orrb_validate_batch(ctx.handle, layout.handle, C.byref(sc), C.byref(cam), C.byref(par),
+                                        _ptr(stats), C.c_void_p(st.cuda_stream)))
+
+
 def render_batch_noalloc(ctx: Context, layout: Layout, state: Dict[str, torch.Tensor], out: Dict[str, torch.Tensor],
                          stream=None):
     """orrb_render_batch_noalloc on `stream`: the workspace comes from the library's fixed

@@ -85,6 +85,7 @@ def test_null_arguments_rejected(lib):
     assert lib.orrb_render_batch(None, None, None, None, None, None, None, 0, None) == 1
     assert lib.orrb_layout_info_get(None, None) == 1
     assert lib.orrb_wait_timeouts(None, None) == 1
+    assert lib.orrb_validate_batch(None, None, None, None, None, None, None) == 1
     lib.orrb_destroy(None)
     lib.orrb_layout_destroy(None)
 
@@ -110,5 +111,6 @@ def test_stat_words_match_header():
     assert [v for _, v in sorted(words.items(), key=lambda kv: kv[1])] == list(range(len(words)))
     expect = {"wait_timeouts": "wait_timeouts", "bin_overflow_frames": "bin_overflow",
               "survivor_resetup_frames": "survivor_resetup", "near_vertices": "near_vertices",
-              "guard_vertices": "guard_vertices", "tiled_extra_flushes": "tiled_extra_flush"}
+              "guard_vertices": "guard_vertices", "tiled_extra_flushes": "tiled_extra_flush",
+              "invalid_state": "invalid_state"}
     assert [expect[n] for n in L.STAT_NAMES] == header_order
