@@ -318,10 +318,8 @@ typedef struct {                  /* destinations; rgb, depth, normal, seg may e
     float *alpha;                 /* [P] or NULL: transparency channel (Sec. 4.4), 1 where a
                                      triangle covers the pixel centre, 0 for background */
     uint8_t *rgb8;                /* [3P] or NULL: post-processed 3 x 8-bit RGB, planar like
-                                     rgb.  Without `rgb` (the paper's 3 x 8-bit format) the
-                                     render kernels encode each pixel as they write it; with
-                                     `rgb` a separate pass encodes the written fp32 rgb.  Both
-                                     give the same bytes. */
+                                     rgb, encoded by the render kernels as they write each
+                                     pixel; `rgb` may be NULL (the paper's 3 x 8-bit format) */
     orrb_track *track;            /* [sum over frames of the scene's objects] or NULL */
 } orrb_outputs;
 
@@ -452,8 +450,6 @@ typedef struct {
     double raster_ms;          /* summed device time of k_raster_shade launches (tiled path) */
     double frame_ms;           /* summed device time of k_frame launches (frame path) */
     int64_t vertex_launches, raster_launches, frame_launches;
-    double post_ms;            /* summed device time of k_post launches (rgb8 with rgb) */
-    int64_t post_launches;
 } orrb_kernel_times;
 
 /* Enable (1) or disable (0) per-kernel timing and reset the totals.  While enabled,

@@ -93,8 +93,7 @@ class Grads(C.Structure):
 
 class KernelTimes(C.Structure):
     _fields_ = [("vertex_ms", C.c_double), ("raster_ms", C.c_double), ("frame_ms", C.c_double),
-                ("vertex_launches", C.c_int64), ("raster_launches", C.c_int64), ("frame_launches", C.c_int64),
-                ("post_ms", C.c_double), ("post_launches", C.c_int64)]
+                ("vertex_launches", C.c_int64), ("raster_launches", C.c_int64), ("frame_launches", C.c_int64)]
 
 
 # name -> (restype, argtypes)

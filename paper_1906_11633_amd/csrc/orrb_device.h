@@ -153,7 +153,6 @@ hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu);
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu);
 hipError_t launch_shadow_cams(const int32_t *spot_light, int n_spot, const float *shadow_view, const float *shadow_intr,
                               float *view, float *intr, float *nearp, hipStream_t stream);
-hipError_t launch_post(const RenderArgs &a, hipStream_t stream, int n_frames, int64_t max_frame_pixels);
 hipError_t launch_validate(const RenderArgs &a, const float *post, int n_obj, int n_lights, int n_frames,
                            uint32_t *stats, hipStream_t stream);
 hipError_t read_wait_timeouts(unsigned int *out);  // frame-kernel waits that hit their bound

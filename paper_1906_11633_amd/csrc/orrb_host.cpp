@@ -103,9 +103,9 @@ struct ScopedDevice {
 struct KernelTimer {
     bool enabled = false;
     std::vector<hipEvent_t> pool;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[4];  // 0 vertex, 1 raster, 2 frame, 3 post
-    double total_ms[4] = {0, 0, 0, 0};
-    int64_t count[4] = {0, 0, 0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];  // 0 vertex, 1 raster, 2 frame
+    double total_ms[3] = {0, 0, 0};
+    int64_t count[3] = {0, 0, 0};
     hipEvent_t get() {
         hipEvent_t e = nullptr;
         if (!pool.empty()) {
@@ -117,7 +117,7 @@ struct KernelTimer {
         return e;
     }
     hipError_t drain() {
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 3; ++k) {
             for (auto &pr : pending[k]) {
                 hipError_t e = hipEventSynchronize(pr.second);
                 if (e != hipSuccess) return e;
@@ -1055,10 +1055,9 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     hipStream_t st = (hipStream_t)stream;
     KernelTimer &T = ctx->timer;
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
         if (k < 2 && a.n_titems == 0) continue;  // no frame on the tiled path
         if (k == 2 && a.n_fitems == 0) continue;
-        if (k == 3 && !(a.out_rgb8 && a.out_rgb)) continue;  // 8-bit output alone: encoded by the render kernels
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (T.enabled && timing) {
             e0 = T.get();
@@ -1066,10 +1065,7 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
             if (e0) e = hipEventRecord(e0, st);
         }
         if (e == hipSuccess)
-            e = k == 0   ? launch_vertex(a, st)
-                : k == 1 ? launch_raster(a, st, ctx->n_cu)
-                : k == 2 ? launch_frame(a, st, ctx->n_cu)
-                         : launch_post(a, st, (int)L->n_frames, L->max_frame_pixels);
+            e = k == 0 ? launch_vertex(a, st) : k == 1 ? launch_raster(a, st, ctx->n_cu) : launch_frame(a, st, ctx->n_cu);
         if (T.enabled && timing && e0 && e1 && e == hipSuccess) {
             e = hipEventRecord(e1, st);
             T.pending[k].push_back({e0, e1});
@@ -1193,7 +1189,7 @@ orrb_status orrb_profile_enable(orrb_context *ctx, int enable) {
     ScopedDevice sd(ctx->device);
     HIP_TRY(ctx->timer.drain());
     ctx->timer.enabled = enable != 0;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 3; ++k) {
         ctx->timer.total_ms[k] = 0;
         ctx->timer.count[k] = 0;
     }
@@ -1221,8 +1217,6 @@ orrb_status orrb_profile_read(orrb_context *ctx, orrb_kernel_times *out) {
     out->vertex_launches = ctx->timer.count[0];
     out->raster_launches = ctx->timer.count[1];
     out->frame_launches = ctx->timer.count[2];
-    out->post_ms = ctx->timer.total_ms[3];
-    out->post_launches = ctx->timer.count[3];
     return ORRB_OK;
 }
 

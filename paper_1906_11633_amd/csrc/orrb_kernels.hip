@@ -347,7 +347,7 @@ ORRB_INLINE void raster_shade_tile(const RenderArgs &a, int item, LD &L) {
     const CamF cam = frame_camera(a, f);
     const int64_t HW = (int64_t)fi.width * fi.height, po = fi.pixel_offset;
     const float inv_tw = __builtin_amdgcn_rcpf((float)tw);
-    const bool fused = a.out_rgb8 && !a.out_rgb;  // 8-bit output encoded here (no fp32 rgb)
+    const bool fused = a.out_rgb8 != nullptr;  // 8-bit output encoded as the pixel is written
     PostFrame pq;
     if (fused) pq = post_frame(a, f);
     for (int p = tid; p < tw * th; p += kBlock) {
@@ -524,16 +524,15 @@ struct StageInfo {
     int W, H, x0, y0, vec, f;
 };
 
-// The 8-bit output encoded by the frame kernel itself (rgb8 requested without the fp32
-// rgb): the waves that write tiles out keep the grading constants of the last frame
-// they wrote.
+// The 8-bit output, encoded by the frame kernel as it writes tiles out: the waves that
+// write them keep the grading constants of the last frame they wrote.
 struct PostCache {
     int f = -1;
     PostFrame q;
     float3 o_bg;  // post_grade of a background pixel (rgb 0)
 };
 
-ORRB_INLINE bool fused_rgb8(const RenderArgs &a) { return a.out_rgb8 && !a.out_rgb; }
+ORRB_INLINE bool fused_rgb8(const RenderArgs &a) { return a.out_rgb8 != nullptr; }
 
 // Codes of the lane's four pixels (i .. i + 3, j) of frame f from linear rgb v, stored
 // to the 8-bit planes: one 4-byte store per plane when the group is whole and aligned.
@@ -1745,7 +1744,7 @@ hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu) {
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu) {
     if (a.n_fitems <= 0 || a.f_grid <= 0) return hipSuccess;
     const int grid = a.f_grid;  // the schedule's grid (at most the CU count)
-    const bool aux = a.out_alpha || a.out_track || (a.out_rgb8 && !a.out_rgb), mixed = a.fscratch != nullptr;
+    const bool aux = a.out_alpha || a.out_track || a.out_rgb8, mixed = a.fscratch != nullptr;
     const dim3 g(grid), b(kFT);
 #define ORRB_FRAME(AUX_, MIXED_, SHADE_) hipLaunchKernelGGL((k_frame<AUX_, MIXED_, SHADE_>), g, b, 0, stream, a)
     switch (a.shade_mode) {

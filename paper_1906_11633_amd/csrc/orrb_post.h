@@ -1,8 +1,8 @@
 // Colour grading, grain and 3 x 8-bit sRGB encoding of linear rgb (Sec. 4.3.1
 // PostprocessingRandomizer: colour grading hue, saturation, contrast, temperature and
-// tint, and grain; Sec. 5 benchmarks 200 x 200 images in 3 x 8-bit RGB), shared by the
-// separate encoding pass (k_post) and the epilogue of the render kernels.  Evaluated
-// without contraction, so every kernel that inlines it produces the same bytes.
+// tint, and grain; Sec. 5 benchmarks 200 x 200 images in 3 x 8-bit RGB): the epilogue of
+// the render kernels, which encode each pixel as they write it.  Evaluated without
+// contraction, so every kernel that inlines it produces the same bytes.
 #pragma once
 
 #include "orrb_primitives.h"
@@ -135,18 +135,6 @@ ORRB_INLINE int grain_coord_small(int x, int S, float rs, int o, int n, float rn
     return t - n * div_small(t, n, rn);
 }
 
-// Row and column of pixel p of a frame W wide: 32-bit division when p fits.
-ORRB_INLINE void pixel_rc(int64_t p, int W, int &j, int &i) {
-    if (p <= 0xffffffffll) {
-        const unsigned u = (unsigned)p, jj = u / (unsigned)W;
-        j = (int)jj;
-        i = (int)(u - jj * (unsigned)W);
-    } else {
-        j = (int)(p / W);
-        i = (int)(p - (int64_t)j * W);
-    }
-}
-
 // Plane value at byte offset `off` (a 32-bit offset from a uniform base: one
 // scalar-based load, no per-lane 64-bit address arithmetic).
 ORRB_INLINE float grain_at(const float *base, unsigned off) {
@@ -189,13 +177,6 @@ ORRB_INLINE void grain_ij(const RenderArgs &a, const PostFrame &q, int i, int j,
 ORRB_INLINE unsigned grain_texel(const RenderArgs &a, const PostFrame &q, int i, int j) {
     const int tx = grain_coord(i, q.gs, q.gx, a.grain_w), ty = grain_coord(j, q.gs, q.gy, a.grain_h);
     return (unsigned)(ty * a.grain_w + tx) * 4u;
-}
-
-// The same for the group starting at pixel p0 of a frame W wide.
-ORRB_INLINE void grain_row(const RenderArgs &a, const PostFrame &q, int W, int64_t p0, float g[3][4]) {
-    int j, i;
-    pixel_rc(p0, W, j, i);
-    grain_ij(a, q, i, j, g);
 }
 
 // The 8-bit codes of four consecutive pixels of one row starting at (i, j), linear rgb v
