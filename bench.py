@@ -31,7 +31,7 @@ METRIC = "randomized 4-channel 200x200 frames/sec on 1 MI355X; shading-grad/sec;
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_frame_traffic.json")
 # the frame kernel's source: its file and the headers it includes
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1906_11633_amd", "csrc", f)
-               for f in ("orrb_kernels.hip", "orrb_primitives.h", "orrb_device.h")]
+               for f in ("orrb_kernels.hip", "orrb_primitives.h", "orrb_device.h", "orrb_post.h")]
 
 
 def kernel_source_sha() -> str:
