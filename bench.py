@@ -298,9 +298,7 @@ def measure_uneven(args, r, S):
     out3 = r.alloc_outputs(job3)
     tuning, _ = autotune(r.ctx, job3.layout, job3.state, out3, job3.workspace)
     inf3 = job3.layout.info
-    # kernels one render of this layout launches: the frame kernel for frames on the
-    # frame path, the vertex and raster kernels for any on the tiled path
-    g_nodes = (1 if inf3.frame_path_frames > 0 else 0) + (2 if inf3.tile_items > 0 else 0)
+    g_nodes = int(inf3.render_kernels)  # kernel nodes of the captured graph
     stream = torch.cuda.Stream()
     g = Graph(r.ctx, job3.layout, job3.state, out3, job3.workspace, stream)
     with torch.cuda.stream(stream):

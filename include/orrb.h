@@ -164,6 +164,8 @@ typedef struct {
     size_t grad_workspace_bytes; /* workspace orrb_shade_backward needs */
     size_t table_bytes;          /* device memory the layout itself holds (its tables) */
     orrb_tuning tuning;
+    int64_t render_kernels;      /* kernel launches one orrb_render_batch makes (current tuning,
+                                    shadow frames included): a captured graph's kernel nodes */
 } orrb_layout_info;
 
 /* Validate `desc` against the context's meshes and build a layout (device tables are

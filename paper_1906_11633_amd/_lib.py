@@ -52,7 +52,7 @@ class LayoutInfo(C.Structure):
                 ("triangle_instances", C.c_int64), ("tile_items", C.c_int64), ("frame_path_frames", C.c_int64),
                 ("workspace_bytes", C.c_size_t),
                 ("workspace_bytes_any", C.c_size_t), ("grad_workspace_bytes", C.c_size_t),
-                ("table_bytes", C.c_size_t), ("tuning", Tuning)]
+                ("table_bytes", C.c_size_t), ("tuning", Tuning), ("render_kernels", C.c_int64)]
 
 
 class Scenes(C.Structure):

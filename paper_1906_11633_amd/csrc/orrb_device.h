@@ -16,6 +16,7 @@ constexpr int kMaxSpots = 4;         // spot lights per scene
 constexpr int kGuard = 1 << 24;      // snapped coordinates beyond this are discarded
 constexpr int kSmallExtent = 1 << 14;// triangles up to 64 px wide use exact int32 edges
 constexpr unsigned long long kEmptyKey = ~0ull;
+constexpr int kFrameQueue = 8;       // word of the workspace counters the frame kernel claims from
 
 // Per frame, built on the host from the layout.
 struct FrameInfo {
@@ -47,7 +48,9 @@ struct RenderArgs {
     const int32_t *fitems;  // frames rendered by k_frame
     const int32_t *light_type;
     int32_t n_vitems, n_titems, n_fitems;
-    int32_t f_grid;         // frame kernel grid: workgroup b renders fitems[b + k f_grid] (-1: none)
+    int32_t f_grid;         // frame kernel grid: workgroup b starts with fitems[b]
+    int32_t f_dynamic;      // 0: workgroup b then renders fitems[b + k f_grid]; 1: it claims
+                            // fitems[f_grid + queue[kFrameQueue]++] after each frame
     int32_t tile_w, tile_h, bin_cap;
     int32_t persistent;
     // resident meshes
@@ -95,7 +98,7 @@ struct RenderArgs {
     int4 *vtx_pos;     // per vertex instance: X, Y (1/256 px), bits of fp32 1/w, valid flag
     float4 *obj_rot;   // per (frame, object): rows of the fp32 view rotation (x, y, z, 0)
     int4 *obj_bbox;    // per (frame, object): covered pixel-centre range i0, j0, i1, j1
-    unsigned int *queue;  // persistent work counter
+    unsigned int *queue;  // persistent work counters: [0] tiled path, [kFrameQueue] frame kernel
     // frame kernel, frames whose scene data live in global scratch (mode 1): one slice
     // of fscratch_stride bytes per workgroup holding fs_verts snapped vertices (X, Y,
     // 1/w), fs_surv survivor entries and fs_bins 16-bit bin entries; null if none

@@ -174,9 +174,10 @@ struct orrb_layout {
     // frames on the frame kernel with scene data in global scratch (tuning path 2)
     int64_t gframes = 0, gf_verts = 0, gf_tris = 0;
     std::vector<int2> vitems, titems;
-    std::vector<int32_t> fitems;  // frame-kernel schedule (see schedule_frames); -1 = no frame
+    std::vector<int32_t> fitems;  // frame-kernel schedule (see schedule_frames)
     int64_t f_frames = 0;          // frames on the frame kernel
     int32_t f_grid = 0;            // its persistent grid
+    int32_t f_dynamic = 0;         // 1: frames claimed from a counter (uneven batch)
     std::vector<int32_t> light_type;
     Packed tab;  // frames, objs, vitems, titems, fitems, light_type, spot tables
     size_t o_frames = 0, o_objs = 0, o_vitems = 0, o_titems = 0, o_fitems = 0, o_light_type = 0;
@@ -272,16 +273,19 @@ static bool valid_tuning(const orrb_tuning &t) {
     return raster_lds_bytes(t.tile_w, t.tile_h, t.bin_cap) <= 160 * 1024;
 }
 
-// Static schedule of the frame kernel's persistent grid (min(frames, CUs) workgroups):
-// frames go, heaviest first, to the workgroup with the least estimated work (longest
-// processing time first), so an uneven batch finishes nearly together.  Workgroup b
-// renders fitems[b], fitems[b + grid], ...; -1 fills the slots of workgroups with fewer
-// frames.  Estimated work: triangles (half again when the scene data live in global
-// scratch) plus a quarter per pixel.  A uniform batch keeps the plain frame order.
+// Schedule of the frame kernel's persistent grid (min(frames, CUs) workgroups).  A
+// uniform batch keeps the plain frame order and a static assignment: workgroup b
+// renders fitems[b], fitems[b + grid], ...  An uneven batch is sorted by estimated work,
+// heaviest first, and handed out at run time: workgroup b starts with fitems[b] and each
+// workgroup takes the next unclaimed frame from a counter as it finishes one, so the
+// workgroups end within about one light frame of each other whatever the estimate's
+// error.  Estimated work: triangles (half again when the scene data live in global
+// scratch) plus a quarter per pixel.
 static void schedule_frames(orrb_layout *L) {
     const int64_t n = (int64_t)L->fitems.size();
     L->f_frames = n;
     L->f_grid = (int32_t)std::min<int64_t>(n, L->ctx ? L->ctx->n_cu : 256);
+    L->f_dynamic = 0;
     if (n == 0) return;
     std::vector<double> cost(n);
     bool uniform = true;
@@ -290,26 +294,25 @@ static void schedule_frames(orrb_layout *L) {
         cost[k] = (double)L->scene_tris[fi.scene] * (fi.mode ? 1.5 : 1.0) + 0.25 * (double)fi.width * fi.height;
         uniform = uniform && cost[k] == cost[0];
     }
-    if (uniform) return;
-    const int G = L->f_grid;
+    if (uniform || n <= L->f_grid) return;
     std::vector<int64_t> order(n);
     for (int64_t k = 0; k < n; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
-    std::vector<double> load(G, 0.0);
-    std::vector<std::vector<int32_t>> lists(G);
-    for (int64_t k : order) {
-        int b = 0;
-        for (int g = 1; g < G; ++g)
-            if (load[g] < load[b]) b = g;
-        load[b] += cost[k];
-        lists[b].push_back(L->fitems[k]);
-    }
-    size_t len = 0;
-    for (auto &l : lists) len = std::max(len, l.size());
-    std::vector<int32_t> slots((size_t)G * len, -1);
-    for (int g = 0; g < G; ++g)
-        for (size_t r = 0; r < lists[g].size(); ++r) slots[(size_t)g + r * G] = lists[g][r];
-    L->fitems.swap(slots);
+    std::vector<int32_t> sorted(n);
+    for (int64_t k = 0; k < n; ++k) sorted[k] = L->fitems[order[k]];
+    L->fitems.swap(sorted);
+    L->f_dynamic = 1;
+}
+
+// Kernel launches of one render call: the shadow frames' (camera gather + their own),
+// vertex + raster for the tiled path, the frame kernel (after a counter clear when its
+// frames are claimed at run time).
+static int64_t render_kernels(const orrb_layout *L) {
+    if (L->n_frames == 0) return 0;
+    int64_t n = L->shadow ? 1 + render_kernels(L->shadow) : 0;
+    if (!L->titems.empty()) n += 2;
+    if (!L->fitems.empty()) n += 1 + L->f_dynamic;
+    return n;
 }
 
 static WsLayout ws_layout(const orrb_layout *L) {
@@ -925,6 +928,7 @@ orrb_status orrb_layout_info_get(const orrb_layout *L, orrb_layout_info *info) {
     info->grad_workspace_bytes = grad_workspace(L);
     info->table_bytes = L->tab.dev.bytes + L->gtab.dev.bytes;
     info->tuning = L->tuning;
+    info->render_kernels = render_kernels(L);
     return ORRB_OK;
 }
 
@@ -1001,6 +1005,7 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     a.fitems = L->tab.at<int32_t>(L->o_fitems);
     a.n_fitems = (int32_t)L->fitems.size();
     a.f_grid = L->f_grid;
+    a.f_dynamic = L->f_dynamic;
     a.n_vitems = (int32_t)L->vitems.size();
     a.n_titems = (int32_t)L->titems.size();
     a.tile_w = L->tuning.tile_w;

@@ -603,6 +603,7 @@ struct FrameLds {
     int cons_seq[kFW];                       // frame each store wave takes tiles from
     int published, all_published;            // frames published; 1 once no more will be
     int cbar;                                // compute-wave barrier arrivals
+    int next_item[2];                        // claimed work item after frame seq, in [seq & 1]
     int abort_flag;                          // 1 once a wait reached its bound: every wave stops
     // Busy tiles rendered by a compute wave and written out by a store wave: planes
     // r, g, b, nx, ny, nz, seg (as bits) and the visibility key per tile pixel.
@@ -1086,7 +1087,6 @@ ORRB_INLINE void stage_end(FrameLds &S, int s, int f, int64_t po, int W, int H, 
 ORRB_INLINE void frame_warm(const RenderArgs &a, int item, int lane) {
     if (item >= a.n_fitems) return;
     const int f = a.fitems[item];
-    if (f < 0) return;
     const FrameInfo fi = a.frames[f];
     int acc = 0;
     if (lane < fi.n_obj) {
@@ -1103,6 +1103,22 @@ ORRB_INLINE void frame_warm(const RenderArgs &a, int item, int lane) {
         acc += __float_as_int(a.view[12 * (int64_t)f]) + __float_as_int(a.view[12 * (int64_t)f + 11]) +
                __float_as_int(a.intr[4 * (int64_t)f]) + __float_as_int(a.near_plane[f]) + __float_as_int(a.exposure[f]);
     asm volatile("" ::"v"(acc));
+}
+
+// The workgroup's work item after frame `seq` (item `item`), found by the first compute
+// wave that runs out of tiles: with the dynamic schedule it claims the next frame from
+// the counter and leaves it in LDS for the other waves, read after the frame's last
+// barrier.  The wave then touches that item's tables (frame_warm).
+ORRB_INLINE void frame_next(const RenderArgs &a, FrameLds &S, int item, int seq, int lane) {
+    int next = item + (int)gridDim.x;
+    if (a.f_dynamic) {
+        if (lane == 0) {
+            next = a.f_grid + (int)atomicAdd(a.queue + kFrameQueue, 1u);
+            S.next_item[seq & 1] = next;
+        }
+        next = __builtin_amdgcn_readlane(next, 0);
+    }
+    frame_warm(a, next, lane);
 }
 
 // Store wave: write staged tile s (every output plane) and free the slot.
@@ -1472,7 +1488,7 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
         if (lane == 0) slot = atomicAdd(&S.misc[0], 1);
         slot = __builtin_amdgcn_readlane(slot, 0);
         if (slot >= n_busy) {
-            if (slot == n_busy) frame_warm(a, item + gridDim.x, lane);
+            if (slot == n_busy) frame_next(a, S, item, seq, lane);
             break;
         }
         const int t = S.order[slot];
@@ -1646,13 +1662,12 @@ __global__ __launch_bounds__(kFT) void k_frame(RenderArgs a) {
     __syncthreads();  // the only barrier of all 16 waves; compute waves use frame_barrier
     if (wave < kFCW) {
         int gen = 0;  // compute-wave barrier generation
-        for (int item = blockIdx.x, seq = 0; item < a.n_fitems; item += gridDim.x) {
+        for (int item = blockIdx.x, seq = 0; item < a.n_fitems; ++seq) {
             const int f = a.fitems[item];
-            if (f < 0) continue;  // this workgroup's schedule is shorter
             const bool stop = MIXED && a.frames[f].mode != 0 ? frame_render<AUX, true, SHADE>(a, S, item, seq, gen)
                                                              : frame_render<AUX, false, SHADE>(a, S, item, seq, gen);
             if (stop) break;
-            ++seq;
+            item = a.f_dynamic ? S.next_item[seq & 1] : item + (int)gridDim.x;  // after the frame's last barrier
         }
         if (wave == 0 && lane == 0) __hip_atomic_store(&S.all_published, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
@@ -1739,10 +1754,17 @@ hipError_t launch_raster(const RenderArgs &a, hipStream_t stream, int n_cu) {
     return hipErrorInvalidValue;
 }
 
+__global__ void k_frame_queue_reset(unsigned int *q) {
+    if (threadIdx.x == 0) *q = 0u;
+}
+
 // Persistent: one workgroup per CU (the frame LDS allows no more), each rendering
-// frames blockIdx.x, blockIdx.x + gridDim.x, ...
+// frames blockIdx.x, blockIdx.x + gridDim.x, ... or, with the dynamic schedule, frame
+// blockIdx.x and then the frames it claims (counter cleared by a one-thread kernel first:
+// the workspace arrives uninitialised).
 hipError_t launch_frame(const RenderArgs &a, hipStream_t stream, int n_cu) {
     if (a.n_fitems <= 0 || a.f_grid <= 0) return hipSuccess;
+    if (a.f_dynamic) hipLaunchKernelGGL(k_frame_queue_reset, dim3(1), dim3(kWave), 0, stream, a.queue + kFrameQueue);
     const int grid = a.f_grid;  // the schedule's grid (at most the CU count)
     const bool aux = a.out_alpha || a.out_track || a.out_rgb8, mixed = a.fscratch != nullptr;
     const dim3 g(grid), b(kFT);

@@ -1,7 +1,7 @@
 """Parity at the benchmark's full sizes, in the launch configuration the benchmark
 times: the 768-frame batch of 256 hand-like scenes x 3 cameras at 200x200 (one
 frame-kernel launch, four channels) and the 3,072-frame uneven batch (autotuned tiling,
-HIP-graph replay).  The oracle renders a seeded sample of whole scenes (always the first
+HIP-graph replay; its frames are claimed at run time, heaviest first).  The oracle renders a seeded sample of whole scenes (always the first
 and the last, so the first and last work items of the persistent grid are covered); the
 GPU frames of those scenes are cut out of the full-size outputs and compared at the
 parity bar."""
@@ -53,6 +53,7 @@ def test_config2_full_size_sampled(renderer):
     b = S.config2(2, 256, 200)
     job = renderer.prepare(b)
     assert job.layout.info.frame_path_frames == b.n_frames  # the timed kernel
+    assert job.layout.info.render_kernels == 1  # a uniform batch: static schedule, no counter
     out = renderer.alloc_outputs(job)
     for _ in range(2):  # a second launch over the same buffers, as in the timed loop
         renderer.render(job, out)
@@ -79,4 +80,33 @@ def test_uneven_full_size_sampled(renderer):
     scenes = sorted(set(_sample(1024, 3, 12)) | {int(tris.argmax())})
     st = _check(b, out, scenes)
     assert st["covered"] > 1000
+    assert renderer.ctx.wait_timeouts() == 0
+
+
+def test_uneven_full_size_every_frame_once(renderer):
+    """The frame kernel's run-time schedule at full size: all 3,072 frames of the uneven
+    batch in one frame-kernel launch (tuning path 2), replayed from a graph (the claim
+    counter is cleared inside it), are bit-identical to the tiled path's frames, so no
+    frame is skipped or rendered twice over another."""
+    import torch
+    from paper_1906_11633_amd.renderer import Graph
+    b = S.config3(3, 1024)
+    job = renderer.prepare(b)
+    job.layout.set_tuning(32, 32, 512, 0, 2)
+    assert job.layout.info.frame_path_frames == b.n_frames and job.layout.info.tile_items == 0
+    assert job.layout.info.render_kernels == 2  # counter clear + frame kernel
+    out = renderer.alloc_outputs(job, tri_id=True)
+    for v in out.values():
+        v.fill_(7)  # a frame left out would keep this
+    stream = torch.cuda.Stream()
+    g = Graph(renderer.ctx, job.layout, job.state, out, job.workspace, stream)
+    for _ in range(3):
+        g.replay(stream)
+        stream.synchronize()
+    g.close()
+    job.layout.set_tuning(32, 32, 256, 1, 1)
+    ref = renderer.render(job, tri_id=True)
+    torch.cuda.synchronize()
+    for k in ("rgb", "depth", "normal", "seg", "tri_id"):
+        assert torch.equal(out[k], ref[k]), k
     assert renderer.ctx.wait_timeouts() == 0
