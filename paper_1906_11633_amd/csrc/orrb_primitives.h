@@ -363,12 +363,15 @@ ORRB_INLINE MatTex mat_inputs(const RenderArgs &a, int o, int mvb, int4 tv) {
 
 // Bilinear sample of a texture at (u, v), repeating: texel (i, j) is centred at
 // ((i + 1/2) / W, (j + 1/2) / H), row 0 first.
-ORRB_INLINE float3 tex_bilinear(const float4 *texels, int4 info, float u, float v) {
+ORRB_INLINE float3 tex_bilinear(const float4 *texels, int4 info, double u, double v) {
 #pragma clang fp contract(off)
+    // texel coordinates and weights in FP64: a bright pixel on a contrasting texel edge
+    // would otherwise carry the fp32 rounding of u W into its colour
     const int W = info.y, H = info.z;
-    const float x = u * (float)W - 0.5f, y = v * (float)H - 0.5f;
-    const float fx = floorf(x), fy = floorf(y), ax = x - fx, ay = y - fy;
-    int i0 = (int)fmodf(fx, (float)W), j0 = (int)fmodf(fy, (float)H);
+    const double x = u * (double)W - 0.5, y = v * (double)H - 0.5;
+    const double fx = floor(x), fy = floor(y);
+    const float ax = (float)(x - fx), ay = (float)(y - fy);
+    int i0 = (int)((long long)fx % W), j0 = (int)((long long)fy % H);
     if (i0 < 0) i0 += W;
     if (j0 < 0) j0 += H;
     const int i1 = i0 + 1 == W ? 0 : i0 + 1, j1 = j0 + 1 == H ? 0 : j0 + 1;
@@ -447,9 +450,13 @@ ORRB_INLINE PixelOut shade_pixel(int xa, int ya, int xb, int yb, int xc, int yc,
     float3 ns = n;  // the normal the lights see
     if (MAT) {  // textures at the perspective-correct, transformed UV, then emission
         if (mt->tex >= 0 || mt->ntex >= 0) {
+            // the UV as vertex a's plus the weighted differences (fp32 rounding relative to
+            // the triangle's UV extent), then the tiling transform in FP64
             const float inv = 1.0f / (t0 + t1 + t2);
-            const float u = (t0 * mt->uva.x + t1 * mt->uvb.x + t2 * mt->uvc.x) * inv * mt->su + mt->ou;
-            const float v = (t0 * mt->uva.y + t1 * mt->uvb.y + t2 * mt->uvc.y) * inv * mt->sv + mt->ov;
+            const float du = (t1 * (mt->uvb.x - mt->uva.x) + t2 * (mt->uvc.x - mt->uva.x)) * inv;
+            const float dv = (t1 * (mt->uvb.y - mt->uva.y) + t2 * (mt->uvc.y - mt->uva.y)) * inv;
+            const double u = ((double)mt->uva.x + du) * mt->su + mt->ou;
+            const double v = ((double)mt->uva.y + dv) * mt->sv + mt->ov;
             if (mt->tex >= 0) {
                 const float3 tx = tex_bilinear(texels, tex_info[mt->tex], u, v);
                 al0 *= tx.x;
