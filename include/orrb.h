@@ -327,7 +327,10 @@ typedef struct {                  /* destinations; rgb, depth, normal, seg may e
 
 /* Render every frame of the layout.  `scenes`, `cameras`, `params`, `out` are host
  * structs holding device pointers; `workspace` is a device buffer of at least
- * orrb_layout_info.workspace_bytes, `stream` a hipStream_t (NULL: the null stream).
+ * orrb_layout_info.workspace_bytes (uninitialised is fine), `stream` a hipStream_t
+ * (NULL: the null stream).  The kernels keep work counters in the workspace (and, on
+ * the tiled path or for scratch-held scenes, vertex records, survivors and bins), so
+ * calls that may overlap in time (other streams) need workspaces of their own.
  * Asynchronous: returns once the kernels are enqueued.  Preconditions the host cannot
  * check without a copy (values inside device arrays: rigid poses, near > 0, roughness
  * in (0, 1]) are the caller's; violating them gives unspecified pixels, never an

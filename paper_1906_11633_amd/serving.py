@@ -187,7 +187,10 @@ class Server:
         self.launches = 0
         self.launch_frames = 0
         self.max_inflight_seen = 0
-        self.workspace = torch.empty(256, dtype=torch.uint8, device=pool.device)  # frame path: untouched
+        # frame-path launches need only the workspace's work counters: one small buffer
+        # per stream (launches on one stream run in order, on different streams they
+        # overlap and must not share counters)
+        self.small_ws = [torch.empty(256, dtype=torch.uint8, device=pool.device) for _ in range(n_streams)]
 
     # -- admission ------------------------------------------------------------------
     def data_bytes(self, r: Request) -> int:
@@ -197,7 +200,7 @@ class Server:
     @staticmethod
     def _workspace_bytes(lay: Layout) -> int:
         n = int(lay.info.workspace_bytes)
-        return n if n > 256 else 0  # frame-path launches share the server's small buffer
+        return n if n > 256 else 0  # frame-path launches use their stream's small buffer
 
     def need_bytes(self, r: Request) -> int:
         """Device bytes the request needs when launched alone: outputs, state and the
@@ -277,7 +280,7 @@ class Server:
         for r in group:
             r.t_admit = now
         desc, oi, li, fi, intr = self.pool.batch_desc(group)
-        stream = self.streams[self.next_stream]
+        stream, small_ws = self.streams[self.next_stream], self.small_ws[self.next_stream]
         self.next_stream = (self.next_stream + 1) % len(self.streams)
         dev = self.pool.device
         P = sum(r.pixels for r in group)
@@ -296,10 +299,11 @@ class Server:
                        depth=torch.empty(P, dtype=torch.float32, device=dev),
                        normal=torch.empty(3 * P, dtype=torch.float32, device=dev),
                        seg=torch.empty(P, dtype=torch.int32, device=dev))
-            # frames on the tiled path use the workspace: launches in flight on other
-            # streams must not share it
+            # the kernels keep counters (and, on the tiled path or for scratch-held
+            # scenes, vertex records and bins) in the workspace: launches in flight on
+            # other streams must not share it
             ws_need = int(lay.info.workspace_bytes)
-            ws = self.workspace if ws_need <= 256 else torch.empty(ws_need, dtype=torch.uint8, device=dev)
+            ws = small_ws if ws_need <= 256 else torch.empty(ws_need, dtype=torch.uint8, device=dev)
             out["stats"] = torch.zeros(_lib.STATS_WORDS, dtype=torch.int32, device=dev)
             render_batch(self.ctx, lay, st, out, ws, stream=stream)
             ev = torch.cuda.Event()

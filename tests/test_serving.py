@@ -45,6 +45,27 @@ def test_result_alone_equals_in_the_mix(setup):
             assert torch.equal(alone[k], q.result[k]), (q.rid, k)
 
 
+def test_large_merged_launches_on_several_streams(setup):
+    """Merged launches of more frames than the frame kernel has workgroups, with mixed
+    sizes (frames claimed at run time), in flight on several streams at once: every
+    request's result equals its render alone."""
+    import torch
+    from paper_1906_11633_amd.serving import Server
+    r, pool = setup
+    reqs = _requests(pool, 60, seed=7)
+    srv = Server(r.ctx, pool, keep_results=True, n_streams=3, max_batch_frames=400)
+    st = srv.run(reqs)
+    assert st["requests"] == len(reqs)
+    assert srv.launches >= 2 and srv.launch_frames / srv.launches > 256
+    torch.cuda.synchronize()
+    for q in reqs:
+        job = r.prepare(pool.standalone_batch(q))
+        alone = r.render(job)
+        torch.cuda.synchronize()
+        for k in ("rgb", "depth", "normal", "seg"):
+            assert torch.equal(alone[k], q.result[k]), (q.rid, k)
+
+
 @pytest.mark.parametrize("res", [64, 128, 200])
 def test_served_request_matches_oracle(setup, res):
     """Requests served in a merged launch match the oracle at every config-5 size."""
