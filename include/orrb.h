@@ -81,7 +81,15 @@ typedef struct orrb_layout orrb_layout;
 /* context and resident meshes (Sec. 3, Single Scene Multiple States)                 */
 /* --------------------------------------------------------------------------------- */
 
-/* Create a context on HIP device `hip_device`.  *out receives the handle. */
+/* Create a context on HIP device `hip_device`.  *out receives the handle.  The
+ * environment is read here, once:
+ *   ORRB_TILE=WxH, ORRB_BIN_CAP=N  the tuning new layouts of this context start from
+ *                                  (otherwise tile 32x32, bin capacity 256); a pair that
+ *                                  is no valid tuning is ORRB_ERR_INVALID_ARGUMENT;
+ *   ORRB_DEBUG_VALIDATE (not "0")  every orrb_render_batch and orrb_render_batch_noalloc
+ *                                  call with a stats destination first runs
+ *                                  orrb_validate_batch into it;
+ * and orrb_autotune reads ORRB_AUTOTUNE_CACHE when its cache_path is NULL. */
 orrb_status orrb_create(int hip_device, orrb_context **out);
 
 /* Destroy a context and free its mesh and texture pools.  If layouts of the context are
@@ -386,8 +394,8 @@ orrb_status orrb_render_batch_noalloc(orrb_context *ctx, const orrb_layout *layo
  * the fastest on the layout (*chosen and *best_ms receive it; either may be NULL).
  * Every tuning gives bit-identical outputs, so tuning changes speed only.  The
  * workspace must hold orrb_layout_info.workspace_bytes_any.  `cache_path` (may be
- * NULL) names a JSON-lines file: an entry for this device and batch structure is used
- * without measuring; a new result is appended.  Synchronizes `stream`.  No work that
+ * NULL: ORRB_AUTOTUNE_CACHE if set, else none) names a JSON-lines file: an entry for
+ * this device and batch structure is used without measuring; a new result is appended.  Synchronizes `stream`.  No work that
  * uses the layout may be in flight on other streams. */
 orrb_status orrb_autotune(orrb_context *ctx, orrb_layout *layout, const orrb_scenes *scenes, const orrb_cameras *cameras,
                           const orrb_params *params, const orrb_outputs *out, void *workspace, size_t workspace_bytes,

@@ -163,6 +163,8 @@ bool frame_fits(int n_verts, int n_obj, int n_tris, int width, int height);
 bool frame_fits_global(int64_t n_verts, int n_obj, int64_t n_tris, int width, int height);
 size_t raster_lds_bytes(int tile_w, int tile_h, int bin_cap);
 // render call shared by orrb_render_batch and orrb_render_batch_noalloc (orrb_host.cpp)
+orrb_status debug_validate(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
+                           const orrb_params *par, const orrb_outputs *out, void *stream);
 orrb_status render_impl(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
                         const orrb_params *par, const orrb_outputs *out, void *workspace, size_t workspace_bytes,
                         void *stream, bool timing);

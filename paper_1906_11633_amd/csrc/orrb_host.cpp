@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -157,6 +158,9 @@ struct orrb_context {
     int n_layouts = 0;
     bool destroy_pending = false;  // orrb_destroy called while layouts were alive: freed with the last one
     uint64_t generation = 0;  // bumped whenever the mesh pool grows (its buffers may move)
+    // from the environment at orrb_create
+    orrb_tuning default_tuning{32, 32, 256, 0, 0};  // new layouts start from it
+    bool debug_validate = false;  // every render call first checks its preconditions
 };
 
 struct orrb_layout {
@@ -588,6 +592,32 @@ orrb_status orrb_create(int hip_device, orrb_context **out) {
     if (!c) return fail(ORRB_ERR_OUT_OF_MEMORY, "host allocation failed");
     c->device = hip_device;
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (const char *v = getenv("ORRB_TILE")) {
+        int w = 0, h = 0;
+        char x = 0;
+        if (sscanf(v, "%d%c%d", &w, &x, &h) != 3 || (x != 'x' && x != 'X')) {
+            delete c;
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "ORRB_TILE=%s: expected WxH", v);
+        }
+        c->default_tuning.tile_w = w;
+        c->default_tuning.tile_h = h;
+    }
+    if (const char *v = getenv("ORRB_BIN_CAP")) {
+        char *end = nullptr;
+        const long n = strtol(v, &end, 10);
+        if (end == v || *end != 0) {
+            delete c;
+            return fail(ORRB_ERR_INVALID_ARGUMENT, "ORRB_BIN_CAP=%s: expected an integer", v);
+        }
+        c->default_tuning.bin_cap = (int)n;
+    }
+    if (!valid_tuning(c->default_tuning)) {
+        const orrb_tuning &t = c->default_tuning;
+        delete c;
+        return fail(ORRB_ERR_INVALID_ARGUMENT, "ORRB_TILE / ORRB_BIN_CAP give no valid tuning (tile %dx%d, cap %d)",
+                    t.tile_w, t.tile_h, t.bin_cap);
+    }
+    if (const char *v = getenv("ORRB_DEBUG_VALIDATE")) c->debug_validate = *v && strcmp(v, "0") != 0;
     {
         // the device's copy of the fixed scratch array (orrb_render_batch_noalloc)
         const hipError_t e = scratch_init(hip_device);
@@ -762,6 +792,7 @@ orrb_status orrb_layout_create(orrb_context *ctx, const orrb_layout_desc *d, orr
     auto *L = new (std::nothrow) orrb_layout();
     if (!L) return fail(ORRB_ERR_OUT_OF_MEMORY, "host allocation failed");
     L->ctx = ctx;
+    L->tuning = ctx->default_tuning;
     L->n_scenes = S;
     L->n_objects = O;
     L->n_lights = NL;
@@ -1080,12 +1111,23 @@ orrb_status orrb::render_impl(orrb_context *ctx, const orrb_layout *L, const orr
     return ORRB_OK;
 }
 
+// With ORRB_DEBUG_VALIDATE set when the context was created: the precondition check
+// (orrb_validate_batch) into the call's stats destination, ahead of the render kernels.
+orrb_status orrb::debug_validate(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc,
+                                 const orrb_cameras *cam, const orrb_params *par, const orrb_outputs *out,
+                                 void *stream) {
+    if (!ctx || !ctx->debug_validate || !out || !out->stats) return ORRB_OK;
+    return orrb_validate_batch(ctx, L, sc, cam, par, out->stats, stream);
+}
+
 extern "C" {
 
 orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
                               const orrb_params *par, const orrb_outputs *out, void *workspace, size_t workspace_bytes,
                               void *stream) {
     g_last_error.clear();
+    const orrb_status st = debug_validate(ctx, L, sc, cam, par, out, stream);
+    if (st != ORRB_OK) return st;
     return render_impl(ctx, L, sc, cam, par, out, workspace, workspace_bytes, stream, true);
 }
 

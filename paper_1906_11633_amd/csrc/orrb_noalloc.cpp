@@ -68,6 +68,9 @@ extern "C" orrb_status orrb_render_batch_noalloc(orrb_context *ctx, const orrb_l
     void *ws = scratch_address(orrb::context_device(ctx));
     if (!ws) return orrb::set_error(ORRB_ERR_DEVICE, "the device's scratch address was not resolved");
     // The kernels reset what must start at zero themselves (the persistent tile
-    // counter is cleared by the vertex kernel), so no memset is issued.
+    // counter is cleared by the vertex kernel, the frame kernel's claim counter by a
+    // one-thread kernel before it), so no memset is issued.
+    const orrb_status st = orrb::debug_validate(ctx, layout, scenes, cameras, params, out, stream);
+    if (st != ORRB_OK) return st;
     return orrb::render_impl(ctx, layout, scenes, cameras, params, out, ws, kScratchBytes, stream, true);
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <string>
@@ -67,6 +68,10 @@ orrb_status orrb_autotune(orrb_context *ctx, orrb_layout *layout, const orrb_sce
                           const orrb_params *params, const orrb_outputs *out, void *workspace, size_t workspace_bytes,
                           void *stream, const char *cache_path, orrb_tuning *chosen, double *best_ms) {
     if (!ctx || !layout) return set_error(ORRB_ERR_INVALID_ARGUMENT, "NULL handle");
+    if (!cache_path) {
+        const char *v = getenv("ORRB_AUTOTUNE_CACHE");
+        if (v && *v) cache_path = v;
+    }
     orrb_layout_info inf;
     orrb_status st = orrb_layout_info_get(layout, &inf);
     if (st != ORRB_OK) return st;
