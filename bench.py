@@ -86,7 +86,7 @@ def cpu_baseline(batch_fn, n_scenes_total: int, target_s: float, threads: int):
             break
     what = "the whole workload" if n == n_scenes_total else f"the first {n} of {n_scenes_total} scenes"
     return dict(value=frames / dt, unit="frames/s", cores=threads, kind="oracle",
-                sample=f"{what} x 3 cameras ({b.n_frames} frames) rendered {reps}x by the FP64 oracle "
+                sample=f"{what} ({n} scenes, {b.n_frames} frames) rendered {reps}x by the FP64 oracle "
                        f"(OpenMP over frames, {threads} threads) in {dt:.1f} s")
 
 
@@ -523,6 +523,8 @@ def main(argv=None):
         cpu["value"] = round(cpu["value"], 3)
         one = cpu_baseline(lambda n: S.config2(2, n, args.res), args.scenes, args.cpu_seconds / 3, 1)
         extra["cpu_single_thread"] = dict(value=round(one["value"], 3), unit="frames/s", sample=one["sample"])
+        c1 = cpu_baseline(lambda n: S.config1(1, n, 64), 4, 2.0, threads)  # the tiny correctness batch, whole
+        extra["cpu_config1"] = dict(value=round(c1["value"], 3), unit="frames/s", cores=threads, sample=c1["sample"])
         extra["cpu_model"] = cpu_model()
         extra["cpu_threads_available"] = os.cpu_count()
 
