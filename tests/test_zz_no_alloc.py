@@ -92,3 +92,15 @@ def test_noalloc_rejects_batch_beyond_scratch(renderer):
     with pytest.raises(L.OrrbError) as e:
         render_batch_noalloc(renderer.ctx, job.layout, job.state, out)
     assert e.value.status == 5 and "workspace" in str(e.value)
+
+
+def test_noalloc_run_time_frame_claims_two_calls(renderer):
+    """Uneven batches of more frames than the frame kernel's workgroups, so the frames
+    are claimed at run time from a counter in the fixed scratch array: the second call
+    finds the counter as the first left it and must clear it itself."""
+    big = S.config3(3, 100, max_tris=4000)   # 300 frames of unequal cost
+    small = S.config3(5, 90, max_tris=3000)  # 270
+    for batch in (big, small):
+        a, b, inf = _both(renderer, batch, None)
+        assert inf.frame_path_frames == batch.n_frames > 256 and inf.render_kernels == 2
+        _assert_identical(a, b)
