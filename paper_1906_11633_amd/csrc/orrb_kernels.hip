@@ -1596,17 +1596,11 @@ ORRB_INLINE bool frame_render(const RenderArgs &a, FrameLds &S, int item, int se
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (AUX && a.out_track) {  // tracker: the object slot of each covered pixel's key
-            for (int c0 = 0; c0 < n_cov; c0 += kWave) {
-                const int c = c0 + lane;
-                int rec = -1, pi = 0, pj = 0;
-                if (c < n_cov) {
-                    const int p = list[c];
-                    rec = fi.track_base + (int)((vis[p] >> 16) & 0xffu);
-                    pi = x0 + (int)((unsigned)p % kFTileW);
-                    pj = y0 + (int)((unsigned)p / kFTileW);
-                }
-                track_wave<true>(a.out_track, rec, pi, pj);  // frames of at most 256 x 256
-            }
+            int sl[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                sl[q] = (covq >> q) & 1 ? (int)((unsigned)vis[lj * kFTileW + li0 + q] >> 16) & 0xff : -1;
+            track_tile(a.out_track + fi.track_base, sl, x0 + li0, y0 + lj);  // frames of at most 256 x 256
         }
 
         // shade the covered pixels, lane-compacted (lane takes list[lane + 64 r]), in

@@ -638,6 +638,54 @@ ORRB_INLINE void track_wave(orrb_track *base, int rec, int i, int j) {
     }
 }
 
+// The same for a whole 64 x 4 tile of the frame path: lane L holds the four pixels
+// (i0 + q, j), q < 4, with object slot s[q] of the frame's records `base` (-1: not
+// covered).  One reduction and one group of atomics per object present in the tile
+// rather than per 64 covered pixels.  i0 + 3 and j are below 256 (the frame path's
+// frames), so a tile's column and row sums (at most 256 x 255) fit 16 bits and travel
+// packed like the minima and maxima; the count (0 to 4 per lane) is summed from three
+// ballots.  Must be called with every lane of the wave active.
+ORRB_INLINE void track_tile(orrb_track *base, const int s[4], int i0, int j) {
+    int left = (s[0] >= 0 ? 1 : 0) | (s[1] >= 0 ? 2 : 0) | (s[2] >= 0 ? 4 : 0) | (s[3] >= 0 ? 8 : 0);
+    unsigned long long pend = __ballot(left != 0);
+    while (pend) {
+        const int first = __builtin_ctzll(pend);
+        int mine = -1;  // the lane's lowest pending slot
+#pragma unroll
+        for (int q = 3; q >= 0; --q)
+            if ((left >> q) & 1) mine = s[q];
+        const int r0 = __builtin_amdgcn_readlane(mine, first);
+        int cnt = 0, mn = -1, mx = 0;
+        unsigned sum = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (((left >> q) & 1) && s[q] == r0) {
+                const int ij = (int)((unsigned)(i0 + q) | ((unsigned)j << 16));
+                ++cnt;
+                mn = pk_min_u16(mn, ij);
+                mx = pk_max_u16(mx, ij);
+                sum += (unsigned)ij;
+                left &= ~(1 << q);
+            }
+        }
+        const unsigned MN = (unsigned)wave_reduce(mn, -1, pk_min_u16);
+        const unsigned MX = (unsigned)wave_reduce(mx, 0, pk_max_u16);
+        const unsigned S2 = wave_sum(sum);
+        const int C = __popcll(__ballot(cnt & 1)) + 2 * __popcll(__ballot(cnt & 2)) + 4 * __popcll(__ballot(cnt & 4));
+        if (lane_id() == first) {
+            orrb_track *t = base + r0;
+            atomicAdd(&t->count, C);
+            atomicMin(&t->i_min, (int)(MN & 0xffffu));
+            atomicMin(&t->j_min, (int)(MN >> 16));
+            atomicMax(&t->i_max, (int)(MX & 0xffffu));
+            atomicMax(&t->j_max, (int)(MX >> 16));
+            atomicAdd((unsigned long long *)&t->sum_i, (unsigned long long)(S2 & 0xffffu));
+            atomicAdd((unsigned long long *)&t->sum_j, (unsigned long long)(S2 >> 16));
+        }
+        pend = __ballot(left != 0);
+    }
+}
+
 ORRB_INLINE CamF frame_camera(const RenderArgs &a, int f) {
     const float *K = a.intr + 4 * (int64_t)f;
     CamF c;
