@@ -15,8 +15,9 @@
 //   4. take tiles with entries from an LDS counter, rasterize each bin into a 256-key
 //      LDS visibility tile (ds_min_u64), shade the covered pixels and put the finished
 //      tile into an LDS staging slot.
-// The other four waves issue every global store: the background of handed-over tiles
-// (while the compute waves go on with the next frame) and the staged tiles.
+// The other four waves issue the global stores: the background of handed-over tiles
+// (while the compute waves go on with the next frame) and the staged tiles; in the
+// auxiliary-output kernels a compute wave out of busy tiles also writes background.
 //
 // Tiled path (k_vertex + k_raster_shade), for any scene size:
 //   k_vertex        one workgroup per (frame, object): FP64 transform and snap into a
@@ -1275,9 +1276,9 @@ ORRB_INLINE void frame_drain(const RenderArgs &a, FrameLds &S, int wave, int lj,
 // With the auxiliary outputs (8-bit encoding with grain, alpha) the store waves carry
 // more per pixel than the compute waves produce, so a compute wave with no busy tile
 // left writes background tiles of frame seq (taken from the same counter as the store
-// waves) while the other compute waves finish.  Without them it would only delay the
-// end of the frame: the store waves keep up, and the plain kernel was measured 8 %
-// slower with this help.
+// waves) while the other compute waves finish.  The plain kernel leaves this out: its
+// store waves keep up, so the same help only delays the end of each frame (measured
+// 8 % slower).
 template <bool AUX>
 ORRB_INLINE void frame_bg_help(const RenderArgs &a, FrameLds &S, int seq, int lj, int li0, int lane) {
     PostCache pc;
