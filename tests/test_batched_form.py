@@ -149,12 +149,18 @@ def test_run_time_schedule_every_feature(renderer):
     """Frames claimed at run time (more frames than workgroups, unequal costs) with every
     feature on: 100 uneven scenes x 3 cameras under three shadowed spot lights each (300
     shadow frames, themselves claimed at run time by the shadow pass), textured
-    materials, transparency, Tracker records and post-processed 8-bit RGB.  The one-launch
+    materials, transparency, Tracker records and post-processed 8-bit RGB, with hidden
+    objects and three frames that see nothing.  The one-launch
     path equals the tiled path bit for bit on every output and matches the oracle."""
     import torch
     from paper_1906_11633_amd.renderer import read_track
     b = S.config3(9, 100, max_tris=6000)
     b = S.with_postprocessing(S.with_materials(S.with_spot_lights(b, seed=9), seed=9), seed=9)
+    vis = b.object_visible.copy()
+    vis[::4] = 0  # hidden objects
+    view = b.view.copy()
+    view[[5, 150, 299], :, 3] += np.array([0.0, 0.0, 50.0], np.float32)  # frames with nothing in view
+    b = b.replace(object_visible=vis, view=view)
     assert b.n_frames > 256  # more frames than the frame kernel's workgroups
     res = []
     for t in ((32, 32, 512, 0, 2), (32, 32, 256, 0, 1)):
