@@ -30,6 +30,8 @@ BYTES_PER_PIXEL = 32  # rgb 12 + depth 4 + normal 12 + seg 4
 METRIC = "randomized 4-channel 200x200 frames/sec on 1 MI355X; shading-grad/sec; p99 ms"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_frame_traffic.json")
 # the frame kernel's source: its file and the headers it includes
+PROFILE_EVERY = 10  # timed region: the kernel of every 10th step bracketed by HIP events
+
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1906_11633_amd", "csrc", f)
                for f in ("orrb_kernels.hip", "orrb_primitives.h", "orrb_device.h", "orrb_post.h")]
 
@@ -386,13 +388,14 @@ def main(argv=None):
     for _ in range(args.warmup):
         r.render(job, out)
     torch.cuda.synchronize()
-    _lib.check(lib.orrb_profile_enable(ctx, 1))
+    _lib.check(lib.orrb_profile_enable(ctx, PROFILE_EVERY))  # one timed launch in PROFILE_EVERY
     stats = torch.zeros(_lib.STATS_WORDS, dtype=torch.int32, device="cuda")
     out["stats"] = stats
     cur = torch.cuda.current_stream()
-    # the timed region: K steps, with only the library's events around its kernels (for
-    # the kernel's duration); per-step events would add their own cost to every step,
-    # so the step-time distribution is taken in a separate pass below
+    # the timed region: K steps, with only the library's events around the kernel of one
+    # step in PROFILE_EVERY (its mean duration for the roofline); events on every step
+    # would add their own cost to each, so the step-time distribution is taken in a
+    # separate pass below
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):

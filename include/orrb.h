@@ -465,9 +465,12 @@ typedef struct {
     int64_t vertex_launches, raster_launches, frame_launches;
 } orrb_kernel_times;
 
-/* Enable (1) or disable (0) per-kernel timing and reset the totals.  While enabled,
- * every render call brackets each kernel with HIP events recorded on the call's own
- * stream (a few microseconds of overhead per call). */
+/* Enable or disable (0) per-kernel timing and reset the totals.  While enabled, every
+ * timed orrb_render_batch call brackets each kernel with HIP events recorded on the
+ * call's own stream (a few microseconds of overhead per timed call): with enable = 1
+ * every call is timed, with enable = N > 1 every N-th (the first, then one in N), which
+ * spreads that overhead over N calls.  Errors: ORRB_ERR_INVALID_ARGUMENT for a NULL
+ * context or enable < 0. */
 orrb_status orrb_profile_enable(orrb_context *ctx, int enable);
 
 /* Wait for the recorded events and return the totals since the last enable. */

@@ -103,6 +103,8 @@ struct ScopedDevice {
 // Per-kernel timing with HIP events on the caller's stream (observability).
 struct KernelTimer {
     bool enabled = false;
+    int every = 1;      // time every `every`-th render call
+    int64_t calls = 0;  // render calls since enabled
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];  // 0 vertex, 1 raster, 2 frame
     double total_ms[3] = {0, 0, 0};
@@ -1128,7 +1130,9 @@ orrb_status orrb_render_batch(orrb_context *ctx, const orrb_layout *L, const orr
     g_last_error.clear();
     const orrb_status st = debug_validate(ctx, L, sc, cam, par, out, stream);
     if (st != ORRB_OK) return st;
-    return render_impl(ctx, L, sc, cam, par, out, workspace, workspace_bytes, stream, true);
+    bool timing = true;  // with profiling on: every `every`-th call is timed
+    if (ctx && ctx->timer.enabled) timing = ctx->timer.calls++ % ctx->timer.every == 0;
+    return render_impl(ctx, L, sc, cam, par, out, workspace, workspace_bytes, stream, timing);
 }
 
 orrb_status orrb_validate_batch(orrb_context *ctx, const orrb_layout *L, const orrb_scenes *sc, const orrb_cameras *cam,
@@ -1234,8 +1238,11 @@ orrb_status orrb_profile_enable(orrb_context *ctx, int enable) {
     g_last_error.clear();
     if (!ctx) return fail(ORRB_ERR_INVALID_ARGUMENT, "NULL context");
     ScopedDevice sd(ctx->device);
+    if (enable < 0) return fail(ORRB_ERR_INVALID_ARGUMENT, "negative sampling interval %d", enable);
     HIP_TRY(ctx->timer.drain());
     ctx->timer.enabled = enable != 0;
+    ctx->timer.every = enable > 1 ? enable : 1;
+    ctx->timer.calls = 0;
     for (int k = 0; k < 3; ++k) {
         ctx->timer.total_ms[k] = 0;
         ctx->timer.count[k] = 0;

@@ -110,3 +110,24 @@ def test_tuning_and_cache_environment(monkeypatch, tmp_path):
     monkeypatch.setenv("ORRB_TILE", "24x24")
     with pytest.raises(RuntimeError, match="ORRB_TILE"):
         Renderer(0)
+
+
+def test_profile_sampling(renderer):
+    """orrb_profile_enable(N): every N-th render call is timed (the first, then one in
+    N); 1 times every call; a negative interval is refused."""
+    import ctypes as C
+    import torch
+    from paper_1906_11633_amd import _lib as L
+    lib, ctx = renderer.ctx.lib, renderer.ctx.handle
+    job = renderer.prepare(S.config2(8, 2, 64))
+    out = renderer.alloc_outputs(job)
+    for every, expect in ((3, 3), (1, 7)):
+        L.check(lib.orrb_profile_enable(ctx, every))
+        for _ in range(7):
+            renderer.render(job, out)
+        torch.cuda.synchronize()
+        kt = L.KernelTimes()
+        L.check(lib.orrb_profile_read(ctx, C.byref(kt)))
+        assert kt.frame_launches == expect and kt.frame_ms > 0, (every, kt.frame_launches)
+    L.check(lib.orrb_profile_enable(ctx, 0))
+    assert lib.orrb_profile_enable(ctx, -1) == 1
