@@ -110,3 +110,50 @@ def test_uneven_full_size_every_frame_once(renderer):
     for k in ("rgb", "depth", "normal", "seg", "tri_id"):
         assert torch.equal(out[k], ref[k]), k
     assert renderer.ctx.wait_timeouts() == 0
+
+
+def test_config2_full_size_every_frame(renderer):
+    """Every frame of the 768-frame batch, in the timed launch configuration, against
+    properties that hold at any size: bit-identical to the tiled path (a separate kernel
+    with its own binning and schedule, so a frame skipped, rendered twice or written
+    into another's pixels shows up); background pixels exactly zero with seg -1; covered
+    pixels with finite positive depth, unit normals, non-negative rgb and the seg id of
+    one of the frame's scene's objects; and every frame with covered pixels (each camera
+    looks at the hand)."""
+    import torch
+    b = S.config2(2, 256, 200)
+    job = renderer.prepare(b)
+    assert job.layout.info.frame_path_frames == b.n_frames and job.layout.info.render_kernels == 1
+    out = renderer.alloc_outputs(job, tri_id=True)
+    for v in out.values():
+        v.fill_(7)  # a pixel left unwritten would keep this
+    for _ in range(2):
+        renderer.render(job, out)
+    torch.cuda.synchronize()
+    assert renderer.ctx.wait_timeouts() == 0
+    job.layout.set_tuning(32, 32, 256, 1, 1)  # the tiled path
+    assert job.layout.info.tile_items > 0 and job.layout.info.frame_path_frames == 0
+    ref = renderer.render(job, tri_id=True)
+    torch.cuda.synchronize()
+    for k in ("rgb", "depth", "normal", "seg", "tri_id"):
+        assert torch.equal(out[k], ref[k]), k
+
+    po = np.asarray(b.pixel_offset, np.int64)
+    depth = out["depth"].cpu().numpy().reshape(-1)
+    seg = out["seg"].cpu().numpy().reshape(-1)
+    rgb = out["rgb"].cpu().numpy().reshape(-1)
+    nrm = out["normal"].cpu().numpy().reshape(-1)
+    sob = np.asarray(b.scene_object_begin, np.int64)
+    for f in range(b.n_frames):
+        n = po[f + 1] - po[f]
+        s, d = seg[po[f]:po[f + 1]], depth[po[f]:po[f + 1]]
+        c3 = rgb[3 * po[f]:3 * po[f + 1]].reshape(3, n)
+        n3 = nrm[3 * po[f]:3 * po[f + 1]].reshape(3, n)
+        cov = s >= 0
+        assert cov.any(), f
+        sc = b.frame_scene[f]
+        assert (s >= -1).all() and np.isin(s[cov], b.object_seg[sob[sc]:sob[sc + 1]]).all(), f
+        assert (d[~cov] == 0).all() and (c3[:, ~cov] == 0).all() and (n3[:, ~cov] == 0).all(), f
+        assert np.isfinite(d[cov]).all() and (d[cov] > 0).all(), f
+        assert (c3[:, cov] >= 0).all() and np.isfinite(c3[:, cov]).all(), f
+        assert np.abs(np.sqrt((n3[:, cov].astype(np.float64) ** 2).sum(0)) - 1.0).max() < 1e-5, f
